@@ -1,0 +1,420 @@
+"""Pins of the CPU oracle against facts fixed by the mathematics (no GPU).
+
+Each test checks the oracle against something other than itself: the
+collocation conditions that define Radau IIA, the Pade approximant of exp,
+closed-form solutions, invariants, and independent stiff integrators from
+scipy.  Together they are meant to catch a dropped term, a wrong sign or index
+or a transposed operand anywhere in the oracle.
+
+Method: Radau5 = 3-stage Radau IIA (Descombes et al. §1 footnote on Radau5;
+Hairer & Wanner, Solving ODEs II, §IV.5 and §IV.8).  Models: paper §1.
+"""
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+from scipy.integrate import solve_ivp
+from scipy.linalg import expm
+
+from paper_1506_04651_amd import workloads as W
+
+mp.mp.dps = 40
+
+
+# ---------------------------------------------------------------------------
+# Independent derivation of the method (test side only)
+# ---------------------------------------------------------------------------
+def radau_iia_from_definition():
+    """Nodes: zeros of d^2/dx^2 [x^2 (x-1)^3] (right Radau points for s=3).
+    A: the unique matrix with sum_j a_ij c_j^(k-1) = c_i^k / k, k = 1..3."""
+    # x^2 (x-1)^3 = x^5 - 3x^4 + 3x^3 - x^2; second derivative:
+    roots = mp.polyroots([20, -36, 18, -2], maxsteps=200, extraprec=200)
+    c = sorted([mp.re(r) for r in roots])
+    V = mp.matrix(3, 3)
+    for k in range(3):
+        for j in range(3):
+            V[k, j] = c[j] ** k
+    A = mp.matrix(3, 3)
+    for i in range(3):
+        rhs = mp.matrix([c[i] ** (k + 1) / (k + 1) for k in range(3)])
+        row = mp.lu_solve(V, rhs)
+        for j in range(3):
+            A[i, j] = row[j]
+    # embedded-estimate weights: d.c = -1, d.c^2 = 0, d.c^3 = 0
+    M = mp.matrix(3, 3)
+    for k in range(3):
+        for j in range(3):
+            M[k, j] = c[j] ** (k + 1)
+    d = mp.lu_solve(M, mp.matrix([-1, 0, 0]))
+    Ainv = mp.inverse(A)
+    ev = mp.eig(Ainv)[0]
+    real = [e for e in ev if abs(mp.im(e)) < mp.mpf(10) ** -30]
+    cplx = [e for e in ev if mp.im(e) > mp.mpf(10) ** -30]
+    return {"c": c, "A": A, "d": [d[0], d[1], d[2]], "gamma": mp.re(real[0]),
+            "alpha": mp.re(cplx[0]), "beta": mp.im(cplx[0])}
+
+
+DEF = radau_iia_from_definition()
+
+
+def pade(k, j, z):
+    """(k, j) Pade approximant of exp(z), textbook closed form."""
+    P = sum(math.factorial(k + j - i) * math.factorial(k)
+            / (math.factorial(k + j) * math.factorial(i) * math.factorial(k - i)) * z ** i
+            for i in range(k + 1))
+    Q = sum(math.factorial(k + j - i) * math.factorial(j)
+            / (math.factorial(k + j) * math.factorial(i) * math.factorial(j - i)) * (-z) ** i
+            for i in range(j + 1))
+    return P / Q
+
+
+# ---------------------------------------------------------------------------
+# P1 constants
+# ---------------------------------------------------------------------------
+def test_p1_constants_match_collocation_definition(orc):
+    k = orc.constants()
+    for i in range(3):
+        assert abs(k["c"][i] - float(DEF["c"][i])) <= 1e-16
+        for j in range(3):
+            assert abs(k["A"][i, j] - float(DEF["A"][i, j])) <= 2e-16, (i, j)
+        assert abs(k["d"][i] - float(DEF["d"][i])) <= 4e-15 * max(1, abs(k["d"][i]))
+    assert abs(k["gamma_hat"] - float(DEF["gamma"])) <= 1e-15
+    # the real eigenvalue is the root of x^3 - 9x^2 + 36x - 60 (Pade denominator of
+    # order 3, scaled): both derivations agree
+    g = DEF["gamma"]
+    assert abs(g ** 3 - 9 * g ** 2 + 36 * g - 60) < mp.mpf(10) ** -30
+
+
+def test_p1_order_conditions_of_quadrature(orc):
+    """Stiffly accurate (b = last row of A) with B(5) true and B(6) false:
+    the order is exactly 5."""
+    k = orc.constants()
+    c, b = k["c"], k["A"][2]
+    for q in range(1, 6):
+        assert abs(np.dot(b, c ** (q - 1)) - 1.0 / q) < 1e-15, q
+    assert abs(np.dot(b, c ** 5) - 1.0 / 6) > 1e-4
+    assert k["c"][2] == 1.0
+    # simplifying assumption C(3) row by row
+    for i in range(3):
+        for q in range(1, 4):
+            assert abs(np.dot(k["A"][i], c ** (q - 1)) - c[i] ** q / q) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# P2 stability function, fixed step on linear problems
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("z", [-0.5, -50.0, -1e6, 0.3])
+def test_p2_stability_function_real(orc, z):
+    h = 0.7
+    lam = z / h
+    y, st, ret = orc.reaction_step(np.array([[1.0]]), h, 1e-10, 1e-12, orc.LINEAR,
+                                   [lam], fixed_steps=1, tol_transform=0)
+    assert ret == 0
+    R = pade(2, 3, z)
+    # y1 = y0 + z3 with z3 ~ -y0 when z << 0: absolute rounding of order eps |y0|
+    assert abs(y[0, 0] - R) <= 1e-13 * abs(R) + 1e-15, (y[0, 0], R)
+
+
+def test_p2_l_stability_limit(orc):
+    """R(infinity) = 0 and R(z) ~ -3/z for z -> -infinity (L-stability)."""
+    z = -1e6
+    y, _, _ = orc.reaction_step(np.array([[1.0]]), 1.0, 1e-10, 1e-14, orc.LINEAR,
+                                [z], fixed_steps=1, tol_transform=0)
+    assert abs(y[0, 0]) < 4e-6
+    assert abs(y[0, 0] * z + 3.0) < 1e-4
+
+
+@pytest.mark.parametrize("a,b", [(-1.0, 10.0), (-1.0, -10.0), (-3.0, 0.5)])
+def test_p2_stability_function_complex(orc, a, b):
+    """y' = K y with K = [[a, -b], [b, a]] is w' = (a + ib) w for w = y1 + i y2."""
+    h = 0.25
+    K = np.array([[a, -b], [b, a]])
+    y, st, ret = orc.reaction_step(np.array([[1.0], [0.0]]), h, 1e-10, 1e-12,
+                                   orc.LINEAR, K, fixed_steps=1, tol_transform=0)
+    assert ret == 0
+    R = pade(2, 3, complex(a, b) * h)
+    assert abs(complex(y[0, 0], y[1, 0]) - R) <= 1e-13 * abs(R)
+
+
+# ---------------------------------------------------------------------------
+# P3 order 5
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("lam,Ns", [(complex(-1, 0), [2, 4, 8, 16]),
+                                    (complex(-1, 10), [8, 16, 32, 64])])
+def test_p3_order_five(orc, lam, Ns):
+    K = np.array([[lam.real, -lam.imag], [lam.imag, lam.real]])
+    errs = []
+    for N in Ns:
+        y, st, ret = orc.reaction_step(np.array([[1.0], [0.0]]), 1.0, 1e-12, 1e-14,
+                                       orc.LINEAR, K, fixed_steps=N, tol_transform=0)
+        assert ret == 0 and st[1, 0] == N
+        errs.append(abs(complex(y[0, 0], y[1, 0]) - np.exp(lam)))
+    slopes = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert all(abs(s - 5.0) <= 0.15 for s in slopes), slopes
+
+
+# ---------------------------------------------------------------------------
+# P4 polynomial exactness and the error estimate on polynomials
+# ---------------------------------------------------------------------------
+def chain(m):
+    K = np.zeros((m, m))
+    for i in range(m - 1):
+        K[i + 1, i] = 1.0
+    return K
+
+
+@pytest.mark.parametrize("fixed", [1, 3, 0])
+def test_p4_degree5_solution_exact(orc, fixed):
+    m, T = 6, 1.7
+    y0 = np.zeros((m, 1))
+    y0[0] = 1.0
+    y, st, ret = orc.reaction_step(y0, T, 1e-8, 1e-8, orc.LINEAR, chain(m),
+                                   fixed_steps=fixed)
+    assert ret == 0
+    exact = np.array([T ** k / math.factorial(k) for k in range(m)])
+    assert np.max(np.abs(y[:, 0] - exact)) <= 1e-14 * np.max(exact)
+    if fixed == 0:
+        # degree <= 3: the embedded estimate is exact too, so the whole interval
+        # is accepted in one step
+        y0 = np.zeros((4, 1))
+        y0[0] = 1.0
+        y, st, ret = orc.reaction_step(y0, T, 1e-8, 1e-8, orc.LINEAR, chain(4))
+        assert ret == 0 and st[1, 0] == 1 and st[2, 0] == 1
+        exact = np.array([T ** k / math.factorial(k) for k in range(4)])
+        assert np.max(np.abs(y[:, 0] - exact)) <= 1e-14 * np.max(exact)
+
+
+def test_p4_error_estimate_vanishes_up_to_degree3(orc):
+    """The embedded solution is exact for degree <= 3: estimate ~ 0 there,
+    clearly nonzero for a degree-4 solution."""
+    h = 0.9
+    for m, expect_zero in [(3, True), (4, True), (5, False)]:
+        y0 = np.zeros(m)
+        y0[0] = 1.0
+        y1, (e1, e2), k, failed = orc.single_step(y0, h, 1e-6, 1e-6, orc.LINEAR,
+                                                  chain(m), tol_transform=0)
+        assert not failed
+        if expect_zero:
+            assert e1 < 1e-8, (m, e1)
+        else:
+            assert e1 > 1e2, (m, e1)
+
+
+def test_p4_error_estimate_matches_definition(orc):
+    """y' = lam y: the stage values solve (I - h lam A) z = h lam A 1 y0; the
+    estimate is e1 = (lam y0 + d.z/h)/(gamma/h - lam), second pass with
+    f(y0 + e1); both scaled by sc = atol + rtol |y0|.  A, d and gamma come from
+    the collocation definition above, not from the oracle."""
+    A = np.array(DEF["A"].tolist(), dtype=float)
+    d = np.array([float(x) for x in DEF["d"]])
+    g = float(DEF["gamma"])
+    rtol, atol = 1e-6, 1e-9
+    for hl in [-0.3, -5.0, -80.0, -1e5]:
+        h, y0 = 0.01, 1.3
+        lam = hl / h
+        z = np.linalg.solve(np.eye(3) - hl * A, hl * A @ np.ones(3) * y0)
+        e1 = (lam * y0 + d @ z / h) / (g / h - lam)
+        e2 = (lam * (y0 + e1) + d @ z / h) / (g / h - lam)
+        sc = atol + rtol * abs(y0)
+        y1, (r1, r2), k, failed = orc.single_step([y0], h, rtol, atol, orc.LINEAR,
+                                                  [lam], tol_transform=0)
+        assert not failed
+        assert abs(y1[0] - (y0 + z[2])) <= 1e-13 * abs(y0)
+        assert abs(r1 - abs(e1) / sc) <= 1e-9 * abs(e1) / sc + 1e-6, (hl, r1, abs(e1) / sc)
+        assert abs(r2 - abs(e2) / sc) <= 1e-9 * abs(e2) / sc + 1e-6, (hl, r2, abs(e2) / sc)
+    # stiff limit: the first pass tends to |y0|/sc, the second pass to 0
+    y1, (r1, r2), _, _ = orc.single_step([1.0], 1.0, rtol, atol, orc.LINEAR, [-1e8],
+                                         tol_transform=0)
+    assert r1 > 0.5 / (atol + rtol) and r2 < 1e-4 * r1
+
+
+# ---------------------------------------------------------------------------
+# P5 Robertson: sum of species conserved
+# ---------------------------------------------------------------------------
+ROBER = [0.04, 1e4, 3e7]
+
+
+@pytest.mark.parametrize("dt", [1.0, 40.0, 1e4])
+def test_p5_robertson_invariant(orc, dt):
+    rng = np.random.default_rng(55)
+    y0 = rng.random((3, 24))
+    y0 /= y0.sum(axis=0, keepdims=True)
+    y0[:, 0] = [1.0, 0.0, 0.0]
+    y, st, ret = orc.reaction_step(y0, dt, 1e-6, 1e-10, orc.ROBERTSON, ROBER)
+    assert ret == 0
+    assert np.max(np.abs(y.sum(axis=0) - 1.0)) <= 1e-12
+    # accuracy of the classic start (1, 0, 0) against a tight independent solve
+    def rhs(t, u):
+        return [-0.04 * u[0] + 1e4 * u[1] * u[2],
+                0.04 * u[0] - 1e4 * u[1] * u[2] - 3e7 * u[1] ** 2, 3e7 * u[1] ** 2]
+    ref = solve_ivp(rhs, (0, dt), [1.0, 0.0, 0.0], method="Radau", rtol=1e-11,
+                    atol=1e-16).y[:, -1]
+    assert np.max(np.abs(y[:, 0] - ref) / np.maximum(np.abs(ref), 1e-10)) < 2e-4
+
+
+# ---------------------------------------------------------------------------
+# P6 linear kinetics against the matrix exponential
+# ---------------------------------------------------------------------------
+def test_p6_linear_kinetics_expm(orc):
+    w = W.kinetics16(n=24, zero_g=True)
+    K = w.info["K"]
+    ref = expm(K * w.dt) @ w.states
+    y, st, ret = orc.reaction_step(w.states, w.dt, w.rtol, w.atol, w.kind, w.params)
+    assert ret == 0
+    s0 = w.states.sum(axis=0)
+    assert np.max(np.abs(y.sum(axis=0) - s0) / s0) <= 1e-12
+    rel = np.abs(y - ref) / np.maximum(np.abs(ref), w.atol)
+    assert rel.max() <= 10 * w.rtol, rel.max()
+    yt, _, ret = orc.reaction_step(w.states, w.dt, 1e-12, 1e-16, w.kind, w.params,
+                                   tol_transform=0)
+    assert ret == 0
+    relt = np.abs(yt - ref) / np.maximum(np.abs(ref), 1e-12)
+    assert relt.max() <= 1e-9, relt.max()
+
+
+# ---------------------------------------------------------------------------
+# P7 Oregonator steady state
+# ---------------------------------------------------------------------------
+def oregonator_rest(f, q):
+    # c = b, a = f b/(q + b), and b^2 + (f + q - 1) b - q (1 + f) = 0
+    s = f + q - 1
+    b = (-s + math.sqrt(s * s + 4 * q * (1 + f))) / 2
+    return np.array([f * b / (q + b), b, b])
+
+
+@pytest.mark.parametrize("q,expect", [(2e-3, (1.29574132, 0.00851737)),
+                                      (0.02, (1.26258, 0.074838))])
+def test_p7_oregonator_steady_state(orc, q, expect):
+    params = [1e-2, 1e-5, 1.6, q]
+    u = oregonator_rest(1.6, q)
+    assert abs(u[0] - expect[0]) < 1e-5 * u[0] and abs(u[1] - expect[1]) < 1e-5 * u[1]
+    f, J = orc.model_eval(orc.OREGONATOR, params, u)
+    scale = np.array([1e5, 1e2, 1.0])
+    assert np.all(np.abs(f) <= 1e-15 * scale * 10), f
+    for dt in [1.0 / 256, 1.0 / 64]:
+        y, st, ret = orc.reaction_step(u[:, None], dt, 1e-5, 1e-8, orc.OREGONATOR, params)
+        assert ret == 0
+        assert np.max(np.abs(y[:, 0] - u) / u) <= 1e-10
+        # minimum work (paper, Appendix A): one sub-step, one Newton iteration
+        assert st[1, 0] == 1 and st[8, 0] == 1 and st[4, 0] == 5
+
+
+def test_p7_oregonator_rest_state_is_unstable(orc):
+    u = oregonator_rest(1.6, 2e-3)
+    _, J = orc.model_eval(orc.OREGONATOR, W.OREG_PARAMS, u)
+    ev = np.sort(np.linalg.eigvals(J).real)
+    assert abs(ev[0] + 1128.8) < 0.5 and abs(ev[1] - 1.069) < 0.01 and abs(ev[2] - 43.68) < 0.05
+
+
+# ---------------------------------------------------------------------------
+# P8 brute force on tiny batches: tight tolerance against scipy's stiff solvers
+# ---------------------------------------------------------------------------
+def _rhs_oreg(params):
+    eps, mu, f, q = params
+
+    def rhs(t, y):
+        a, b, c = y
+        return [(-q * a - a * b + f * c) / mu, (q * a - a * b + b * (1 - b)) / eps, b - c]
+
+    def jac(t, y):
+        a, b, c = y
+        return [[(-q - b) / mu, -a / mu, f / mu], [(q - b) / eps, (1 - a - 2 * b) / eps, 0],
+                [0, 1, -1]]
+    return rhs, jac
+
+
+def _rhs_kin(K, G):
+    def rhs(t, u):
+        return K @ u - u * (G @ u)
+
+    def jac(t, u):
+        return K - np.diag(G @ u) - u[:, None] * G
+    return rhs, jac
+
+
+def _brute(orc, w, ncell, seed, floor):
+    idx = W.sample_indices(w.n, ncell, seed)
+    s = w.subset(idx)
+    if s.kind == W.KIND_OREGONATOR:
+        rhs, jac = _rhs_oreg(s.params)
+    else:
+        rhs, jac = _rhs_kin(s.info["K"], s.info["G"])
+    yt, _, ret = orc.reaction_step(s.states, s.dt, 1e-12, 1e-12 * floor, s.kind, s.params,
+                                   tol_transform=0)
+    assert ret == 0
+    yp, _, ret = orc.reaction_step(s.states, s.dt, s.rtol, s.atol, s.kind, s.params)
+    assert ret == 0
+    worst_t, worst_p = 0.0, 0.0
+    for c in range(s.n):
+        ref = solve_ivp(rhs, (0, s.dt), s.states[:, c], method="Radau", jac=jac,
+                        rtol=1e-12, atol=1e-12 * floor * 1e-3).y[:, -1]
+        worst_t = max(worst_t, np.max(np.abs(yt[:, c] - ref) / np.maximum(np.abs(ref), floor)))
+        worst_p = max(worst_p, np.max(np.abs(yp[:, c] - ref) / np.maximum(np.abs(ref), s.atol)))
+    return worst_t, worst_p / s.rtol
+
+
+@pytest.mark.parametrize("gen,ncell", [("1d", 12), ("2d", 12), ("3d", 8)])
+def test_p8_brute_force_oregonator(orc, gen, ncell):
+    w = {"1d": lambda: W.oregonator_1d(),
+         "2d": lambda: W.oregonator_2d(),
+         "3d": lambda: W.oregonator_3d(side=32, n_total=32 ** 3, check=False)}[gen]()
+    tight, prod = _brute(orc, w, ncell, 8, 1e-6)
+    assert tight <= 1e-9, tight
+    print(f"{w.name}: tight {tight:.2e}, production error / rtol {prod:.2f}")
+    assert prod <= 20.0
+
+
+@pytest.mark.slow
+def test_p8_brute_force_kinetics16(orc):
+    w = W.kinetics16(n=64)
+    tight, prod = _brute(orc, w, 3, 9, 1e-8)
+    assert tight <= 1e-9, tight
+    print(f"{w.name}: tight {tight:.2e}, production error / rtol {prod:.2f}")
+    assert prod <= 50.0
+
+
+# ---------------------------------------------------------------------------
+# P9 model code
+# ---------------------------------------------------------------------------
+def _fd_check(orc, kind, params, y, rel=1e-6):
+    f, J = orc.model_eval(kind, params, y)
+    m = y.size
+    Jfd = np.zeros((m, m))
+    for j in range(m):
+        hj = 1e-6 * max(abs(y[j]), 1e-3)
+        yp, ym = y.copy(), y.copy()
+        yp[j] += hj
+        ym[j] -= hj
+        Jfd[:, j] = (orc.model_eval(kind, params, yp)[0] - orc.model_eval(kind, params, ym)[0]) / (2 * hj)
+    scale = np.max(np.abs(J)) + 1e-300
+    assert np.max(np.abs(J - Jfd)) <= rel * scale, np.max(np.abs(J - Jfd)) / scale
+    return f, J
+
+
+def test_p9_models_against_finite_differences(orc):
+    rng = np.random.default_rng(99)
+    _fd_check(orc, orc.OREGONATOR, W.OREG_PARAMS, np.array([0.7, 0.3, 0.2]))
+    f, J = _fd_check(orc, orc.ROBERTSON, ROBER, np.array([0.9, 3e-5, 0.1]))
+    assert np.max(np.abs(J.sum(axis=0))) <= 1e-9 * np.max(np.abs(J))  # e^T J = 0
+    assert abs(f.sum()) <= 1e-12 * np.max(np.abs(f))
+    _fd_check(orc, orc.NAGUMO, [10.0], np.array([0.4]))
+    K, G = W.kinetics_matrices(16, seed=4)
+    u = 10.0 ** rng.uniform(-3, 0, 16)
+    f, J = _fd_check(orc, orc.KINETICS, np.concatenate([K.ravel(), G.ravel()]), u)
+    fl, Jl = orc.model_eval(orc.KINETICS, np.concatenate([K.ravel(), 0 * G.ravel()]), u)
+    assert abs(fl.sum()) <= 1e-10 * np.max(np.abs(fl))  # 1^T K = 0
+    assert np.max(np.abs(Jl - K)) == 0.0
+    # f against a direct evaluation of the definition for one random point
+    assert np.allclose(f, K @ u - u * (G @ u), rtol=1e-13, atol=0)
+    Kl = rng.normal(size=(5, 5))
+    fl, Jl = orc.model_eval(orc.LINEAR, Kl, u[:5])
+    assert np.allclose(fl, Kl @ u[:5], rtol=1e-14) and np.array_equal(Jl, Kl)
+
+
+def test_p9_nagumo_derivative_bound(orc):
+    """Paper §1, NAGUMO: |df/du| <= 3k on [0, 1]."""
+    k = 10.0
+    for u in np.linspace(0, 1, 101):
+        _, J = orc.model_eval(orc.NAGUMO, [k], np.array([u]))
+        assert abs(J[0, 0]) <= 3 * k
