@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Benchmark of the Radau5 reaction substep on one MI355X.
+
+One "step" is one reaction substep over a whole synthetic leaf set: the
+states are restored from a resident copy (a device-to-device copy of
+2*8*m bytes per cell) and every cell is integrated over dt with Radau5 by the
+HIP kernels.  Default workload: the 512 x 512 BZ/Oregonator spiral field
+(262 144 cells, m = 3, dt = 1/64, rtol = 1e-5, atol = 1e-8), FP64, persistent
+work-stealing kernel; the one-launch-per-batch schedule and the mixed
+precision path are timed beside it.
+
+Prints ONE JSON line (see the keys below).  --gpus N with N > 1 exits: the
+reaction step needs no communication and this build measures one GPU.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Radau5 cell-integrations/s per split step, FP64 vs mixed; p50/p99 latency"
+
+WORKLOADS = {
+    "oregonator_2d": "BZ/Oregonator 512x512 spiral field, 262144 cells, m=3, dt=1/64",
+    "oregonator_1d": "BZ/Oregonator 1D fronts, 4096 cells, m=3, dt=1/256",
+    "oregonator_3d": "BZ/Oregonator 160^3 scroll wave, 4194304 cells, m=3, dt=1/64",
+    "kinetics16": "synthetic stiff kinetics, 1048576 cells, m=16, dt=1e-2",
+}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    from paper_1506_04651_amd import workloads as W
+    return {"oregonator_2d": W.oregonator_2d, "oregonator_1d": W.oregonator_1d,
+            "oregonator_3d": W.oregonator_3d, "kinetics16": W.kinetics16}[name]()
+
+
+def time_path(rd, torch, w, u0, steps, warmup, **opts):
+    """Time `steps` reaction substeps; returns dict with wall and per-launch times."""
+    u = torch.empty_like(u0)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        u.copy_(u0)
+        rd.reaction_step(u, w.dt, w.rtol, w.atol, w.kind, w.params, async_=True, **opts)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        u.copy_(u0)
+        ev[i][0].record(stream)
+        rd.reaction_step(u, w.dt, w.rtol, w.atol, w.kind, w.params, async_=True, **opts)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = sorted(a.elapsed_time(b) for a, b in ev)
+    import numpy as np
+    return {"wall_s": wall, "launch_ms": ms, "avg_launch_ms": float(np.mean(ms)),
+            "p50_ms": float(np.percentile(ms, 50)), "p99_ms": float(np.percentile(ms, 99)),
+            "value": w.n * steps / wall, "out": u}
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1506_04651_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_name, workload):
+    """HBM bytes per launch from a committed rocprofv3 PMC summary, if it was
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(f"{kernel_name}@{workload}")
+    if not ent or ent.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="oregonator_2d", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--schedule", default="persistent", choices=["persistent", "onelaunch"])
+    ap.add_argument("--variant", type=int, default=0)
+    ap.add_argument("--graph", action="store_true", help="replay a captured hipGraph per step")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the one-launch and mixed-precision side measurements")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): the reaction step has no "
+              "cross-cell communication, so more GPUs would each run an independent shard; "
+              "see DESIGN.md for how the path shards.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1506_04651_amd as rd
+    from paper_1506_04651_amd import roofline
+
+    rd.load()
+    torch.cuda.set_device(0)
+    log("workload", args.workload)
+    w = make_workload(args.workload)
+    prec = rd.FP64 if args.precision == "fp64" else rd.MIXED
+    sched = rd.PERSISTENT if args.schedule == "persistent" else rd.ONE_LAUNCH
+    opts = dict(precision=prec, schedule=sched, variant=args.variant, use_graph=args.graph)
+    u0 = torch.tensor(w.states, dtype=torch.float64, device="cuda")
+
+    # counters of one launch (identical every launch: the integration is
+    # deterministic) -> algorithmic FLOPs per launch
+    log("counter pass")
+    st = torch.zeros((9, w.n), dtype=torch.int32, device="cuda")
+    u = u0.clone()
+    nfail = rd.reaction_step(u, w.dt, w.rtol, w.atol, w.kind, w.params, stats=st, **opts)
+    stats = st.cpu().numpy()
+    flops = roofline.algorithmic_flops(stats, w.kind, w.m)
+    ref_out = u.cpu().numpy()
+    del st
+
+    log("timed run", args.precision, args.schedule, "steps", args.steps)
+    main_run = time_path(rd, torch, w, u0, args.steps, args.warmup, **opts)
+    out_main = main_run.pop("out").cpu().numpy()
+    if not np.array_equal(out_main, ref_out):
+        raise SystemExit("timed launches did not reproduce the counter pass bitwise")
+    avg_s = main_run["avg_launch_ms"] * 1e-3
+    achieved = flops / avg_s / 1e12
+    kname = rd.variant_name(w.kind, w.m, prec, sched, args.variant) or "?"
+    traffic = measured_traffic(kname, args.workload)
+
+    compare = {}
+    if not args.no_compare:
+        for label, o in [("fp64_onelaunch", dict(precision=rd.FP64, schedule=rd.ONE_LAUNCH)),
+                         ("fp64_persistent", dict(precision=rd.FP64, schedule=rd.PERSISTENT)),
+                         ("mixed_persistent", dict(precision=rd.MIXED, schedule=rd.PERSISTENT))]:
+            if o["precision"] == prec and o["schedule"] == sched:
+                continue
+            log("side run", label)
+            r = time_path(rd, torch, w, u0, max(3, args.steps // 4), 1, **o)
+            out = r.pop("out").cpu().numpy()
+            err = np.max(np.abs(out - ref_out) / np.maximum(np.abs(ref_out), w.atol), axis=0)
+            compare[label] = {"value": r["value"], "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
+                              "max_rel_diff_vs_main": float(err.max()),
+                              "frac_within_1e-8_of_main": float(np.mean(err <= 1e-8))}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        from paper_1506_04651_amd import workloads as W
+        ns = min(w.n, 262144 if w.m <= 4 else 2048)
+        idx = W.sample_indices(w.n, ns, 77) if ns < w.n else slice(None)
+        s = w.subset(idx) if ns < w.n else w
+        nth = os.cpu_count() or 1
+        log("cpu baseline: oracle on", s.n, "cells,", nth, "threads")
+        t0 = time.perf_counter()
+        oracle.reaction_step(s.states, s.dt, s.rtol, s.atol, s.kind, s.params, nthreads=nth)
+        el = time.perf_counter() - t0
+        cpu = {"value": s.n / el, "unit": "cell-integrations/s", "cores": nth, "kind": "oracle",
+               "sample": f"{s.n} cells of {w.name} (seeded sample, one pass, {el:.2f} s)"}
+
+    line = {
+        "metric": METRIC,
+        "value": main_run["value"],
+        "unit": "cell-integrations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_run["wall_s"] * 1e3 / args.steps,
+        "p50_ms": main_run["p50_ms"],
+        "p99_ms": main_run["p99_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == rd.FP64 else "f64+f32lu",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_cells": w.n, "m": w.m, "dt": w.dt, "rtol": w.rtol,
+                   "atol": w.atol, "precision": args.precision, "schedule": args.schedule,
+                   "kernel": kname, "graph": bool(args.graph),
+                   "failed_cells": int(nfail)},
+        "roofline": {"bound": "alu", "achieved": achieved,
+                     "peak": roofline.PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / roofline.PEAK_FP64_VECTOR_TFLOPS,
+                     "traffic": traffic,
+                     "flops_per_launch": flops, "avg_launch_ms": main_run["avg_launch_ms"],
+                     "algorithmic_bytes_per_launch": w.n * roofline.bytes_per_cell(w.m)},
+        "cpu_baseline": cpu,
+        "compare": compare,
+        "counters_mean": {k: float(stats[i].mean()) for i, k in enumerate(rd.STAT_NAMES)},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

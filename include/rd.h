@@ -1,0 +1,210 @@
+/*
+ * rd.h -- C ABI of librd, the MI355X (gfx950) Radau5 reaction-step library.
+ *
+ * Operation.  The reaction substep R_dt of the Strang splitting scheme
+ * U_{n+1} = R_{Δt/2} D_{Δt} R_{Δt/2} U_n (Descombes et al., §2.1): every cell
+ * (leaf of the adapted grid) integrates its own stiff system du/dt = f(u) over
+ * [0, dt] with Radau5 (paper §1, footnote: implicit fifth-order Runge-Kutta,
+ * A- and L-stable, adaptive time step), i.e. the 3-stage Radau IIA method with a
+ * simplified Newton iteration on the stage equations, solved through one real
+ * and one complex m x m linear system, an embedded error estimate, and
+ * step-size control (Hairer & Wanner, Solving ODEs II, §IV.8).  Cells are
+ * independent (paper §2.1: as many independent problems as grid nodes); the
+ * number of sub-steps and Newton iterations differs from cell to cell (paper
+ * Appendix A), which is why the default schedule is a persistent kernel whose
+ * lanes claim new cells as soon as theirs finish.
+ *
+ * Layout.  Structure of arrays (paper §3.2, one contiguous array per unknown):
+ * states[i * n_cells + c] is species i of cell c, float64.  The update is in
+ * place: on return (or completion, for async calls) states holds u(dt).
+ * Optional stats: int32, [RD_NSTATS][n_cells], rows
+ *   0 status, 1 nstep (step attempts), 2 naccept, 3 nreject (error-test
+ *   rejections and Newton failures), 4 nfev (f evaluations), 5 njac,
+ *   6 ndec (factorizations of the iteration matrices), 7 nsol (linear solves),
+ *   8 nnewt (Newton iterations).
+ * nfev is the paper's per-node complexity measure (Appendix A).
+ *
+ * Ownership.  states and stats are DEVICE pointers owned by the caller (for
+ * instance torch tensors); the library never frees them and they must stay
+ * valid and untouched until the call completes.  rd_model.params is a HOST
+ * pointer, read during the call only.  The library owns its workspace (claim
+ * counters, model-parameter blocks, captured graphs), allocated lazily per
+ * device and released at process exit.
+ *
+ * Errors.  >= 0: the number of cells whose per-cell status is nonzero (those
+ * cells keep their last accepted state; the others are unaffected).  Per-cell
+ * status: 1 MAXSTEPS, 2 H_TOO_SMALL, 3 SINGULAR (five singular factorizations
+ * in a row), 4 NONFINITE, 5 NEWTON_FAIL (fixed-step mode only).
+ * < 0: nothing was done: RD_EINVAL, RD_ENOMEM, RD_EDEVICE (a HIP error; text in
+ * rd_last_error()), RD_ETOOBIG (request larger than a session's budget),
+ * RD_ECLOSED (session destroyed), RD_ENOTFOUND (unknown request id).
+ * n_cells == 0 is valid and does nothing.
+ */
+#ifndef RD_H
+#define RD_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    RD_OREGONATOR = 1, /* m = 3, params {eps, mu, f, q}: BZ model (paper §1, II):
+                          a' = (-q a - a b + f c)/mu, b' = (q a - a b + b(1-b))/eps,
+                          c' = b - c                                              */
+    RD_KINETICS = 2,   /* m in {1..16}, params {K[m*m], G[m*m]} row-major:
+                          f_i = sum_j K_ij u_j - u_i sum_k G_ik u_k              */
+    RD_NAGUMO = 3,     /* m = 1, params {k}: f = k u^2 (1 - u) (paper §1, I)      */
+    RD_LINEAR = 4,     /* m in {1..16}, params {K[m*m]}: f = K u (tests)         */
+    RD_ROBERTSON = 5   /* m = 3, params {k1, k2, k3}: Robertson kinetics (tests)  */
+};
+
+enum { RD_FP64 = 0, RD_MIXED = 1 };            /* precision */
+enum { RD_PERSISTENT = 0, RD_ONE_LAUNCH = 1 };  /* schedule  */
+
+enum { RD_OK = 0, RD_MAXSTEPS = 1, RD_H_TOO_SMALL = 2, RD_SINGULAR = 3,
+       RD_NONFINITE = 4, RD_NEWTON_FAIL = 5 };
+
+enum { RD_EINVAL = -1, RD_ENOMEM = -2, RD_EDEVICE = -3, RD_ETOOBIG = -4,
+       RD_ECLOSED = -5, RD_ENOTFOUND = -6 };
+
+#define RD_NSTATS 9
+#define RD_MAX_M 16
+
+typedef struct {
+    int32_t kind;          /* RD_OREGONATOR ... */
+    int32_t m;             /* species per cell; must match the kind */
+    const double* params;  /* HOST pointer, n_params doubles */
+    int64_t n_params;
+} rd_model;
+
+typedef struct {
+    int32_t precision;     /* RD_FP64 (default) or RD_MIXED: iteration-matrix LU
+                              factors and triangular solves in FP32; f, residuals,
+                              stage update, error estimate, control in FP64      */
+    int32_t schedule;      /* RD_PERSISTENT (default) or RD_ONE_LAUNCH           */
+    int32_t tol_transform; /* 1 (default): local tolerances rtol' = 0.1 rtol^(2/3),
+                              atol' = rtol' atol / rtol; 0: use rtol, atol as given */
+    int32_t max_steps;     /* step attempts per cell (default 100000)            */
+    int32_t newton_max;    /* Newton iterations per attempt (default 7)          */
+    int32_t fixed_steps;   /* 0 (default): adaptive; N > 0: N equal steps, no error
+                              control (tests)                                      */
+    double h0;             /* first trial step, 0 (default) means dt             */
+    double h_min;          /* 0 (default) means 1e-14 dt                          */
+    int32_t variant;       /* kernel variant: 0 = tuned default, else an id from
+                              rd_variant_count/rd_variant_name                     */
+    int32_t use_graph;     /* 1: capture the launch sequence of this shape in a
+                              hipGraph on first use and replay it afterwards       */
+} rd_options;
+
+/* Fill *opts with the defaults above. */
+void rd_default_options(rd_options* opts);
+
+/*
+ * Synchronous reaction step with default options on the current device's
+ * null stream.  See the file comment for layout, ownership and errors.
+ */
+int64_t rd_reaction_step(double* states, int64_t n_cells, int32_t m, double dt,
+                         double rtol, double atol, const rd_model* model);
+
+/*
+ * Full form.  opts nullable (defaults); stats nullable (DEVICE, [9][n_cells]
+ * int32); hip_stream nullable (= null stream) is a hipStream_t.  async = 0:
+ * returns after completion with the failed-cell count.  async = 1: returns 0
+ * once the work is enqueued; completion is observed through the stream, and
+ * failures through stats.
+ */
+int64_t rd_reaction_step_ex(double* states, int64_t n_cells, int32_t m,
+                            double dt, double rtol, double atol,
+                            const rd_model* model, const rd_options* opts,
+                            int32_t* stats, void* hip_stream, int32_t async);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: a session admits reaction-step requests into an HBM arena of a    */
+/* fixed byte budget.  Admitted requests are copied into the arena, batched   */
+/* with whatever else was admitted at the same time, and run by persistent    */
+/* kernels on a pool of streams, so work of requests that arrive while others */
+/* run overlaps on the device.  Results are copied back into the caller's     */
+/* states (and stats) when the request completes.                             */
+/* ------------------------------------------------------------------------ */
+typedef struct rd_session rd_session;
+
+typedef struct {
+    int32_t done;          /* 1 when complete                                    */
+    int32_t status;        /* 0, or a negative call-level error                  */
+    int64_t n_failed;      /* cells with nonzero per-cell status                 */
+    int64_t n_cells;
+    uint64_t t_submit_ns;  /* CLOCK_MONOTONIC timestamps                         */
+    uint64_t t_admit_ns;
+    uint64_t t_done_ns;    /* completion observed by the session                 */
+    int64_t batch_id;      /* launch batch the request ran in                   */
+} rd_request_info;
+
+/*
+ * Create a session on `device` (HIP ordinal) whose arena holds at most
+ * hbm_budget_bytes.  defaults nullable.  n_streams: concurrent launch streams
+ * (0 = 4).  Returns 0 or a negative error.
+ */
+int32_t rd_session_create(rd_session** out, int32_t device,
+                          size_t hbm_budget_bytes, const rd_options* defaults,
+                          int32_t n_streams);
+
+/*
+ * Queue a request (non-blocking).  states/stats are DEVICE pointers owned by
+ * the caller and must stay valid until the request is done; stats nullable.
+ * The model parameters are copied.  RD_ETOOBIG if the request can never fit the
+ * budget.  *req_id receives an id for rd_poll / rd_wait.
+ */
+int32_t rd_submit(rd_session* s, double* states, int64_t n_cells, int32_t m,
+                  double dt, double rtol, double atol, const rd_model* model,
+                  int32_t* stats, uint64_t* req_id);
+
+/* 0 done (info filled), 1 pending, < 0 error. info nullable. */
+int32_t rd_poll(rd_session* s, uint64_t req_id, rd_request_info* info);
+
+/* Block until done; 0 or < 0. info nullable. */
+int32_t rd_wait(rd_session* s, uint64_t req_id, rd_request_info* info);
+
+/* Bytes of the arena a request of this size would occupy. */
+size_t rd_request_bytes(int64_t n_cells, int32_t m, int32_t with_stats);
+
+/* Drain outstanding requests, free the arena and streams. */
+int32_t rd_session_destroy(rd_session* s);
+
+/* ------------------------------------------------------------------------ */
+/* Introspection                                                              */
+/* ------------------------------------------------------------------------ */
+
+/* Last error message of the calling thread ("" if none). */
+const char* rd_last_error(void);
+
+/* Number of kernel variants for (model kind, m, precision, schedule), and the
+ * name of variant v (1-based); NULL when out of range. */
+int32_t rd_variant_count(int32_t kind, int32_t m, int32_t precision,
+                         int32_t schedule);
+const char* rd_variant_name(int32_t kind, int32_t m, int32_t precision,
+                            int32_t schedule, int32_t variant);
+
+/* Make variant v (1-based) the default for (kind, m, precision, schedule):
+ * the autotuner's result.  0 or RD_EINVAL. */
+int32_t rd_set_default_variant(int32_t kind, int32_t m, int32_t precision,
+                               int32_t schedule, int32_t variant);
+
+/* Device properties the launch sizing uses: compute units and the persistent
+ * grid (workgroups) chosen for (kind, m, precision, variant); < 0 on error. */
+int32_t rd_persistent_grid(int32_t kind, int32_t m, int32_t precision,
+                           int32_t variant, int64_t n_cells);
+
+/*
+ * Time the last call's main kernel: returns the duration in milliseconds of
+ * the most recent rd_reaction_step_ex launch on this thread, measured with HIP
+ * events recorded on the launch stream around the kernel (not the counter
+ * reset), or a negative value if unavailable (async calls must have completed).
+ */
+double rd_last_kernel_ms(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

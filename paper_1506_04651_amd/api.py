@@ -1,0 +1,163 @@
+"""Python surface of librd: the same entry points as include/rd.h, taking torch
+tensors for device memory and torch streams for ordering.  Marshalling only."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import FP64, PERSISTENT, RdModel, RdOptions, RdRequestInfo
+
+
+class RdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"librd error {code} ({_lib.ERRORS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+def _check(ret: int) -> int:
+    if ret < 0:
+        raise RdError(int(ret), _lib.last_error())
+    return int(ret)
+
+
+def _model(kind: int, m: int, params):
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).ravel())
+    mdl = RdModel(int(kind), int(m), p.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), p.size)
+    return mdl, p
+
+
+def make_options(precision=FP64, schedule=PERSISTENT, tol_transform=1, max_steps=100000,
+                 newton_max=7, fixed_steps=0, h0=0.0, h_min=0.0, variant=0,
+                 use_graph=False) -> RdOptions:
+    o = RdOptions()
+    o.precision, o.schedule, o.tol_transform = int(precision), int(schedule), int(tol_transform)
+    o.max_steps, o.newton_max, o.fixed_steps = int(max_steps), int(newton_max), int(fixed_steps)
+    o.h0, o.h_min, o.variant, o.use_graph = float(h0), float(h_min), int(variant), int(use_graph)
+    return o
+
+
+def _check_states(states):
+    import torch
+    if not isinstance(states, torch.Tensor) or states.dtype != torch.float64 or \
+            not states.is_cuda or states.dim() != 2 or not states.is_contiguous():
+        raise ValueError("states must be a contiguous float64 CUDA tensor of shape [m, n]")
+
+
+def _check_stats(stats, n):
+    import torch
+    if stats is None:
+        return None
+    if not isinstance(stats, torch.Tensor) or stats.dtype != torch.int32 or not stats.is_cuda \
+            or tuple(stats.shape) != (_lib.NSTATS, n) or not stats.is_contiguous():
+        raise ValueError(f"stats must be a contiguous int32 CUDA tensor of shape [9, {n}]")
+    return stats.data_ptr()
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def reaction_step(states, dt, rtol, atol, kind, params, *, stats=None, stream=None,
+                  async_=False, **opts) -> int:
+    """Advance every cell (column) of ``states`` [m, n] float64 (device) over
+    [0, dt] in place.  Returns the number of cells with a nonzero status
+    (0 when async_).  Keyword options as in rd_options (precision, schedule,
+    tol_transform, max_steps, newton_max, fixed_steps, h0, h_min, variant,
+    use_graph)."""
+    lib = _lib.load()
+    _check_states(states)
+    m, n = int(states.shape[0]), int(states.shape[1])
+    sp = _check_stats(stats, n)
+    mdl, keep = _model(kind, m, params)
+    o = make_options(**opts)
+    ret = lib.rd_reaction_step_ex(ctypes.c_void_p(states.data_ptr()), n, m, float(dt),
+                                  float(rtol), float(atol), ctypes.byref(mdl), ctypes.byref(o),
+                                  ctypes.c_void_p(sp) if sp else None, _stream_handle(stream),
+                                  1 if async_ else 0)
+    del keep
+    return _check(ret)
+
+
+def last_kernel_ms() -> float:
+    """Duration of this thread's last reaction-step kernel (HIP events on its
+    launch stream), in ms; negative if unavailable."""
+    return float(_lib.load().rd_last_kernel_ms())
+
+
+def variant_count(kind, m, precision=FP64, schedule=PERSISTENT) -> int:
+    return int(_lib.load().rd_variant_count(kind, m, precision, schedule))
+
+
+def variant_name(kind, m, precision=FP64, schedule=PERSISTENT, variant=0) -> str | None:
+    r = _lib.load().rd_variant_name(kind, m, precision, schedule, variant)
+    return r.decode() if r else None
+
+
+def set_default_variant(kind, m, precision, schedule, variant) -> None:
+    _check(_lib.load().rd_set_default_variant(kind, m, precision, schedule, variant))
+
+
+def persistent_grid(kind, m, precision=FP64, variant=0, n_cells=1 << 30) -> int:
+    return _check(_lib.load().rd_persistent_grid(kind, m, precision, variant, n_cells))
+
+
+def request_bytes(n_cells, m, with_stats=False) -> int:
+    return int(_lib.load().rd_request_bytes(n_cells, m, 1 if with_stats else 0))
+
+
+class Session:
+    """Serving session (rd_session_*): requests of any size and model are
+    admitted into an HBM arena of ``budget_bytes`` and run concurrently."""
+
+    def __init__(self, budget_bytes: int, device: int = 0, n_streams: int = 0, **opts):
+        lib = _lib.load()
+        self._h = ctypes.c_void_p()
+        o = make_options(**opts)
+        _check(lib.rd_session_create(ctypes.byref(self._h), int(device), int(budget_bytes),
+                                     ctypes.byref(o), int(n_streams)))
+        self._keep = {}
+
+    def submit(self, states, dt, rtol, atol, kind, params, stats=None) -> int:
+        lib = _lib.load()
+        _check_states(states)
+        m, n = int(states.shape[0]), int(states.shape[1])
+        sp = _check_stats(stats, n)
+        mdl, keep = _model(kind, m, params)
+        rid = ctypes.c_uint64()
+        _check(lib.rd_submit(self._h, ctypes.c_void_p(states.data_ptr()), n, m, float(dt),
+                             float(rtol), float(atol), ctypes.byref(mdl),
+                             ctypes.c_void_p(sp) if sp else None, ctypes.byref(rid)))
+        del keep
+        self._keep[rid.value] = (states, stats)
+        return rid.value
+
+    def poll(self, rid: int):
+        info = RdRequestInfo()
+        r = _check(_lib.load().rd_poll(self._h, ctypes.c_uint64(rid), ctypes.byref(info)))
+        if r == 0:
+            self._keep.pop(rid, None)
+            return info
+        return None
+
+    def wait(self, rid: int) -> RdRequestInfo:
+        info = RdRequestInfo()
+        _check(_lib.load().rd_wait(self._h, ctypes.c_uint64(rid), ctypes.byref(info)))
+        self._keep.pop(rid, None)
+        return info
+
+    def close(self):
+        if self._h:
+            _check(_lib.load().rd_session_destroy(self._h))
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

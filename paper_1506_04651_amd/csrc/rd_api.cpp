@@ -1,0 +1,469 @@
+/*
+ * rd_api.cpp -- the C ABI of librd (declared in include/rd.h): argument
+ * validation, tolerance transformation, model-parameter upload, kernel
+ * selection, launch (direct or through a cached hipGraph) and completion.
+ *
+ * The operation is the reaction substep of the Strang splitting scheme
+ * (Descombes et al., §2.1) integrated per cell with Radau5 (paper §1 footnote;
+ * Hairer & Wanner §IV.8); see include/rd.h for the contract.
+ */
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "rd_internal.h"
+
+namespace rd {
+
+const KernelEntry* small_kernel_table(int* count);
+const KernelEntry* group_kernel_table(int* count);
+
+/* ---------------------------------------------------------------- errors */
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            set_error("%s failed: %s", #expr, hipGetErrorString(e_));                  \
+            return RD_EDEVICE;                                                         \
+        }                                                                              \
+    } while (0)
+
+/* ---------------------------------------------------------------- kernels */
+static std::vector<KernelEntry>& all_kernels() {
+    static std::vector<KernelEntry> v = [] {
+        std::vector<KernelEntry> out;
+        int n = 0;
+        const KernelEntry* t = small_kernel_table(&n);
+        out.insert(out.end(), t, t + n);
+        t = group_kernel_table(&n);
+        out.insert(out.end(), t, t + n);
+        return out;
+    }();
+    return v;
+}
+
+const KernelEntry* kernel_table(int* count) {
+    *count = (int)all_kernels().size();
+    return all_kernels().data();
+}
+
+static std::mutex g_variant_mu;
+static std::map<std::tuple<int, int, int, int>, int> g_default_variant;
+
+static int default_variant(int kind, int m, int precision, int schedule) {
+    std::lock_guard<std::mutex> lk(g_variant_mu);
+    auto it = g_default_variant.find({kind, m, precision, schedule});
+    return it == g_default_variant.end() ? 1 : it->second;
+}
+
+const KernelEntry* find_kernel(int kind, int m, int precision, int schedule, int fixed,
+                               int variant) {
+    if (fixed) variant = 1;
+    else if (variant <= 0) variant = default_variant(kind, m, precision, schedule);
+    for (const KernelEntry& e : all_kernels())
+        if (e.kind == kind && e.m == m && e.precision == precision && e.schedule == schedule &&
+            e.fixed == fixed && e.variant == variant)
+            return &e;
+    return nullptr;
+}
+
+/* ---------------------------------------------------------------- devices */
+static std::mutex g_ctx_mu;
+static DevCtx* g_ctx[64];
+
+DevCtx* current_ctx() {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_error("hipGetDevice: %s", hipGetErrorString(e));
+        return nullptr;
+    }
+    if (dev < 0 || dev >= 64) {
+        set_error("device ordinal %d out of range", dev);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_ctx_mu);
+    if (g_ctx[dev]) return g_ctx[dev];
+    DevCtx* c = new DevCtx();
+    c->device = dev;
+    hipDeviceProp_t prop;
+    if ((e = hipGetDeviceProperties(&prop, dev)) != hipSuccess) {
+        set_error("hipGetDeviceProperties: %s", hipGetErrorString(e));
+        delete c;
+        return nullptr;
+    }
+    c->cu_count = prop.multiProcessorCount;
+    if ((e = hipMalloc((void**)&c->slots, sizeof(unsigned long long) * 2 * kSlots)) != hipSuccess) {
+        set_error("hipMalloc(counter slots): %s", hipGetErrorString(e));
+        delete c;
+        return nullptr;
+    }
+    if ((e = hipMemset(c->slots, 0, sizeof(unsigned long long) * 2 * kSlots)) != hipSuccess) {
+        set_error("hipMemset(counter slots): %s", hipGetErrorString(e));
+        return nullptr;
+    }
+    g_ctx[dev] = c;
+    return c;
+}
+
+int persistent_grid(const DevCtx& c, const KernelEntry* e, int64_t n) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, e->func, e->block, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    const int64_t resident = (int64_t)per_cu * c.cu_count;
+    const int64_t needed = (n + e->block - 1) / e->block;
+    int64_t g = needed < resident ? needed : resident;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+/* ---------------------------------------------------------------- models */
+static bool all_finite(const double* p, int64_t k) {
+    for (int64_t i = 0; i < k; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+bool model_block(const rd_model* md, int32_t m, std::vector<double>& block) {
+    if (!md || md->m != m || !md->params) return false;
+    const double* p = md->params;
+    block.clear();
+    switch (md->kind) {
+    case RD_OREGONATOR:
+        if (m != 3 || md->n_params < 4 || !all_finite(p, 4) || p[0] == 0.0 || p[1] == 0.0) return false;
+        /* {eps, mu, f, q} -> {q, f, 1/mu, 1/eps} */
+        block = {p[3], p[2], 1.0 / p[1], 1.0 / p[0]};
+        return true;
+    case RD_ROBERTSON:
+        if (m != 3 || md->n_params < 3 || !all_finite(p, 3)) return false;
+        block.assign(p, p + 3);
+        return true;
+    case RD_NAGUMO:
+        if (m != 1 || md->n_params < 1 || !all_finite(p, 1)) return false;
+        block.assign(p, p + 1);
+        return true;
+    case RD_LINEAR:
+        if (m < 1 || m > RD_MAX_M || md->n_params < (int64_t)m * m || !all_finite(p, (int64_t)m * m))
+            return false;
+        block.assign(p, p + (size_t)m * m);
+        return true;
+    case RD_KINETICS:
+        if (m < 1 || m > RD_MAX_M || md->n_params < 2LL * m * m || !all_finite(p, 2LL * m * m))
+            return false;
+        block.assign(p, p + 2 * (size_t)m * m);
+        return true;
+    default:
+        return false;
+    }
+}
+
+static const double* device_params(DevCtx& c, int kind, int m, const std::vector<double>& block,
+                                   int* err) {
+    std::vector<double> key;
+    key.reserve(block.size() + 2);
+    key.push_back((double)kind);
+    key.push_back((double)m);
+    key.insert(key.end(), block.begin(), block.end());
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.params.find(key);
+    if (it != c.params.end()) return it->second;
+    double* d = nullptr;
+    hipError_t e = hipMalloc((void**)&d, sizeof(double) * (block.size() + 1));
+    if (e != hipSuccess) {
+        set_error("hipMalloc(params): %s", hipGetErrorString(e));
+        *err = RD_ENOMEM;
+        return nullptr;
+    }
+    e = hipMemcpy(d, block.data(), sizeof(double) * block.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        set_error("hipMemcpy(params): %s", hipGetErrorString(e));
+        *err = RD_EDEVICE;
+        return nullptr;
+    }
+    c.params.emplace(std::move(key), d);
+    return d;
+}
+
+/* ---------------------------------------------------------------- tolerances */
+void make_step_params(double dt, double rtol, double atol, const rd_options& o, StepParams* P) {
+    const double uround = 2.220446049250313e-16;
+    double rt = rtol, at = atol;
+    if (o.tol_transform) {
+        /* the published Radau5 convention: local error test against
+         * 0.1 rtol^(2/3), atol scaled by the same factor */
+        const double q = atol / rtol;
+        rt = 0.1 * std::pow(rtol, 2.0 / 3.0);
+        at = rt * q;
+    }
+    P->dt = dt;
+    P->rtol = rt;
+    P->atol = at;
+    P->newton_tol = std::max(10.0 * uround / rt, std::min(0.03, std::sqrt(rt)));
+    P->h0 = o.h0;
+    P->h_min = o.h_min > 0.0 ? o.h_min : 1e-14 * dt;
+    P->max_steps = o.max_steps;
+    P->kmax = o.newton_max;
+    P->fixed_steps = o.fixed_steps;
+    P->pad = 0;
+}
+
+static bool options_valid(const rd_options& o) {
+    return (o.precision == RD_FP64 || o.precision == RD_MIXED) &&
+           (o.schedule == RD_PERSISTENT || o.schedule == RD_ONE_LAUNCH) && o.max_steps >= 1 &&
+           o.newton_max >= 1 && o.newton_max <= 50 && o.fixed_steps >= 0 && o.h0 >= 0.0 &&
+           o.h_min >= 0.0 && std::isfinite(o.h0) && std::isfinite(o.h_min) && o.variant >= 0;
+}
+
+int prepare(double* states, int64_t n, int32_t m, double dt, double rtol, double atol,
+            const rd_model* model, const rd_options* opts, int32_t* stats, Prepared* out) {
+    rd_options o;
+    rd_default_options(&o);
+    if (opts) o = *opts;
+    if (n < 0 || m < 1 || m > RD_MAX_M) { set_error("bad n_cells or m"); return RD_EINVAL; }
+    if (!std::isfinite(dt) || !(dt > 0.0)) { set_error("dt must be finite and > 0"); return RD_EINVAL; }
+    if (!std::isfinite(rtol) || !(rtol > 0.0)) { set_error("rtol must be finite and > 0"); return RD_EINVAL; }
+    if (!std::isfinite(atol) || !(atol >= 0.0)) { set_error("atol must be finite and >= 0"); return RD_EINVAL; }
+    if (!options_valid(o)) { set_error("invalid rd_options"); return RD_EINVAL; }
+    std::vector<double> block;
+    if (!model || model->m != m || !model_block(model, m, block)) {
+        set_error("invalid model (kind/m/params)");
+        return RD_EINVAL;
+    }
+    if (n > 0 && !states) { set_error("states is null"); return RD_EINVAL; }
+    if (o.fixed_steps > 0 && o.precision != RD_FP64) {
+        set_error("fixed-step mode is available in FP64 only");
+        return RD_EINVAL;
+    }
+    const KernelEntry* e = find_kernel(model->kind, m, o.precision, o.schedule, o.fixed_steps > 0,
+                                       o.variant);
+    if (!e) {
+        set_error("no kernel for kind %d, m %d, precision %d, schedule %d, variant %d", model->kind, m,
+                  o.precision, o.schedule, o.variant);
+        return RD_EINVAL;
+    }
+    out->entry = e;
+    make_step_params(dt, rtol, atol, o, &out->args.P);
+    out->args.states = states;
+    out->args.stats = stats;
+    out->args.n = n;
+    if (n == 0) return 0;
+    DevCtx* c = current_ctx();
+    if (!c) return RD_EDEVICE;
+    out->device = c->device;
+    int err = 0;
+    const double* dp = device_params(*c, model->kind, m, block, &err);
+    if (!dp) return err ? err : RD_EDEVICE;
+    out->args.params = dp;
+    out->grid = e->schedule == RD_PERSISTENT ? persistent_grid(*c, e, n)
+                                             : (int)((n + e->block - 1) / e->block);
+    return 0;
+}
+
+/* ---------------------------------------------------------------- launches */
+struct ThreadTiming {
+    hipEvent_t a = nullptr, b = nullptr;
+    bool valid = false;
+    unsigned long long* host = nullptr; /* pinned readback word */
+};
+static thread_local ThreadTiming g_tt;
+
+static int ensure_thread_objects() {
+    if (!g_tt.a) {
+        HIP_TRY(hipEventCreate(&g_tt.a));
+        HIP_TRY(hipEventCreate(&g_tt.b));
+    }
+    if (!g_tt.host) HIP_TRY(hipHostMalloc((void**)&g_tt.host, sizeof(unsigned long long), 0));
+    return 0;
+}
+
+struct GraphKey {
+    hipStream_t stream;
+    const KernelEntry* entry;
+    double* states;
+    int32_t* stats;
+    const double* params;
+    int64_t n;
+    int grid;
+    StepParams P;
+    bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(*this)) == 0; }
+};
+struct GraphKeyHash {
+    size_t operator()(const GraphKey& k) const {
+        const unsigned char* p = (const unsigned char*)&k;
+        size_t h = 1469598103934665603ull;
+        for (size_t i = 0; i < sizeof(k); ++i) h = (h ^ p[i]) * 1099511628211ull;
+        return h;
+    }
+};
+struct GraphVal {
+    hipGraphExec_t exec = nullptr;
+    unsigned long long* counters = nullptr;
+};
+static std::mutex g_graph_mu;
+static std::unordered_map<GraphKey, GraphVal, GraphKeyHash> g_graphs;
+
+static int launch_prepared(Prepared& pr, hipStream_t s, bool use_graph, unsigned long long** nfail_out) {
+    DevCtx* c = current_ctx();
+    if (!c) return RD_EDEVICE;
+    if (int r = ensure_thread_objects()) return r;
+    g_tt.valid = false;
+    if (use_graph && s != nullptr) {
+        GraphKey key;
+        std::memset(&key, 0, sizeof(key));
+        key.stream = s;
+        key.entry = pr.entry;
+        key.states = pr.args.states;
+        key.stats = pr.args.stats;
+        key.params = pr.args.params;
+        key.n = pr.args.n;
+        key.grid = pr.grid;
+        key.P = pr.args.P;
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        auto it = g_graphs.find(key);
+        if (it == g_graphs.end()) {
+            GraphVal v;
+            HIP_TRY(hipMalloc((void**)&v.counters, 2 * sizeof(unsigned long long)));
+            LaunchArgs a = pr.args;
+            a.counter = v.counters;
+            a.nfail = v.counters + 1;
+            hipGraph_t g = nullptr;
+            HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            hipError_t e1 = launch_reset(v.counters, 2, s);
+            hipError_t e2 = pr.entry->launch(a, pr.grid, s);
+            hipError_t e3 = hipStreamEndCapture(s, &g);
+            if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+                set_error("graph capture failed: %s / %s / %s", hipGetErrorString(e1),
+                          hipGetErrorString(e2), hipGetErrorString(e3));
+                return RD_EDEVICE;
+            }
+            HIP_TRY(hipGraphInstantiate(&v.exec, g, nullptr, nullptr, 0));
+            HIP_TRY(hipGraphDestroy(g));
+            it = g_graphs.emplace(key, v).first;
+        }
+        HIP_TRY(hipEventRecord(g_tt.a, s));
+        HIP_TRY(hipGraphLaunch(it->second.exec, s));
+        HIP_TRY(hipEventRecord(g_tt.b, s));
+        g_tt.valid = true;
+        *nfail_out = it->second.counters + 1;
+        return 0;
+    }
+    const unsigned slot = c->next_slot.fetch_add(1) % kSlots;
+    unsigned long long* cnt = c->slots + 2 * slot;
+    pr.args.counter = cnt;
+    pr.args.nfail = cnt + 1;
+    HIP_TRY(launch_reset(cnt, 2, s));
+    HIP_TRY(hipEventRecord(g_tt.a, s));
+    HIP_TRY(pr.entry->launch(pr.args, pr.grid, s));
+    HIP_TRY(hipEventRecord(g_tt.b, s));
+    g_tt.valid = true;
+    *nfail_out = pr.args.nfail;
+    return 0;
+}
+
+}  // namespace rd
+
+using namespace rd;
+
+extern "C" {
+
+void rd_default_options(rd_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = RD_FP64;
+    o->schedule = RD_PERSISTENT;
+    o->tol_transform = 1;
+    o->max_steps = 100000;
+    o->newton_max = 7;
+    o->fixed_steps = 0;
+    o->h0 = 0.0;
+    o->h_min = 0.0;
+    o->variant = 0;
+    o->use_graph = 0;
+}
+
+int64_t rd_reaction_step_ex(double* states, int64_t n_cells, int32_t m, double dt, double rtol,
+                            double atol, const rd_model* model, const rd_options* opts,
+                            int32_t* stats, void* hip_stream, int32_t async) {
+    Prepared pr;
+    int r = prepare(states, n_cells, m, dt, rtol, atol, model, opts, stats, &pr);
+    if (r < 0) return r;
+    if (n_cells == 0) return 0;
+    hipStream_t s = (hipStream_t)hip_stream;
+    unsigned long long* nfail = nullptr;
+    r = launch_prepared(pr, s, opts && opts->use_graph, &nfail);
+    if (r < 0) return r;
+    if (async) return 0;
+    HIP_TRY(hipMemcpyAsync(g_tt.host, nfail, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return (int64_t)*g_tt.host;
+}
+
+int64_t rd_reaction_step(double* states, int64_t n_cells, int32_t m, double dt, double rtol,
+                         double atol, const rd_model* model) {
+    return rd_reaction_step_ex(states, n_cells, m, dt, rtol, atol, model, nullptr, nullptr, nullptr, 0);
+}
+
+const char* rd_last_error(void) { return g_err; }
+
+double rd_last_kernel_ms(void) {
+    if (!g_tt.valid) return -1.0;
+    if (hipEventSynchronize(g_tt.b) != hipSuccess) return -1.0;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, g_tt.a, g_tt.b) != hipSuccess) return -1.0;
+    return (double)ms;
+}
+
+int32_t rd_variant_count(int32_t kind, int32_t m, int32_t precision, int32_t schedule) {
+    int best = 0;
+    for (const KernelEntry& e : all_kernels())
+        if (e.kind == kind && e.m == m && e.precision == precision && e.schedule == schedule &&
+            !e.fixed && e.variant > best)
+            best = e.variant;
+    return best;
+}
+
+const char* rd_variant_name(int32_t kind, int32_t m, int32_t precision, int32_t schedule,
+                            int32_t variant) {
+    const KernelEntry* e = find_kernel(kind, m, precision, schedule, 0, variant <= 0 ? 0 : variant);
+    return e ? e->name : nullptr;
+}
+
+int32_t rd_set_default_variant(int32_t kind, int32_t m, int32_t precision, int32_t schedule,
+                               int32_t variant) {
+    if (variant < 1 || variant > rd_variant_count(kind, m, precision, schedule)) {
+        set_error("no variant %d for kind %d m %d precision %d schedule %d", variant, kind, m,
+                  precision, schedule);
+        return RD_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_variant_mu);
+    g_default_variant[{kind, m, precision, schedule}] = variant;
+    return 0;
+}
+
+int32_t rd_persistent_grid(int32_t kind, int32_t m, int32_t precision, int32_t variant,
+                           int64_t n_cells) {
+    const KernelEntry* e = find_kernel(kind, m, precision, RD_PERSISTENT, 0, variant);
+    if (!e) { set_error("no such kernel"); return RD_EINVAL; }
+    DevCtx* c = current_ctx();
+    if (!c) return RD_EDEVICE;
+    return persistent_grid(*c, e, n_cells);
+}
+
+}  // extern "C"

@@ -1,0 +1,64 @@
+/*
+ * rd_internal.h -- host-side internals shared by the C-ABI entry points
+ * (rd_api.cpp) and the serving session (rd_serving.cpp).
+ */
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/rd.h"
+#include "rd_launch.h"
+
+namespace rd {
+
+void set_error(const char* fmt, ...);
+
+/* One validated call, ready to launch. */
+struct Prepared {
+    const KernelEntry* entry = nullptr;
+    LaunchArgs args{};
+    int grid = 0;
+    int device = 0;
+    size_t param_key = 0;
+};
+
+/* Per-device state: properties, counter slots, cached parameter blocks. */
+struct DevCtx {
+    int device = -1;
+    int cu_count = 0;
+    unsigned long long* slots = nullptr; /* 2 * kSlots counters */
+    std::atomic<unsigned> next_slot{0};
+    std::mutex mu;
+    std::map<std::vector<double>, double*> params; /* key: {kind, m, block...} */
+};
+constexpr unsigned kSlots = 4096;
+
+/* Context of the current device (created on first use); null on error. */
+DevCtx* current_ctx();
+
+/* Validate arguments, transform tolerances, upload (or find) the model's
+ * parameter block, select the kernel.  Returns 0 or a negative RD_E* code. */
+int prepare(double* states, int64_t n, int32_t m, double dt, double rtol, double atol,
+            const rd_model* model, const rd_options* opts, int32_t* stats, Prepared* out);
+
+/* Grid for a persistent kernel: resident workgroups on the device, capped by
+ * the number of workgroups the cells would fill. */
+int persistent_grid(const DevCtx& c, const KernelEntry* e, int64_t n);
+
+/* Host-side parameter pre-processing shared by direct calls and sessions:
+ * returns false when the model is invalid.  block receives the device layout. */
+bool model_block(const rd_model* model, int32_t m, std::vector<double>& block);
+
+/* Tolerance transformation and Newton stopping tolerance. */
+void make_step_params(double dt, double rtol, double atol, const rd_options& o,
+                      StepParams* P);
+
+const KernelEntry* find_kernel(int kind, int m, int precision, int schedule, int fixed,
+                               int variant);
+
+}  // namespace rd

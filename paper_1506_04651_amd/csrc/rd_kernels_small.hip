@@ -1,0 +1,158 @@
+/*
+ * rd_kernels_small.hip -- reaction-step kernels with one cell per lane
+ * (m <= 4: Oregonator, Robertson, NAGUMO, small linear / kinetics models).
+ *
+ * Two schedules over the same per-cell engine (bitwise-identical results):
+ *
+ *  - one launch per batch: lane c owns cell c start to finish; a wave lives
+ *    as long as its slowest cell.
+ *  - persistent work stealing: a grid sized to the resident capacity of the
+ *    chip; a lane whose cell has finished stores it and claims the next cell
+ *    index from a global counter (one atomic per wave per refill, the claims of
+ *    all idle lanes aggregated).  Every pass of the loop advances each busy
+ *    lane by exactly one Newton iteration, plus step start / step end work for
+ *    the lanes that need it, so lanes of one wave desynchronise freely.  This
+ *    replaces the CPU design's dynamic work stealing over leaves (paper §3.2,
+ *    parallel_for over a blocked range; §4.2 on the uneven reaction cost).
+ *
+ * Every wave leaves the loop once all cell indices are claimed and its own
+ * cells are finished; each cell finishes within max_steps step attempts.
+ */
+#include <hip/hip_runtime.h>
+
+#include "rd_cell_small.h"
+#include "rd_launch.h"
+
+namespace rd {
+
+template <class Model, typename LT, bool FIXED>
+__device__ __forceinline__ void advance(SmallCell<Model, LT>& cell, const Model& md,
+                                        const StepParams& P) {
+    if (cell.phase == PH_START) cell.template start<FIXED>(md, P);
+    if (cell.phase == PH_NEWTON) {
+        const int o = cell.newton(md, P);
+        if (o != NW_CONTINUE) cell.template finish<FIXED>(md, P, o);
+    }
+}
+
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
+k_onelaunch(LaunchArgs a) {
+    const int64_t c = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (c >= a.n) return;
+    const Model md(a.params);
+    SmallCell<Model, LT> cell;
+    cell.load(md, a.P, a.states, a.n, c);
+    while (cell.phase != PH_IDLE) advance<Model, LT, FIXED>(cell, md, a.P);
+    cell.store(a.states, a.stats, a.n, c);
+    if (cell.status != ST_OK) atomicAdd(a.nfail, 1ull);
+}
+
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
+k_persistent(LaunchArgs a) {
+    const Model md(a.params);
+    SmallCell<Model, LT> cell;
+    cell.phase = PH_IDLE;
+    cell.status = ST_OK;
+    int64_t c = -1;
+    bool alive = true;
+    const unsigned lane = __lane_id();
+    for (;;) {
+        const bool need = alive && cell.phase == PH_IDLE;
+        if (need && c >= 0) {
+            cell.store(a.states, a.stats, a.n, c);
+            if (cell.status != ST_OK) atomicAdd(a.nfail, 1ull);
+            c = -1;
+        }
+        const unsigned long long mask = __ballot(need);
+        if (mask) {
+            const int leader = __ffsll((long long)mask) - 1;
+            unsigned long long base = 0;
+            if (lane == (unsigned)leader)
+                base = atomicAdd(a.counter, (unsigned long long)__popcll(mask));
+            base = __shfl(base, leader);
+            if (need) {
+                const unsigned rank = __popcll(mask & ((1ull << lane) - 1ull));
+                const int64_t idx = (int64_t)(base + rank);
+                if (idx < a.n) {
+                    c = idx;
+                    cell.load(md, a.P, a.states, a.n, c);
+                } else {
+                    alive = false;
+                }
+            }
+        }
+        if (__ballot(alive) == 0ull) break;
+        advance<Model, LT, FIXED>(cell, md, a.P);
+    }
+}
+
+__global__ void k_reset(unsigned long long* p, int n) {
+    const int i = threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+hipError_t launch_reset(unsigned long long* p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, p, n);
+    return hipGetLastError();
+}
+
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE>
+hipError_t launch_one(const LaunchArgs& a, int grid, hipStream_t s) {
+    if (grid <= 0) grid = (int)((a.n + BLOCK - 1) / BLOCK);
+    hipLaunchKernelGGL((k_onelaunch<Model, LT, FIXED, BLOCK, WPE>), dim3(grid), dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE>
+hipError_t launch_pers(const LaunchArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_persistent<Model, LT, FIXED, BLOCK, WPE>), dim3(grid), dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+#define RD_ONE(KIND, MODEL, M, PREC, LT, FIXED, VAR, BLOCK, WPE, NAME)                          \
+    {KIND, M, PREC, 1, FIXED, VAR, BLOCK, BLOCK, NAME, &launch_one<MODEL, LT, FIXED, BLOCK, WPE>, \
+     (const void*)&k_onelaunch<MODEL, LT, FIXED, BLOCK, WPE>}
+#define RD_PERS(KIND, MODEL, M, PREC, LT, FIXED, VAR, BLOCK, WPE, NAME)                          \
+    {KIND, M, PREC, 0, FIXED, VAR, BLOCK, BLOCK, NAME, &launch_pers<MODEL, LT, FIXED, BLOCK, WPE>, \
+     (const void*)&k_persistent<MODEL, LT, FIXED, BLOCK, WPE>}
+
+/* model kinds (same numbering as the public header) */
+enum { K_OREG = 1, K_KIN = 2, K_NAG = 3, K_LIN = 4, K_ROB = 5 };
+
+#define RD_MODEL_SET(KIND, MODEL, M, TAG)                                                   \
+    RD_ONE(KIND, MODEL, M, 0, double, false, 1, 256, 1, TAG ".fp64.onelaunch.b256"),        \
+    RD_ONE(KIND, MODEL, M, 1, float, false, 1, 256, 1, TAG ".mixed.onelaunch.b256"),        \
+    RD_PERS(KIND, MODEL, M, 0, double, false, 1, 256, 1, TAG ".fp64.persistent.b256"),      \
+    RD_PERS(KIND, MODEL, M, 1, float, false, 1, 256, 1, TAG ".mixed.persistent.b256"),      \
+    RD_ONE(KIND, MODEL, M, 0, double, true, 1, 256, 1, TAG ".fp64.onelaunch.fixed"),        \
+    RD_PERS(KIND, MODEL, M, 0, double, true, 1, 256, 1, TAG ".fp64.persistent.fixed")
+
+static const KernelEntry g_small_table[] = {
+    RD_MODEL_SET(K_OREG, Oregonator, 3, "oregonator"),
+    /* tuning variants: block size and waves-per-SIMD hint */
+    RD_PERS(K_OREG, Oregonator, 3, 0, double, false, 2, 128, 1, "oregonator.fp64.persistent.b128"),
+    RD_PERS(K_OREG, Oregonator, 3, 0, double, false, 3, 256, 2, "oregonator.fp64.persistent.b256.w2"),
+    RD_PERS(K_OREG, Oregonator, 3, 0, double, false, 4, 64, 1, "oregonator.fp64.persistent.b64"),
+    RD_PERS(K_OREG, Oregonator, 3, 1, float, false, 2, 128, 1, "oregonator.mixed.persistent.b128"),
+    RD_PERS(K_OREG, Oregonator, 3, 1, float, false, 3, 256, 2, "oregonator.mixed.persistent.b256.w2"),
+    RD_PERS(K_OREG, Oregonator, 3, 1, float, false, 4, 64, 1, "oregonator.mixed.persistent.b64"),
+    RD_MODEL_SET(K_ROB, Robertson, 3, "robertson"),
+    RD_MODEL_SET(K_NAG, Nagumo, 1, "nagumo"),
+    RD_MODEL_SET(K_LIN, Linear<1>, 1, "linear1"),
+    RD_MODEL_SET(K_LIN, Linear<2>, 2, "linear2"),
+    RD_MODEL_SET(K_LIN, Linear<3>, 3, "linear3"),
+    RD_MODEL_SET(K_LIN, Linear<4>, 4, "linear4"),
+    RD_MODEL_SET(K_KIN, Kinetics<1>, 1, "kinetics1"),
+    RD_MODEL_SET(K_KIN, Kinetics<2>, 2, "kinetics2"),
+    RD_MODEL_SET(K_KIN, Kinetics<3>, 3, "kinetics3"),
+    RD_MODEL_SET(K_KIN, Kinetics<4>, 4, "kinetics4"),
+};
+
+const KernelEntry* small_kernel_table(int* count) {
+    *count = (int)(sizeof(g_small_table) / sizeof(g_small_table[0]));
+    return g_small_table;
+}
+
+}  // namespace rd

@@ -1,0 +1,49 @@
+/*
+ * rd_launch.h -- internal interface between the host library (rd_api.cpp) and
+ * the kernel translation units: launch arguments and the kernel table.
+ */
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rd {
+
+/* Per-call integration constants (tolerances already transformed). */
+struct StepParams {
+    double dt, rtol, atol, newton_tol, h0, h_min;
+    int32_t max_steps, kmax, fixed_steps, pad;
+};
+
+struct LaunchArgs {
+    double* states;                 /* [m][n] device, in place                  */
+    int32_t* stats;                 /* [9][n] device or null                    */
+    const double* params;           /* device parameter block (pre-processed)  */
+    int64_t n;
+    unsigned long long* counter;    /* claim counter (persistent schedule)      */
+    unsigned long long* nfail;      /* cells with nonzero status                */
+    StepParams P;
+};
+
+typedef hipError_t (*launch_fn)(const LaunchArgs&, int grid, hipStream_t);
+
+struct KernelEntry {
+    int kind;           /* RD_* model kind                              */
+    int m;
+    int precision;      /* 0 FP64, 1 mixed                              */
+    int schedule;       /* 0 persistent, 1 one launch                   */
+    int fixed;          /* 1: fixed-step test mode                      */
+    int variant;        /* 1-based within (kind, m, precision, schedule) */
+    int block;          /* threads per block                            */
+    int cells_per_block;/* for one-launch grids                         */
+    const char* name;
+    launch_fn launch;
+    const void* func;   /* for occupancy queries                        */
+};
+
+/* All kernels compiled into the library. */
+const KernelEntry* kernel_table(int* count);
+
+/* Zero two counters (graph-safe replacement for a memset). */
+hipError_t launch_reset(unsigned long long* p, int n, hipStream_t s);
+
+}  // namespace rd

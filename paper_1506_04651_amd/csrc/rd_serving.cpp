@@ -1,0 +1,380 @@
+/*
+ * rd_serving.cpp -- request sessions (include/rd.h, "Serving").
+ *
+ * A session owns an arena of device memory of a fixed byte budget.  Requests
+ * queue in arrival order; a scheduler thread admits a request as soon as its
+ * working copy (states, and stats if asked for) fits in the arena, copies the
+ * caller's states into the arena, launches the reaction-step kernel on one of
+ * a pool of streams, copies the results back and records an event.  Requests
+ * admitted while others run go to other streams, so their kernels overlap on
+ * the device; completion frees arena space, which admits the next requests.
+ * Per-cell arithmetic does not depend on what else runs, so a request gives
+ * bitwise the same result alone or in a mix (same kernel variant).
+ *
+ * A request that is larger than the whole budget is refused (RD_ETOOBIG).
+ * The queue head may be bypassed by later requests that fit, until it has
+ * waited kHeadWaitNs; from then on admission waits for the head.
+ */
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "rd_internal.h"
+
+namespace rd {
+
+static uint64_t now_ns() {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+/* First-fit allocator over [0, size) with coalescing. */
+class Arena {
+public:
+    explicit Arena(size_t size) { free_[0] = size; }
+    bool alloc(size_t bytes, size_t* off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t noff = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[noff] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+private:
+    std::map<size_t, size_t> free_;
+};
+
+enum ReqState { Q_QUEUED = 0, Q_RUNNING = 1, Q_DONE = 2 };
+
+struct Request {
+    uint64_t id = 0;
+    Prepared pr;
+    double* user_states = nullptr;
+    int32_t* user_stats = nullptr;
+    int32_t m = 0;
+    size_t bytes = 0, off = 0;
+    int state = Q_QUEUED;
+    int status = 0;
+    int slot = -1, stream = -1;
+    int64_t n_failed = 0, batch = -1;
+    uint64_t t_submit = 0, t_admit = 0, t_done = 0;
+    hipEvent_t ev = nullptr;
+};
+
+}  // namespace rd
+
+struct rd_session {
+    int device = 0;
+    size_t budget = 0;
+    char* arena_base = nullptr;
+    std::unique_ptr<rd::Arena> arena;
+    std::vector<hipStream_t> streams;
+    unsigned next_stream = 0;
+    unsigned long long* counters = nullptr; /* 2 per slot */
+    unsigned long long* host_fail = nullptr;/* pinned, 1 per slot */
+    std::vector<int> free_slots;
+    std::vector<hipEvent_t> free_events;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<rd::Request*> queue;
+    std::vector<rd::Request*> running;
+    std::unordered_map<uint64_t, std::unique_ptr<rd::Request>> reqs;
+    uint64_t next_id = 1;
+    int64_t next_batch = 0;
+    bool closing = false;
+    std::thread worker;
+    rd_options defaults{};
+};
+
+namespace rd {
+
+constexpr int kSessionSlots = 1024;
+constexpr uint64_t kHeadWaitNs = 50ull * 1000 * 1000;
+
+/* Enqueue the copies and the kernel of an admitted request; false on a HIP
+ * error (the request then completes with RD_EDEVICE). */
+static bool launch_request(rd_session* s, Request* r) {
+    hipStream_t st = s->streams[r->stream];
+    const int64_t n = r->pr.args.n;
+    const size_t sbytes = (size_t)n * r->m * sizeof(double);
+    double* a_states = (double*)(s->arena_base + r->off);
+    int32_t* a_stats = r->user_stats ? (int32_t*)(s->arena_base + r->off + align256(sbytes)) : nullptr;
+    LaunchArgs a = r->pr.args;
+    a.states = a_states;
+    a.stats = a_stats;
+    a.counter = s->counters + 2 * r->slot;
+    a.nfail = a.counter + 1;
+    if (hipMemcpyAsync(a_states, r->user_states, sbytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return false;
+    if (launch_reset(a.counter, 2, st) != hipSuccess) return false;
+    if (r->pr.entry->launch(a, r->pr.grid, st) != hipSuccess) return false;
+    if (hipMemcpyAsync(r->user_states, a_states, sbytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return false;
+    if (a_stats &&
+        hipMemcpyAsync(r->user_stats, a_stats, (size_t)n * RD_NSTATS * sizeof(int32_t),
+                       hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return false;
+    if (hipMemcpyAsync(s->host_fail + r->slot, a.nfail, sizeof(unsigned long long),
+                       hipMemcpyDeviceToHost, st) != hipSuccess)
+        return false;
+    if (hipEventRecord(r->ev, st) != hipSuccess) return false;
+    return true;
+}
+
+static void complete(rd_session* s, Request* r, int status) {
+    r->status = status;
+    if (status == 0 && r->slot >= 0) r->n_failed = (int64_t)s->host_fail[r->slot];
+    r->state = Q_DONE;
+    r->t_done = now_ns();
+    s->arena->release(r->off, r->bytes);
+    if (r->slot >= 0) s->free_slots.push_back(r->slot);
+    if (r->ev) s->free_events.push_back(r->ev);
+    r->ev = nullptr;
+    r->slot = -1;
+}
+
+static void scheduler(rd_session* s) {
+    hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        /* completions */
+        for (size_t i = 0; i < s->running.size();) {
+            Request* r = s->running[i];
+            const hipError_t q = hipEventQuery(r->ev);
+            if (q == hipErrorNotReady) { ++i; continue; }
+            complete(s, r, q == hipSuccess ? 0 : RD_EDEVICE);
+            s->running[i] = s->running.back();
+            s->running.pop_back();
+            s->cv_done.notify_all();
+        }
+        /* admissions, in arrival order; later requests may pass a head that
+         * does not fit yet unless the head has waited too long */
+        const uint64_t t = now_ns();
+        bool admitted_any = false;
+        const int64_t batch = s->next_batch;
+        for (auto it = s->queue.begin(); it != s->queue.end();) {
+            Request* r = *it;
+            if (s->free_slots.empty() || s->free_events.empty()) break;
+            size_t off = 0;
+            if (!s->arena->alloc(r->bytes, &off)) {
+                if (it == s->queue.begin() && t - r->t_submit > kHeadWaitNs) break;
+                ++it;
+                continue;
+            }
+            r->off = off;
+            r->slot = s->free_slots.back();
+            s->free_slots.pop_back();
+            r->ev = s->free_events.back();
+            s->free_events.pop_back();
+            r->stream = (int)(s->next_stream++ % s->streams.size());
+            r->t_admit = now_ns();
+            r->batch = batch;
+            r->state = Q_RUNNING;
+            admitted_any = true;
+            if (!launch_request(s, r)) {
+                set_error("session launch failed");
+                complete(s, r, RD_EDEVICE);
+                s->cv_done.notify_all();
+            } else {
+                s->running.push_back(r);
+            }
+            it = s->queue.erase(it);
+        }
+        if (admitted_any) ++s->next_batch;
+        if (s->closing && s->queue.empty() && s->running.empty()) break;
+        if (s->running.empty() && !admitted_any) {
+            s->cv_work.wait(lk);
+        } else {
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            lk.lock();
+        }
+    }
+}
+
+}  // namespace rd
+
+using namespace rd;
+
+extern "C" {
+
+size_t rd_request_bytes(int64_t n_cells, int32_t m, int32_t with_stats) {
+    if (n_cells <= 0 || m <= 0) return 0;
+    size_t b = align256((size_t)n_cells * m * sizeof(double));
+    if (with_stats) b += align256((size_t)n_cells * RD_NSTATS * sizeof(int32_t));
+    return b;
+}
+
+int32_t rd_session_create(rd_session** out, int32_t device, size_t hbm_budget_bytes,
+                          const rd_options* defaults, int32_t n_streams) {
+    if (!out || hbm_budget_bytes < 256) { set_error("bad session arguments"); return RD_EINVAL; }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        set_error("bad device %d", device);
+        return RD_EINVAL;
+    }
+    if (hipSetDevice(device) != hipSuccess) { set_error("hipSetDevice failed"); return RD_EDEVICE; }
+    auto* s = new rd_session();
+    s->device = device;
+    s->budget = hbm_budget_bytes;
+    rd_default_options(&s->defaults);
+    if (defaults) s->defaults = *defaults;
+    if (hipMalloc((void**)&s->arena_base, hbm_budget_bytes) != hipSuccess) {
+        set_error("hipMalloc(arena of %zu bytes) failed", hbm_budget_bytes);
+        delete s;
+        return RD_ENOMEM;
+    }
+    s->arena.reset(new Arena(hbm_budget_bytes));
+    const int ns = n_streams > 0 ? n_streams : 4;
+    for (int i = 0; i < ns; ++i) {
+        hipStream_t st;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            set_error("hipStreamCreate failed");
+            return RD_EDEVICE;
+        }
+        s->streams.push_back(st);
+    }
+    if (hipMalloc((void**)&s->counters, 2 * kSessionSlots * sizeof(unsigned long long)) != hipSuccess ||
+        hipHostMalloc((void**)&s->host_fail, kSessionSlots * sizeof(unsigned long long), 0) != hipSuccess) {
+        set_error("session workspace allocation failed");
+        return RD_ENOMEM;
+    }
+    for (int i = kSessionSlots - 1; i >= 0; --i) {
+        s->free_slots.push_back(i);
+        hipEvent_t ev;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            set_error("hipEventCreate failed");
+            return RD_EDEVICE;
+        }
+        s->free_events.push_back(ev);
+    }
+    s->worker = std::thread(scheduler, s);
+    *out = s;
+    return 0;
+}
+
+int32_t rd_submit(rd_session* s, double* states, int64_t n_cells, int32_t m, double dt, double rtol,
+                  double atol, const rd_model* model, int32_t* stats, uint64_t* req_id) {
+    if (!s || !req_id) { set_error("null session or req_id"); return RD_EINVAL; }
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->closing) { set_error("session is closing"); return RD_ECLOSED; }
+    }
+    if (hipSetDevice(s->device) != hipSuccess) { set_error("hipSetDevice failed"); return RD_EDEVICE; }
+    std::unique_ptr<Request> r(new Request());
+    int rc = prepare(states, n_cells, m, dt, rtol, atol, model, &s->defaults, stats, &r->pr);
+    if (rc < 0) return rc;
+    r->user_states = states;
+    r->user_stats = stats;
+    r->m = m;
+    r->bytes = rd_request_bytes(n_cells, m, stats != nullptr);
+    if (r->bytes > s->budget) {
+        set_error("request of %zu bytes exceeds the session budget of %zu", r->bytes, s->budget);
+        return RD_ETOOBIG;
+    }
+    r->t_submit = now_ns();
+    std::lock_guard<std::mutex> lk(s->mu);
+    r->id = s->next_id++;
+    *req_id = r->id;
+    if (n_cells == 0) {
+        r->state = Q_DONE;
+        r->t_admit = r->t_done = r->t_submit;
+        s->reqs.emplace(r->id, std::move(r));
+        return 0;
+    }
+    s->queue.push_back(r.get());
+    s->reqs.emplace(r->id, std::move(r));
+    s->cv_work.notify_one();
+    return 0;
+}
+
+static void fill_info(const Request& r, rd_request_info* info) {
+    if (!info) return;
+    std::memset(info, 0, sizeof(*info));
+    info->done = r.state == Q_DONE;
+    info->status = r.status;
+    info->n_failed = r.n_failed;
+    info->n_cells = r.pr.args.n;
+    info->t_submit_ns = r.t_submit;
+    info->t_admit_ns = r.t_admit;
+    info->t_done_ns = r.t_done;
+    info->batch_id = r.batch;
+}
+
+int32_t rd_poll(rd_session* s, uint64_t req_id, rd_request_info* info) {
+    if (!s) { set_error("null session"); return RD_EINVAL; }
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(req_id);
+    if (it == s->reqs.end()) { set_error("unknown request %llu", (unsigned long long)req_id); return RD_ENOTFOUND; }
+    fill_info(*it->second, info);
+    if (it->second->state != Q_DONE) return 1;
+    const int st = it->second->status;
+    s->reqs.erase(it);
+    return st < 0 ? st : 0;
+}
+
+int32_t rd_wait(rd_session* s, uint64_t req_id, rd_request_info* info) {
+    if (!s) { set_error("null session"); return RD_EINVAL; }
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(req_id);
+    if (it == s->reqs.end()) { set_error("unknown request %llu", (unsigned long long)req_id); return RD_ENOTFOUND; }
+    Request* r = it->second.get();
+    s->cv_done.wait(lk, [&] { return r->state == Q_DONE; });
+    fill_info(*r, info);
+    const int st = r->status;
+    s->reqs.erase(req_id);
+    return st < 0 ? st : 0;
+}
+
+int32_t rd_session_destroy(rd_session* s) {
+    if (!s) { set_error("null session"); return RD_EINVAL; }
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->closing = true;
+        s->cv_work.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    for (hipStream_t st : s->streams) {
+        hipStreamSynchronize(st);
+        hipStreamDestroy(st);
+    }
+    for (hipEvent_t ev : s->free_events) hipEventDestroy(ev);
+    hipFree(s->counters);
+    hipHostFree(s->host_fail);
+    hipFree(s->arena_base);
+    delete s;
+    return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+"""The C-ABI library loads on the host and exports every symbol include/rd.h
+declares; host-side validation paths (no GPU compute)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "rd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rd_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1506_04651_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("librd.so not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_1506_04651_amd import _lib
+    names = declared_symbols()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in _lib.SIGNATURES, f"{n} has no Python binding"
+
+
+def test_default_options(lib):
+    from paper_1506_04651_amd import _lib
+    o = _lib.default_options()
+    assert (o.precision, o.schedule, o.tol_transform, o.max_steps, o.newton_max,
+            o.fixed_steps, o.h0, o.h_min, o.variant, o.use_graph) == (0, 0, 1, 100000, 7, 0,
+                                                                       0.0, 0.0, 0, 0)
+
+
+def test_request_bytes(lib):
+    assert lib.rd_request_bytes(0, 3, 0) == 0
+    assert lib.rd_request_bytes(1000, 3, 0) == 24064  # 24000 rounded up to 256
+    assert lib.rd_request_bytes(1000, 3, 1) == 24064 + 36096
+
+
+def test_variants_listed(lib):
+    import paper_1506_04651_amd as rd
+    for prec in (rd.FP64, rd.MIXED):
+        for sched in (rd.PERSISTENT, rd.ONE_LAUNCH):
+            n = rd.variant_count(rd.OREGONATOR, 3, prec, sched)
+            assert n >= 1
+            for v in range(1, n + 1):
+                assert rd.variant_name(rd.OREGONATOR, 3, prec, sched, v)
+    with pytest.raises(rd.RdError):
+        rd.set_default_variant(rd.OREGONATOR, 3, rd.FP64, rd.PERSISTENT, 999)
+
+
+def test_validation_before_device_use(lib):
+    """Invalid calls return RD_EINVAL from host-side checks; empty batches
+    return 0 without touching a device."""
+    from paper_1506_04651_amd import _lib
+    p = (ctypes.c_double * 4)(1e-2, 1e-5, 1.6, 2e-3)
+    good = _lib.RdModel(1, 3, ctypes.cast(p, ctypes.POINTER(ctypes.c_double)), 4)
+    bad_kind = _lib.RdModel(9, 3, ctypes.cast(p, ctypes.POINTER(ctypes.c_double)), 4)
+    short = _lib.RdModel(1, 3, ctypes.cast(p, ctypes.POINTER(ctypes.c_double)), 2)
+    call = lib.rd_reaction_step_ex
+    assert call(None, 0, 3, 0.1, 1e-5, 1e-5, ctypes.byref(good), None, None, None, 0) == 0
+    dummy = ctypes.c_void_p(1)
+    for args in [(dummy, 10, 3, 0.0, 1e-5, 1e-5, good), (dummy, 10, 3, float("nan"), 1e-5, 1e-5, good),
+                 (dummy, 10, 3, 0.1, 0.0, 1e-5, good), (dummy, 10, 3, 0.1, 1e-5, -1.0, good),
+                 (dummy, -1, 3, 0.1, 1e-5, 1e-5, good), (dummy, 10, 2, 0.1, 1e-5, 1e-5, good),
+                 (dummy, 10, 3, 0.1, 1e-5, 1e-5, bad_kind), (dummy, 10, 3, 0.1, 1e-5, 1e-5, short),
+                 (None, 10, 3, 0.1, 1e-5, 1e-5, good)]:
+        st, n, m, dt, rt, at, md = args
+        assert call(st, n, m, dt, rt, at, ctypes.byref(md), None, None, None, 0) == -1, args
+        assert lib.rd_last_error()
+    o = _lib.default_options()
+    o.precision = 1
+    o.fixed_steps = 3
+    assert call(dummy, 10, 3, 0.1, 1e-5, 1e-5, ctypes.byref(good), ctypes.byref(o), None, None, 0) == -1
+    o = _lib.default_options()
+    o.newton_max = 0
+    assert call(dummy, 10, 3, 0.1, 1e-5, 1e-5, ctypes.byref(good), ctypes.byref(o), None, None, 0) == -1
+
+
+def test_product_path_does_not_reference_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1506_04651_amd")
+    for dp, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                txt = open(os.path.join(dp, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "rdo_" not in txt and "liboracle" not in txt, f
