@@ -107,6 +107,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the one-launch and mixed-precision side measurements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the library's default kernel variants instead of timing them all")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -129,6 +131,19 @@ def main():
     sched = rd.PERSISTENT if args.schedule == "persistent" else rd.ONE_LAUNCH
     opts = dict(precision=prec, schedule=sched, variant=args.variant, use_graph=args.graph)
     u0 = torch.tensor(w.states, dtype=torch.float64, device="cuda")
+
+    tuning = {}
+    if not args.no_autotune and args.variant == 0:
+        from paper_1506_04651_amd import autotune
+        paths = [(prec, sched)]
+        if not args.no_compare:
+            paths += [(p, s) for p in (rd.FP64, rd.MIXED) for s in (rd.PERSISTENT, rd.ONE_LAUNCH)
+                      if (p, s) != (prec, sched)]
+        for p, s in paths:
+            log("autotune precision", p, "schedule", s)
+            r = autotune.tune(u0, w.dt, w.rtol, w.atol, w.kind, w.params, p, s, reps=2)
+            tuning[f"precision{p}_schedule{s}"] = {r["names"][v]: round(ms, 4)
+                                                   for v, ms in r["ms"].items()}
 
     # counters of one launch (identical every launch: the integration is
     # deterministic) -> algorithmic FLOPs per launch
@@ -155,7 +170,8 @@ def main():
     if not args.no_compare:
         for label, o in [("fp64_onelaunch", dict(precision=rd.FP64, schedule=rd.ONE_LAUNCH)),
                          ("fp64_persistent", dict(precision=rd.FP64, schedule=rd.PERSISTENT)),
-                         ("mixed_persistent", dict(precision=rd.MIXED, schedule=rd.PERSISTENT))]:
+                         ("mixed_persistent", dict(precision=rd.MIXED, schedule=rd.PERSISTENT)),
+                         ("mixed_onelaunch", dict(precision=rd.MIXED, schedule=rd.ONE_LAUNCH))]:
             if o["precision"] == prec and o["schedule"] == sched:
                 continue
             log("side run", label)
@@ -163,6 +179,8 @@ def main():
             out = r.pop("out").cpu().numpy()
             err = np.max(np.abs(out - ref_out) / np.maximum(np.abs(ref_out), w.atol), axis=0)
             compare[label] = {"value": r["value"], "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
+                              "kernel": rd.variant_name(w.kind, w.m, o["precision"],
+                                                        o["schedule"], 0),
                               "max_rel_diff_vs_main": float(err.max()),
                               "frac_within_1e-8_of_main": float(np.mean(err <= 1e-8))}
 
@@ -208,6 +226,7 @@ def main():
                      "algorithmic_bytes_per_launch": w.n * roofline.bytes_per_cell(w.m)},
         "cpu_baseline": cpu,
         "compare": compare,
+        "autotune_ms": tuning,
         "counters_mean": {k: float(stats[i].mean()) for i, k in enumerate(rd.STAT_NAMES)},
     }
     print(json.dumps(line), flush=True)

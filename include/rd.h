@@ -96,6 +96,9 @@ typedef struct {
                               rd_variant_count/rd_variant_name                     */
     int32_t use_graph;     /* 1: capture the launch sequence of this shape in a
                               hipGraph on first use and replay it afterwards       */
+    int32_t order;         /* claim order of the persistent schedule: 1 (default)
+                              longest first, by a per-cell cost estimate (bucketed
+                              scaled initial rate |f(u0)| dt / sc); 0 cell order  */
 } rd_options;
 
 /* Fill *opts with the defaults above. */

@@ -30,7 +30,8 @@ class RdOptions(ctypes.Structure):
                 ("tol_transform", ctypes.c_int32), ("max_steps", ctypes.c_int32),
                 ("newton_max", ctypes.c_int32), ("fixed_steps", ctypes.c_int32),
                 ("h0", ctypes.c_double), ("h_min", ctypes.c_double),
-                ("variant", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("variant", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("order", ctypes.c_int32)]
 
 
 class RdRequestInfo(ctypes.Structure):

@@ -30,8 +30,9 @@ def _model(kind: int, m: int, params):
 
 def make_options(precision=FP64, schedule=PERSISTENT, tol_transform=1, max_steps=100000,
                  newton_max=7, fixed_steps=0, h0=0.0, h_min=0.0, variant=0,
-                 use_graph=False) -> RdOptions:
+                 use_graph=False, order=1) -> RdOptions:
     o = RdOptions()
+    o.order = int(order)
     o.precision, o.schedule, o.tol_transform = int(precision), int(schedule), int(tol_transform)
     o.max_steps, o.newton_max, o.fixed_steps = int(max_steps), int(newton_max), int(fixed_steps)
     o.h0, o.h_min, o.variant, o.use_graph = float(h0), float(h_min), int(variant), int(use_graph)

@@ -1,0 +1,137 @@
+"""Autotuner for the reaction-step kernels.
+
+The library compiles several variants of each kernel: work-group size, the
+waves-per-SIMD target the register allocator is held to (higher occupancy at
+the price of spills), and where the per-cell matrices live (registers or
+LDS).  Which one is fastest depends on the model, m, the precision and on the
+distribution of per-cell cost in the batch, so the choice is measured: every
+variant is timed on the caller's own batch (HIP events on the launch stream),
+the fastest becomes the library default for (kind, m, precision, schedule),
+and the result is cached in a JSON file keyed by device name.
+
+CLI:  python -m paper_1506_04651_amd.autotune --workload oregonator_2d
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+
+from . import api
+from ._lib import FP64, MIXED, ONE_LAUNCH, PERSISTENT
+
+DEFAULT_CACHE = os.environ.get("RD_AUTOTUNE_CACHE",
+                               os.path.join(os.path.expanduser("~"), ".cache", "rd_autotune.json"))
+
+
+def _device_name():
+    import torch
+    return torch.cuda.get_device_name(0)
+
+
+def time_variant(states0, dt, rtol, atol, kind, params, precision, schedule, variant, reps=3):
+    """Median milliseconds of `reps` launches of one variant (after one warm-up)."""
+    import torch
+    u = torch.empty_like(states0)
+    stream = torch.cuda.current_stream()
+    times = []
+    for i in range(reps + 1):
+        u.copy_(states0)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        api.reaction_step(u, dt, rtol, atol, kind, params, precision=precision,
+                          schedule=schedule, variant=variant, async_=True)
+        b.record(stream)
+        b.synchronize()
+        if i:
+            times.append(a.elapsed_time(b))
+    times.sort()
+    return times[len(times) // 2], u
+
+
+def tune(states0, dt, rtol, atol, kind, params, precision=FP64, schedule=PERSISTENT, reps=3,
+         apply=True, verbose=False):
+    """Time every variant; make the fastest the default.  Returns
+    {"best": v, "ms": {v: ms}, "names": {v: name}}.  Variants whose output
+    differs bitwise from variant 1's are rejected (they must run the same
+    per-cell arithmetic)."""
+    import torch
+    m = int(states0.shape[0])
+    nv = api.variant_count(kind, m, precision, schedule)
+    res = {"ms": {}, "names": {}, "rejected": []}
+    ref = None
+    for v in range(1, nv + 1):
+        ms, out = time_variant(states0, dt, rtol, atol, kind, params, precision, schedule, v, reps)
+        name = api.variant_name(kind, m, precision, schedule, v)
+        if ref is None:
+            ref = out.clone()
+        elif not torch.equal(out, ref):
+            res["rejected"].append(v)
+            if verbose:
+                print(f"  variant {v} {name}: output differs from variant 1, rejected",
+                      file=sys.stderr)
+            continue
+        res["ms"][v] = ms
+        res["names"][v] = name
+        if verbose:
+            print(f"  variant {v:2d} {name:45s} {ms:8.3f} ms", file=sys.stderr, flush=True)
+    best = min(res["ms"], key=res["ms"].get)
+    res["best"] = best
+    if apply:
+        api.set_default_variant(kind, m, precision, schedule, best)
+    return res
+
+
+def save(results: dict, path: str = DEFAULT_CACHE):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    try:
+        with open(path) as fh:
+            cache = json.load(fh)
+    except (OSError, ValueError):
+        cache = {}
+    cache.setdefault(_device_name(), {}).update(results)
+    with open(path, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+
+
+def apply_cache(path: str = DEFAULT_CACHE) -> int:
+    """Set the cached best variants for this device as defaults; returns how many."""
+    try:
+        with open(path) as fh:
+            cache = json.load(fh)
+    except (OSError, ValueError):
+        return 0
+    n = 0
+    for key, rec in cache.get(_device_name(), {}).items():
+        kind, m, prec, sched = (int(x) for x in key.split(":")[:4])
+        api.set_default_variant(kind, m, prec, sched, int(rec["best"]))
+        n += 1
+    return n
+
+
+def main():
+    import torch
+
+    from . import workloads as W
+    ap = argparse.ArgumentParser(description="time every kernel variant on a workload")
+    ap.add_argument("--workload", default="oregonator_2d", choices=sorted(W.CONFIGS))
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--cache", default=DEFAULT_CACHE)
+    args = ap.parse_args()
+    w = W.CONFIGS[args.workload]()
+    u0 = torch.tensor(w.states, dtype=torch.float64, device="cuda")
+    out = {}
+    for prec in (FP64, MIXED):
+        for sched in (PERSISTENT, ONE_LAUNCH):
+            print(f"{w.name} precision {prec} schedule {sched}", file=sys.stderr, flush=True)
+            r = tune(u0, w.dt, w.rtol, w.atol, w.kind, w.params, prec, sched, args.reps,
+                     verbose=True)
+            out[f"{w.kind}:{w.m}:{prec}:{sched}:{w.name}"] = {"best": r["best"], "ms": r["ms"],
+                                                              "names": r["names"]}
+    save(out, args.cache)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -18,7 +18,8 @@ BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "librd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["rd_api.cpp", "rd_serving.cpp", "rd_kernels_small.hip", "rd_kernels_group.hip"]
+SOURCES = ["rd_api.cpp", "rd_serving.cpp", "rd_kernels_small.hip", "rd_kernels_group.hip",
+           "rd_order.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-result", "-I", INCLUDE, "-I", CSRC]

@@ -122,6 +122,49 @@ DevCtx* current_ctx() {
     return c;
 }
 
+void* stream_workspace(DevCtx& c, hipStream_t s, size_t bytes, int* err) {
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.order_ws.find(s);
+    if (it != c.order_ws.end() && it->second.second >= bytes) return it->second.first;
+    size_t cap = bytes + bytes / 2;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, cap);
+    if (e != hipSuccess) {
+        set_error("hipMalloc(workspace of %zu bytes): %s", cap, hipGetErrorString(e));
+        *err = RD_ENOMEM;
+        return nullptr;
+    }
+    if (it != c.order_ws.end()) {
+        c.retired.push_back(it->second.first);
+        it->second = {p, cap};
+    } else {
+        c.order_ws[s] = {p, cap};
+    }
+    return p;
+}
+
+/* Below this many cells the claim order is left natural (the sort would cost
+ * more than the tail it removes). */
+constexpr int64_t kOrderMinCells = 8192;
+
+int enqueue_order(DevCtx& c, Prepared& pr, hipStream_t s) {
+    pr.args.order = nullptr;
+    if (pr.entry->schedule != RD_PERSISTENT || !pr.order || pr.args.n < kOrderMinCells ||
+        pr.args.n > INT32_MAX)
+        return 0;
+    order_fn fn = find_order_fn(pr.entry->kind, pr.entry->m);
+    if (!fn) return 0;
+    const size_t wsb = order_workspace_bytes(pr.args.n);
+    const size_t ordb = ((size_t)pr.args.n * sizeof(int32_t) + 255) & ~(size_t)255;
+    int err = 0;
+    char* ws = (char*)stream_workspace(c, s, ordb + wsb, &err);
+    if (!ws) return err ? err : RD_ENOMEM;
+    int32_t* order = (int32_t*)ws;
+    HIP_TRY(fn(pr.args, ws + ordb, order, s));
+    pr.args.order = order;
+    return 0;
+}
+
 int persistent_grid(const DevCtx& c, const KernelEntry* e, int64_t n) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, e->func, e->block, 0) != hipSuccess ||
@@ -228,7 +271,8 @@ static bool options_valid(const rd_options& o) {
     return (o.precision == RD_FP64 || o.precision == RD_MIXED) &&
            (o.schedule == RD_PERSISTENT || o.schedule == RD_ONE_LAUNCH) && o.max_steps >= 1 &&
            o.newton_max >= 1 && o.newton_max <= 50 && o.fixed_steps >= 0 && o.h0 >= 0.0 &&
-           o.h_min >= 0.0 && std::isfinite(o.h0) && std::isfinite(o.h_min) && o.variant >= 0;
+           o.h_min >= 0.0 && std::isfinite(o.h0) && std::isfinite(o.h_min) && o.variant >= 0 &&
+           (o.order == 0 || o.order == 1);
 }
 
 int prepare(double* states, int64_t n, int32_t m, double dt, double rtol, double atol,
@@ -259,6 +303,7 @@ int prepare(double* states, int64_t n, int32_t m, double dt, double rtol, double
         return RD_EINVAL;
     }
     out->entry = e;
+    out->order = o.order;
     make_step_params(dt, rtol, atol, o, &out->args.P);
     out->args.states = states;
     out->args.stats = stats;
@@ -344,7 +389,21 @@ static int launch_prepared(Prepared& pr, hipStream_t s, bool use_graph, unsigned
             a.counter = v.counters;
             a.nfail = v.counters + 1;
             hipGraph_t g = nullptr;
+            /* workspace is allocated before the capture starts */
+            if (pr.entry->schedule == RD_PERSISTENT && pr.order) {
+                int err = 0;
+                const size_t need = (((size_t)pr.args.n * 4 + 255) & ~(size_t)255) +
+                                    order_workspace_bytes(pr.args.n);
+                if (!stream_workspace(*c, s, need, &err)) return err;
+            }
             HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            if (int r = enqueue_order(*c, pr, s)) {
+                hipGraph_t dummy = nullptr;
+                hipStreamEndCapture(s, &dummy);
+                if (dummy) hipGraphDestroy(dummy);
+                return r;
+            }
+            a.order = pr.args.order;
             hipError_t e1 = launch_reset(v.counters, 2, s);
             hipError_t e2 = pr.entry->launch(a, pr.grid, s);
             hipError_t e3 = hipStreamEndCapture(s, &g);
@@ -368,6 +427,7 @@ static int launch_prepared(Prepared& pr, hipStream_t s, bool use_graph, unsigned
     unsigned long long* cnt = c->slots + 2 * slot;
     pr.args.counter = cnt;
     pr.args.nfail = cnt + 1;
+    if (int r = enqueue_order(*c, pr, s)) return r;
     HIP_TRY(launch_reset(cnt, 2, s));
     HIP_TRY(hipEventRecord(g_tt.a, s));
     HIP_TRY(pr.entry->launch(pr.args, pr.grid, s));
@@ -396,6 +456,7 @@ void rd_default_options(rd_options* o) {
     o->h_min = 0.0;
     o->variant = 0;
     o->use_graph = 0;
+    o->order = 1;
 }
 
 int64_t rd_reaction_step_ex(double* states, int64_t n_cells, int32_t m, double dt, double rtol,

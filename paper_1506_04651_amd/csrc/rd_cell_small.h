@@ -1,5 +1,5 @@
 /*
- * rd_cell_small.h -- Radau5 for one cell held entirely by one lane (m <= 4).
+ * rd_cell_small.h -- Radau5 for one cell held by one lane (m <= 4).
  *
  * Method (Hairer & Wanner, Solving ODEs II, §IV.8; paper §1 footnote on
  * Radau5 and Appendix A): 3-stage Radau IIA; the stage increments Z solve
@@ -9,17 +9,23 @@
  * into one real m x m system with E1 = (gamma/h) I - J and one complex m x m
  * system with E2 = ((alpha + i beta)/h) I - J.  The embedded error estimate
  * is filtered through E1; step sizes follow the classical controller with the
- * predictive (Gustafsson) correction.  Every decision below is the same as in
- * the FP64 CPU oracle's reading of the method; only the linear algebra is
- * arranged for registers.
+ * predictive (Gustafsson) correction.  Every decision is the one the FP64 CPU
+ * oracle takes; only the arithmetic is arranged for registers (reciprocals
+ * instead of divisions, division-free forms of the Newton tests), so results
+ * agree with the oracle to rounding.
  *
- * The cell advances as a small state machine (START -> NEWTON* -> START ...)
- * so that a lane can take one Newton iteration per pass of the scheduling loop
- * regardless of what the other lanes of its wave are doing.
+ * Register budget: the Newton iterate is kept in transformed form W only
+ * (Z = T W is formed on the fly), and the two arrays touched once per step --
+ * the Jacobian and the stage increments of the last accepted step -- live in
+ * LDS, one column of a [rows][BLOCK] array per lane (conflict-free).
+ *
+ * The cell advances as a state machine (START -> NEWTON* -> START ...) so a
+ * lane takes one Newton iteration per pass of the scheduling loop whatever its
+ * wave-mates are doing.
  *
  * LT is the type of the LU factors and triangular solves: double for the FP64
- * path, float for the mixed path (residuals, stage values, error estimate and
- * control stay double).
+ * path, float for the mixed path (f, residuals, W, error estimate and control
+ * stay double).
  */
 #pragma once
 #include <hip/hip_runtime.h>
@@ -36,18 +42,23 @@ enum : int { ST_OK = 0, ST_MAXSTEPS = 1, ST_HSMALL = 2, ST_SINGULAR = 3,
 enum : int { PH_IDLE = 0, PH_START = 1, PH_NEWTON = 2 };
 enum : int { NW_CONTINUE = 0, NW_CONVERGED = 1, NW_FAILED = 2 };
 
+/* flag bits */
+enum : unsigned { F_FIRST = 1u, F_REJECT = 2u, F_JSTALE = 4u, F_JATY0 = 8u, F_LUOK = 16u,
+                  F_OLD = 32u, F_ACC = 64u, F_LAST = 128u, F_KEEPJ = 256u };
+
 constexpr double UROUND = 2.220446049250313e-16;
 
 __device__ __forceinline__ bool finite_d(double x) { return __builtin_isfinite(x); }
 
 /* ---------------- small dense LU with partial pivoting ------------------ */
 /* Factor a in place (unit-lower L below the diagonal, reciprocal of U's
- * diagonal on the diagonal).  Row swaps are done with selects so every index
- * stays a compile-time constant (registers, no scratch).  Returns false on an
- * exactly-zero pivot. */
+ * diagonal on the diagonal).  Row swaps are selects so every index stays a
+ * compile-time constant.  The pivot rows are returned packed, 2 bits per
+ * elimination step.  Returns false on an exactly-zero pivot. */
 template <int M, typename T>
-__device__ __forceinline__ bool lu_real(T (&a)[M][M], int (&piv)[M]) {
+__device__ __forceinline__ bool lu_real(T (&a)[M][M], unsigned& piv) {
     bool ok = true;
+    piv = 0;
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         int p = k;
@@ -59,7 +70,7 @@ __device__ __forceinline__ bool lu_real(T (&a)[M][M], int (&piv)[M]) {
             best = gt ? v : best;
             p = gt ? i : p;
         }
-        piv[k] = p;
+        piv |= (unsigned)p << (2 * k);
 #pragma unroll
         for (int i = k + 1; i < M; ++i) {
             const bool s = (p == i);
@@ -85,13 +96,13 @@ __device__ __forceinline__ bool lu_real(T (&a)[M][M], int (&piv)[M]) {
 }
 
 template <int M, typename T>
-__device__ __forceinline__ void lu_solve_real(const T (&a)[M][M], const int (&piv)[M],
-                                              T (&b)[M]) {
+__device__ __forceinline__ void lu_solve_real(const T (&a)[M][M], unsigned piv, T (&b)[M]) {
 #pragma unroll
-    for (int k = 0; k < M; ++k) {
+    for (int k = 0; k < M - 1; ++k) {
+        const int p = (piv >> (2 * k)) & 3;
 #pragma unroll
         for (int i = k + 1; i < M; ++i) {
-            const bool s = (piv[k] == i);
+            const bool s = (p == i);
             const T bk = b[k], bi = b[i];
             b[k] = s ? bi : bk;
             b[i] = s ? bk : bi;
@@ -112,8 +123,9 @@ __device__ __forceinline__ void lu_solve_real(const T (&a)[M][M], const int (&pi
 
 /* Complex version, real and imaginary parts in separate arrays. */
 template <int M, typename T>
-__device__ __forceinline__ bool lu_cplx(T (&ar)[M][M], T (&ai)[M][M], int (&piv)[M]) {
+__device__ __forceinline__ bool lu_cplx(T (&ar)[M][M], T (&ai)[M][M], unsigned& piv) {
     bool ok = true;
+    piv = 0;
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         int p = k;
@@ -125,7 +137,7 @@ __device__ __forceinline__ bool lu_cplx(T (&ar)[M][M], T (&ai)[M][M], int (&piv)
             best = gt ? v : best;
             p = gt ? i : p;
         }
-        piv[k] = p;
+        piv |= (unsigned)p << (2 * k);
 #pragma unroll
         for (int i = k + 1; i < M; ++i) {
             const bool s = (p == i);
@@ -165,12 +177,13 @@ __device__ __forceinline__ bool lu_cplx(T (&ar)[M][M], T (&ai)[M][M], int (&piv)
 
 template <int M, typename T>
 __device__ __forceinline__ void lu_solve_cplx(const T (&ar)[M][M], const T (&ai)[M][M],
-                                              const int (&piv)[M], T (&br)[M], T (&bi)[M]) {
+                                              unsigned piv, T (&br)[M], T (&bi)[M]) {
 #pragma unroll
-    for (int k = 0; k < M; ++k) {
+    for (int k = 0; k < M - 1; ++k) {
+        const int p = (piv >> (2 * k)) & 3;
 #pragma unroll
         for (int i = k + 1; i < M; ++i) {
-            const bool s = (piv[k] == i);
+            const bool s = (p == i);
             T x = br[k], y = br[i];
             br[k] = s ? y : x;
             br[i] = s ? x : y;
@@ -203,22 +216,41 @@ __device__ __forceinline__ void lu_solve_cplx(const T (&ar)[M][M], const T (&ai)
     }
 }
 
+/* Per-lane LDS slots: a [ROWS][BLOCK] array, lane column `tid`. */
+template <int BLOCK>
+struct LdsCol {
+    double* base; /* &arr[0][tid] */
+    __device__ __forceinline__ double& operator[](int row) const { return base[row * BLOCK]; }
+};
+
+/* Rows of the per-lane LDS column: Jacobian (M*M), then Z of the last
+ * accepted step (3*M). */
+template <int M>
+struct SmallLds {
+    static constexpr int J0 = 0;
+    static constexpr int Z0 = M * M;
+    static constexpr int ROWS = M * M + 3 * M;
+};
+
 /* ---------------- the per-cell engine ----------------------------------- */
-template <class Model, typename LT>
+template <class Model, typename LT, int BLOCK>
 struct SmallCell {
     static constexpr int M = Model::M;
+    using L = SmallLds<M>;
 
     /* state */
     double y[M], f0[M], isc[M];
-    double z[3][M], w[3][M], zold[3][M];
-    double J[M][M];
+    double w[3][M];
     LT e1[M][M], e2r[M][M], e2i[M][M];
-    int p1[M], p2[M];
-    double t, h, h_lu, h_old, h_acc, err_acc, eta, theta, nprev;
+    double t, h, ih, h_old, h_acc, qerr_acc, eta, nprev;
+    unsigned p1, p2, flags;
     int phase, status, k, nsing;
-    bool first, reject, j_stale, j_at_y0, have_lu, have_old, have_acc, last;
     /* counters (paper Appendix A: f evaluations per node) */
     int nstep, naccept, nreject, nfev, njac, ndec, nsol, nnewt;
+    LdsCol<BLOCK> lds;
+
+    __device__ __forceinline__ bool has(unsigned f) const { return (flags & f) != 0u; }
+    __device__ __forceinline__ void set(unsigned f, bool v) { flags = v ? (flags | f) : (flags & ~f); }
 
     __device__ __forceinline__ void load(const Model& md, const StepParams& P,
                                          const double* __restrict__ states, int64_t n,
@@ -234,21 +266,13 @@ struct SmallCell {
         for (int r = 0; r < M; ++r) fin = fin && finite_d(y[r]) && finite_d(f0[r]);
         t = 0.0;
         h = P.fixed_steps > 0 ? P.dt / P.fixed_steps : fmin(P.h0 > 0.0 ? P.h0 : P.dt, P.dt);
-        h_lu = h_old = h_acc = err_acc = theta = nprev = 0.0;
+        h_old = h_acc = qerr_acc = nprev = 0.0;
         eta = 1.0;
         k = 0;
         nsing = 0;
-        first = true;
-        reject = false;
-        j_stale = true;
-        j_at_y0 = false;
-        have_lu = have_old = have_acc = last = false;
-        if (!fin) {
-            status = ST_NONFINITE;
-            phase = PH_IDLE;
-        } else {
-            phase = PH_START;
-        }
+        flags = F_FIRST | F_JSTALE;
+        phase = fin ? PH_START : PH_IDLE;
+        if (!fin) status = ST_NONFINITE;
     }
 
     __device__ __forceinline__ void store(double* __restrict__ states, int32_t* __restrict__ stats,
@@ -270,13 +294,12 @@ struct SmallCell {
 
     /* E1 = (gamma/h) I - J, E2 = ((alpha + i beta)/h) I - J, both factored. */
     __device__ __forceinline__ bool factor() {
-        const double ih = 1.0 / h;
         const double g = radau::GAMMA * ih, ar = radau::ALPHA * ih, bi = radau::BETA * ih;
 #pragma unroll
         for (int i = 0; i < M; ++i)
 #pragma unroll
             for (int j = 0; j < M; ++j) {
-                const double mj = -J[i][j];
+                const double mj = -lds[L::J0 + i * M + j];
                 e1[i][j] = (LT)(i == j ? g + mj : mj);
                 e2r[i][j] = (LT)(i == j ? ar + mj : mj);
                 e2i[i][j] = (LT)(i == j ? bi : 0.0);
@@ -294,67 +317,70 @@ struct SmallCell {
         if (!FIXED) {
             if (nstep >= P.max_steps) { status = ST_MAXSTEPS; phase = PH_IDLE; return; }
             if (h < P.h_min) { status = ST_HSMALL; phase = PH_IDLE; return; }
-            last = false;
-            if (t + 1.0001 * h >= P.dt) { h = P.dt - t; last = true; }
+            const bool last = t + 1.0001 * h >= P.dt;
+            if (last) {
+                const double hl = P.dt - t;
+                if (hl != h) flags &= ~F_LUOK;
+                h = hl;
+            }
+            set(F_LAST, last);
         }
+        ih = 1.0 / h;
 #pragma unroll
         for (int r = 0; r < M; ++r) isc[r] = 1.0 / (P.atol + P.rtol * __builtin_fabs(y[r]));
-        if (FIXED || j_stale) {
+        if (FIXED || has(F_JSTALE)) {
+            double J[M][M];
             md.jac(y, J);
+#pragma unroll
+            for (int i = 0; i < M; ++i)
+#pragma unroll
+                for (int j = 0; j < M; ++j) lds[L::J0 + i * M + j] = J[i][j];
             ++njac;
-            j_stale = false;
-            j_at_y0 = true;
-            have_lu = false;
+            flags = (flags & ~(F_JSTALE | F_LUOK)) | F_JATY0;
         }
-        if (FIXED || !have_lu || h != h_lu) {
+        if (FIXED || !has(F_LUOK)) {
             ++ndec;
             if (!factor()) {
-                have_lu = false;
                 if (FIXED || ++nsing >= 5) { status = ST_SINGULAR; phase = PH_IDLE; return; }
                 h *= 0.5;
                 phase = PH_START;
                 return;
             }
             nsing = 0;
-            have_lu = true;
-            h_lu = h;
+            flags |= F_LUOK;
         }
         /* Newton start: zero, or the collocation cubic of the last accepted
          * step continued to the new stage points (nodes s = -1, c1-1, c2-1, 0
-         * in units of h_old; values -z3, z1 - z3, z2 - z3, 0). */
-        if (have_old) {
+         * in units of h_old; values -z3, z1 - z3, z2 - z3, 0), then W = T^-1 Z. */
+        if (has(F_OLD)) {
             const double r = h / h_old;
             const double s1 = -1.0, s2 = radau::C1 - 1.0, s3 = radau::C2 - 1.0;
             const double cs[3] = {radau::C1 * r, radau::C2 * r, r};
-            double L[3][3];
+            double Lw[3][3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 const double s = cs[i];
-                const double d1 = s - s1, d2 = s - s2, d3 = s - s3, d4 = s; /* s - 0 */
-                L[i][0] = d2 * d3 * d4 * radau::LAG_INV0;
-                L[i][1] = d1 * d3 * d4 * radau::LAG_INV1;
-                L[i][2] = d1 * d2 * d4 * radau::LAG_INV2;
+                const double d1 = s - s1, d2 = s - s2, d3 = s - s3, d4 = s;
+                Lw[i][0] = d2 * d3 * d4 * radau::LAG_INV0;
+                Lw[i][1] = d1 * d3 * d4 * radau::LAG_INV1;
+                Lw[i][2] = d1 * d2 * d4 * radau::LAG_INV2;
             }
 #pragma unroll
             for (int q = 0; q < M; ++q) {
-                const double v0 = -zold[2][q];
-                const double v1 = zold[0][q] - zold[2][q];
-                const double v2 = zold[1][q] - zold[2][q];
-#pragma unroll
-                for (int i = 0; i < 3; ++i) z[i][q] = L[i][0] * v0 + L[i][1] * v1 + L[i][2] * v2;
+                const double z1o = lds[L::Z0 + q], z2o = lds[L::Z0 + M + q], z3o = lds[L::Z0 + 2 * M + q];
+                const double v0 = -z3o, v1 = z1o - z3o, v2 = z2o - z3o;
+                const double a = Lw[0][0] * v0 + Lw[0][1] * v1 + Lw[0][2] * v2;
+                const double b = Lw[1][0] * v0 + Lw[1][1] * v1 + Lw[1][2] * v2;
+                const double c = Lw[2][0] * v0 + Lw[2][1] * v1 + Lw[2][2] * v2;
+                w[0][q] = radau::TI11 * a + radau::TI12 * b + radau::TI13 * c;
+                w[1][q] = radau::TI21 * a + radau::TI22 * b + radau::TI23 * c;
+                w[2][q] = radau::TI31 * a + radau::TI32 * b + radau::TI33 * c;
             }
         } else {
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
-                for (int q = 0; q < M; ++q) z[i][q] = 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < M; ++q) {
-            const double a = z[0][q], b = z[1][q], c = z[2][q];
-            w[0][q] = radau::TI11 * a + radau::TI12 * b + radau::TI13 * c;
-            w[1][q] = radau::TI21 * a + radau::TI22 * b + radau::TI23 * c;
-            w[2][q] = radau::TI31 * a + radau::TI32 * b + radau::TI33 * c;
+                for (int q = 0; q < M; ++q) w[i][q] = 0.0;
         }
         k = 0;
         nprev = 0.0;
@@ -365,27 +391,43 @@ struct SmallCell {
     __device__ __forceinline__ int newton(const Model& md, const StepParams& P) {
         ++k;
         ++nnewt;
-        double F[3][M];
+        /* G = T^-1 F(y0 + Z), Z = T W, one stage at a time */
+        double G[3][M];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            double ys[M];
+            double ys[M], F[M];
 #pragma unroll
-            for (int q = 0; q < M; ++q) ys[q] = y[q] + z[i][q];
-            md.rhs(ys, F[i]);
+            for (int q = 0; q < M; ++q) {
+                const double zi = i == 0 ? radau::T11 * w[0][q] + radau::T12 * w[1][q] + radau::T13 * w[2][q]
+                                : i == 1 ? radau::T21 * w[0][q] + radau::T22 * w[1][q] + radau::T23 * w[2][q]
+                                         : w[0][q] + w[1][q]; /* row 3 of T is (1, 1, 0) */
+                ys[q] = y[q] + zi;
+            }
+            md.rhs(ys, F);
+            const double t1 = i == 0 ? radau::TI11 : i == 1 ? radau::TI12 : radau::TI13;
+            const double t2 = i == 0 ? radau::TI21 : i == 1 ? radau::TI22 : radau::TI23;
+            const double t3 = i == 0 ? radau::TI31 : i == 1 ? radau::TI32 : radau::TI33;
+#pragma unroll
+            for (int q = 0; q < M; ++q) {
+                if (i == 0) {
+                    G[0][q] = t1 * F[q];
+                    G[1][q] = t2 * F[q];
+                    G[2][q] = t3 * F[q];
+                } else {
+                    G[0][q] += t1 * F[q];
+                    G[1][q] += t2 * F[q];
+                    G[2][q] += t3 * F[q];
+                }
+            }
         }
         nfev += 3;
-        const double ih = 1.0 / h;
         const double g = radau::GAMMA * ih, al = radau::ALPHA * ih, be = radau::BETA * ih;
         LT r1[M], r2[M], r3[M];
 #pragma unroll
         for (int q = 0; q < M; ++q) {
-            const double a = F[0][q], b = F[1][q], c = F[2][q];
-            const double g1 = radau::TI11 * a + radau::TI12 * b + radau::TI13 * c;
-            const double g2 = radau::TI21 * a + radau::TI22 * b + radau::TI23 * c;
-            const double g3 = radau::TI31 * a + radau::TI32 * b + radau::TI33 * c;
-            r1[q] = (LT)(g1 - g * w[0][q]);
-            r2[q] = (LT)(g2 - al * w[1][q] + be * w[2][q]);
-            r3[q] = (LT)(g3 - be * w[1][q] - al * w[2][q]);
+            r1[q] = (LT)(G[0][q] - g * w[0][q]);
+            r2[q] = (LT)(G[1][q] - al * w[1][q] + be * w[2][q]);
+            r3[q] = (LT)(G[2][q] - be * w[1][q] - al * w[2][q]);
         }
         lu_solve_real<M, LT>(e1, p1, r1);
         lu_solve_cplx<M, LT>(e2r, e2i, p2, r2, r3);
@@ -399,36 +441,44 @@ struct SmallCell {
             w[2][q] += d3;
             const double dz1 = radau::T11 * d1 + radau::T12 * d2 + radau::T13 * d3;
             const double dz2 = radau::T21 * d1 + radau::T22 * d2 + radau::T23 * d3;
-            const double dz3 = d1 + d2; /* row 3 of T is (1, 1, 0) */
-            z[0][q] += dz1;
-            z[1][q] += dz2;
-            z[2][q] += dz3;
+            const double dz3 = d1 + d2;
             const double s1 = dz1 * isc[q], s2 = dz2 * isc[q], s3 = dz3 * isc[q];
             acc += s1 * s1 + s2 * s2 + s3 * s3;
         }
         const double nk = __builtin_sqrt(acc * (1.0 / (3 * M)));
         if (!finite_d(nk)) return NW_FAILED;
+        const double tol = P.newton_tol;
         if (k >= 2) {
+            /* theta = n_k / n_{k-1}; diverging if theta >= 0.99; eta =
+             * theta / (1 - theta); too slow if theta^(kmax-k) / (1 - theta)
+             * n_k > tol, tested as theta^(kmax-k) n_k > tol (1 - theta) since
+             * 1 - theta > 0.01 here */
             const double th = nk / nprev;
-            theta = th;
             if (th >= 0.99) return NW_FAILED;
-            eta = th / (1.0 - th);
+            const double om = 1.0 - th;
+            eta = th / om;
             double tp = 1.0;
             for (int j = 0; j < P.kmax - k; ++j) tp *= th;
-            if (tp / (1.0 - th) * nk > P.newton_tol) return NW_FAILED;
+            if (tp * nk > tol * om) return NW_FAILED;
+            set(F_KEEPJ, th <= 1e-3);
+        } else {
+            set(F_KEEPJ, true);
         }
-        if (eta * nk <= P.newton_tol) return NW_CONVERGED;
+        if (eta * nk <= tol) return NW_CONVERGED;
         nprev = nk;
         return k >= P.kmax ? NW_FAILED : NW_CONTINUE;
     }
 
     /* e = E1^{-1} [fb + (d1 z1 + d2 z2 + d3 z3)/h]; returns RMS(e/sc). */
     __device__ __forceinline__ double estimate(const double (&fb)[M], double (&e)[M]) {
-        const double ih = 1.0 / h;
+        /* d.Z = (d^T T) W */
+        constexpr double DW1 = radau::D1 * radau::T11 + radau::D2 * radau::T21 + radau::D3;
+        constexpr double DW2 = radau::D1 * radau::T12 + radau::D2 * radau::T22 + radau::D3;
+        constexpr double DW3 = radau::D1 * radau::T13 + radau::D2 * radau::T23;
         LT v[M];
 #pragma unroll
         for (int q = 0; q < M; ++q)
-            v[q] = (LT)(fb[q] + (radau::D1 * z[0][q] + radau::D2 * z[1][q] + radau::D3 * z[2][q]) * ih);
+            v[q] = (LT)(fb[q] + (DW1 * w[0][q] + DW2 * w[1][q] + DW3 * w[2][q]) * ih);
         lu_solve_real<M, LT>(e1, p1, v);
         ++nsol;
         double acc = 0.0;
@@ -449,19 +499,11 @@ struct SmallCell {
             if (outcome == NW_FAILED) { status = ST_NEWTON; phase = PH_IDLE; return; }
             ++nstep;
             ++naccept;
-#pragma unroll
-            for (int q = 0; q < M; ++q) y[q] += z[2][q];
-            md.rhs(y, f0);
-            ++nfev;
+            accept_state(md);
             bool fin = true;
 #pragma unroll
             for (int q = 0; q < M; ++q) fin = fin && finite_d(y[q]);
             if (!fin) { status = ST_NONFINITE; phase = PH_IDLE; return; }
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int q = 0; q < M; ++q) zold[i][q] = z[i][q];
-            have_old = true;
             h_old = h;
             eta = pow(fmax(eta, UROUND), 0.8);
             phase = (naccept >= P.fixed_steps) ? PH_IDLE : PH_START;
@@ -471,14 +513,14 @@ struct SmallCell {
             ++nstep;
             ++nreject;
             h *= 0.5;
-            reject = true;
-            if (!j_at_y0) j_stale = true;
+            flags = (flags | F_REJECT) & ~F_LUOK;
+            if (!has(F_JATY0)) flags |= F_JSTALE;
             phase = PH_START;
             return;
         }
         double e[M];
         double err = estimate(f0, e);
-        if (err >= 1.0 && (first || reject)) {
+        if (err >= 1.0 && (flags & (F_FIRST | F_REJECT))) {
             double ye[M], fe[M];
 #pragma unroll
             for (int q = 0; q < M; ++q) ye[q] = y[q] + e[q];
@@ -490,57 +532,82 @@ struct SmallCell {
         ++nstep;
         const double kmx = (double)P.kmax;
         const double fac = 0.9 * (2.0 * kmx + 1.0) / (2.0 * kmx + (double)k);
-        const double ratio =
-            (err == 0.0) ? 8.0 : fmin(8.0, fmax(0.2, fac / __builtin_sqrt(__builtin_sqrt(err))));
+        const double qerr = __builtin_sqrt(__builtin_sqrt(err));
+        const double ratio = (err == 0.0) ? 8.0 : fmin(8.0, fmax(0.2, fac / qerr));
         double h_new = h * ratio;
         if (err < 1.0) {
-            if (have_acc) {
+            if (has(F_ACC)) {
                 const double r2 = (err == 0.0)
                     ? 8.0
-                    : fmin(8.0, fmax(0.2, fac * (h / h_acc) * __builtin_sqrt(__builtin_sqrt(err_acc)) /
-                                              __builtin_sqrt(err)));
+                    : fmin(8.0, fmax(0.2, fac * (h / h_acc) * qerr_acc / (qerr * qerr)));
                 h_new = fmin(h_new, h * r2);
             }
+            double zs[3][M];
             double y1[M], f1[M];
 #pragma unroll
-            for (int q = 0; q < M; ++q) y1[q] = y[q] + z[2][q];
+            for (int q = 0; q < M; ++q) {
+                zs[0][q] = radau::T11 * w[0][q] + radau::T12 * w[1][q] + radau::T13 * w[2][q];
+                zs[1][q] = radau::T21 * w[0][q] + radau::T22 * w[1][q] + radau::T23 * w[2][q];
+                zs[2][q] = w[0][q] + w[1][q];
+                y1[q] = y[q] + zs[2][q];
+            }
             md.rhs(y1, f1);
             ++nfev;
             bool fin = true;
 #pragma unroll
             for (int q = 0; q < M; ++q) fin = fin && finite_d(y1[q]) && finite_d(f1[q]);
             if (!fin) { status = ST_NONFINITE; phase = PH_IDLE; return; }
-            have_acc = true;
             h_acc = h;
-            err_acc = fmax(err, 1e-2);
+            qerr_acc = __builtin_sqrt(__builtin_sqrt(fmax(err, 1e-2)));
 #pragma unroll
-            for (int q = 0; q < M; ++q) { y[q] = y1[q]; f0[q] = f1[q]; }
-            t = last ? P.dt : t + h;
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int q = 0; q < M; ++q) zold[i][q] = z[i][q];
+            for (int q = 0; q < M; ++q) {
+                y[q] = y1[q];
+                f0[q] = f1[q];
+                lds[L::Z0 + q] = zs[0][q];
+                lds[L::Z0 + M + q] = zs[1][q];
+                lds[L::Z0 + 2 * M + q] = zs[2][q];
+            }
+            t = has(F_LAST) ? P.dt : t + h;
             h_old = h;
-            have_old = true;
             eta = pow(fmax(eta, UROUND), 0.8);
             ++naccept;
-            if (reject) h_new = fmin(h_new, h);
-            first = false;
-            reject = false;
-            j_stale = !(k == 1 || theta <= 1e-3);
-            j_at_y0 = false;
-            if (!j_stale) {
+            if (has(F_REJECT)) h_new = fmin(h_new, h);
+            const bool keep_j = has(F_KEEPJ);
+            flags = (flags & ~(F_FIRST | F_REJECT | F_JATY0 | F_JSTALE)) | F_OLD | F_ACC |
+                    (keep_j ? 0u : F_JSTALE);
+            if (keep_j) {
                 const double qq = h_new / h;
                 if (qq >= 1.0 && qq <= 1.2) h_new = h;
             }
-            h = fmin(h_new, P.dt - t);
+            const double hn = fmin(h_new, P.dt - t);
+            if (hn != h) flags &= ~F_LUOK;
+            h = hn;
             phase = (t < P.dt) ? PH_START : PH_IDLE;
         } else {
             ++nreject;
-            h = first ? 0.1 * h : h_new;
-            reject = true;
+            const double hn = has(F_FIRST) ? 0.1 * h : h_new;
+            if (hn != h) flags &= ~F_LUOK;
+            h = hn;
+            flags |= F_REJECT;
             phase = PH_START;
         }
+    }
+
+    /* fixed-step accept: y += z3, f0 = f(y), keep Z for the next start */
+    __device__ __forceinline__ void accept_state(const Model& md) {
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            const double z1 = radau::T11 * w[0][q] + radau::T12 * w[1][q] + radau::T13 * w[2][q];
+            const double z2 = radau::T21 * w[0][q] + radau::T22 * w[1][q] + radau::T23 * w[2][q];
+            const double z3 = w[0][q] + w[1][q];
+            y[q] += z3;
+            lds[L::Z0 + q] = z1;
+            lds[L::Z0 + M + q] = z2;
+            lds[L::Z0 + 2 * M + q] = z3;
+        }
+        md.rhs(y, f0);
+        ++nfev;
+        flags |= F_OLD;
     }
 };
 

@@ -25,6 +25,7 @@ struct Prepared {
     int grid = 0;
     int device = 0;
     size_t param_key = 0;
+    int order = 0; /* claim-order option of the call */
 };
 
 /* Per-device state: properties, counter slots, cached parameter blocks. */
@@ -35,6 +36,10 @@ struct DevCtx {
     std::atomic<unsigned> next_slot{0};
     std::mutex mu;
     std::map<std::vector<double>, double*> params; /* key: {kind, m, block...} */
+    /* per-stream scratch for the claim order; outgrown buffers are kept
+     * (captured graphs may still reference them) */
+    std::map<hipStream_t, std::pair<void*, size_t>> order_ws;
+    std::vector<void*> retired;
 };
 constexpr unsigned kSlots = 4096;
 
@@ -45,6 +50,13 @@ DevCtx* current_ctx();
  * parameter block, select the kernel.  Returns 0 or a negative RD_E* code. */
 int prepare(double* states, int64_t n, int32_t m, double dt, double rtol, double atol,
             const rd_model* model, const rd_options* opts, int32_t* stats, Prepared* out);
+
+/* Scratch of at least `bytes` for launches on stream s (claim order). */
+void* stream_workspace(DevCtx& c, hipStream_t s, size_t bytes, int* err);
+
+/* Enqueue the claim-order kernels for a prepared persistent launch (when the
+ * options ask for it and an order kernel exists); sets pr.args.order. */
+int enqueue_order(DevCtx& c, Prepared& pr, hipStream_t s);
 
 /* Grid for a persistent kernel: resident workgroups on the device, capped by
  * the number of workgroups the cells would fill. */

@@ -25,39 +25,56 @@
 
 namespace rd {
 
-template <class Model, typename LT, bool FIXED>
-__device__ __forceinline__ void advance(SmallCell<Model, LT>& cell, const Model& md,
+/* One pass: a Newton iteration for lanes in PH_NEWTON (and the step end for
+ * the lanes whose Newton loop ended), then the step start for lanes that need
+ * one -- so a lane that ends a step starts the next one in the same pass. */
+template <class Model, typename LT, bool FIXED, int BLOCK>
+__device__ __forceinline__ void advance(SmallCell<Model, LT, BLOCK>& cell, const Model& md,
                                         const StepParams& P) {
-    if (cell.phase == PH_START) cell.template start<FIXED>(md, P);
     if (cell.phase == PH_NEWTON) {
         const int o = cell.newton(md, P);
         if (o != NW_CONTINUE) cell.template finish<FIXED>(md, P, o);
     }
+    if (cell.phase == PH_START) cell.template start<FIXED>(md, P);
 }
 
 template <class Model, typename LT, bool FIXED, int BLOCK, int WPE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_onelaunch(LaunchArgs a) {
+    using L = SmallLds<Model::M>;
+    __shared__ double sh[L::ROWS * BLOCK];
     const int64_t c = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (c >= a.n) return;
     const Model md(a.params);
-    SmallCell<Model, LT> cell;
+    SmallCell<Model, LT, BLOCK> cell;
+    cell.lds.base = sh + threadIdx.x;
     cell.load(md, a.P, a.states, a.n, c);
-    while (cell.phase != PH_IDLE) advance<Model, LT, FIXED>(cell, md, a.P);
+    while (cell.phase != PH_IDLE) advance<Model, LT, FIXED, BLOCK>(cell, md, a.P);
     cell.store(a.states, a.stats, a.n, c);
     if (cell.status != ST_OK) atomicAdd(a.nfail, 1ull);
 }
 
+/* Claim queue of one wave: a range [next, end) of positions in the claim
+ * order already reserved from the global counter.  Idle lanes take positions
+ * from it in lane order; only when it runs dry does one lane reserve a new
+ * chunk (at least kClaimChunk positions) with a single atomic. */
+constexpr unsigned kClaimChunk = 16;
+
 template <class Model, typename LT, bool FIXED, int BLOCK, int WPE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_persistent(LaunchArgs a) {
+    using L = SmallLds<Model::M>;
+    __shared__ double sh[L::ROWS * BLOCK];
     const Model md(a.params);
-    SmallCell<Model, LT> cell;
+    SmallCell<Model, LT, BLOCK> cell;
+    cell.lds.base = sh + threadIdx.x;
     cell.phase = PH_IDLE;
     cell.status = ST_OK;
     int64_t c = -1;
     bool alive = true;
     const unsigned lane = __lane_id();
+    const unsigned long long below = (1ull << lane) - 1ull;
+    unsigned long long qnext = 0, qend = 0; /* wave-uniform */
     for (;;) {
         const bool need = alive && cell.phase == PH_IDLE;
         if (need && c >= 0) {
@@ -67,16 +84,27 @@ k_persistent(LaunchArgs a) {
         }
         const unsigned long long mask = __ballot(need);
         if (mask) {
-            const int leader = __ffsll((long long)mask) - 1;
-            unsigned long long base = 0;
-            if (lane == (unsigned)leader)
-                base = atomicAdd(a.counter, (unsigned long long)__popcll(mask));
-            base = __shfl(base, leader);
+            const unsigned cnt = (unsigned)__popcll(mask);
+            const unsigned rank = (unsigned)__popcll(mask & below);
+            const unsigned long long avail = qend - qnext;
+            unsigned long long pos;
+            if (avail >= cnt) {
+                pos = qnext + rank;
+                qnext += cnt;
+            } else {
+                const unsigned take = (cnt - (unsigned)avail) > kClaimChunk
+                                          ? cnt - (unsigned)avail : kClaimChunk;
+                const int leader = __ffsll((long long)mask) - 1;
+                unsigned long long base = 0;
+                if (lane == (unsigned)leader) base = atomicAdd(a.counter, (unsigned long long)take);
+                base = __shfl(base, leader);
+                pos = rank < avail ? qnext + rank : base + (rank - avail);
+                qnext = base + (cnt - avail);
+                qend = base + take;
+            }
             if (need) {
-                const unsigned rank = __popcll(mask & ((1ull << lane) - 1ull));
-                const int64_t idx = (int64_t)(base + rank);
-                if (idx < a.n) {
-                    c = idx;
+                if (pos < (unsigned long long)a.n) {
+                    c = a.order ? (int64_t)a.order[pos] : (int64_t)pos;
                     cell.load(md, a.P, a.states, a.n, c);
                 } else {
                     alive = false;
@@ -84,7 +112,7 @@ k_persistent(LaunchArgs a) {
             }
         }
         if (__ballot(alive) == 0ull) break;
-        advance<Model, LT, FIXED>(cell, md, a.P);
+        advance<Model, LT, FIXED, BLOCK>(cell, md, a.P);
     }
 }
 
@@ -133,10 +161,12 @@ static const KernelEntry g_small_table[] = {
     RD_MODEL_SET(K_OREG, Oregonator, 3, "oregonator"),
     /* tuning variants: block size and waves-per-SIMD hint */
     RD_PERS(K_OREG, Oregonator, 3, 0, double, false, 2, 128, 1, "oregonator.fp64.persistent.b128"),
-    RD_PERS(K_OREG, Oregonator, 3, 0, double, false, 3, 256, 2, "oregonator.fp64.persistent.b256.w2"),
+    RD_PERS(K_OREG, Oregonator, 3, 0, double, false, 3, 256, 3, "oregonator.fp64.persistent.b256.w3"),
+    RD_PERS(K_OREG, Oregonator, 3, 0, double, false, 5, 256, 4, "oregonator.fp64.persistent.b256.w4"),
     RD_PERS(K_OREG, Oregonator, 3, 0, double, false, 4, 64, 1, "oregonator.fp64.persistent.b64"),
     RD_PERS(K_OREG, Oregonator, 3, 1, float, false, 2, 128, 1, "oregonator.mixed.persistent.b128"),
-    RD_PERS(K_OREG, Oregonator, 3, 1, float, false, 3, 256, 2, "oregonator.mixed.persistent.b256.w2"),
+    RD_PERS(K_OREG, Oregonator, 3, 1, float, false, 3, 256, 3, "oregonator.mixed.persistent.b256.w3"),
+    RD_PERS(K_OREG, Oregonator, 3, 1, float, false, 5, 256, 4, "oregonator.mixed.persistent.b256.w4"),
     RD_PERS(K_OREG, Oregonator, 3, 1, float, false, 4, 64, 1, "oregonator.mixed.persistent.b64"),
     RD_MODEL_SET(K_ROB, Robertson, 3, "robertson"),
     RD_MODEL_SET(K_NAG, Nagumo, 1, "nagumo"),

@@ -16,6 +16,7 @@ struct StepParams {
 
 struct LaunchArgs {
     double* states;                 /* [m][n] device, in place                  */
+    const int32_t* order;           /* claim order (persistent), or null        */
     int32_t* stats;                 /* [9][n] device or null                    */
     const double* params;           /* device parameter block (pre-processed)  */
     int64_t n;
@@ -39,6 +40,13 @@ struct KernelEntry {
     launch_fn launch;
     const void* func;   /* for occupancy queries                        */
 };
+
+/* Longest-first claim order: launches the cost-bucket, scan and scatter
+ * kernels that write order[n] (cell indices, most expensive estimate first).
+ * ws must hold order_workspace_bytes(n) bytes. */
+typedef hipError_t (*order_fn)(const LaunchArgs&, void* ws, int32_t* order, hipStream_t);
+size_t order_workspace_bytes(int64_t n);
+order_fn find_order_fn(int kind, int m);
 
 /* All kernels compiled into the library. */
 const KernelEntry* kernel_table(int* count);

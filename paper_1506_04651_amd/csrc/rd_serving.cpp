@@ -132,14 +132,17 @@ static bool launch_request(rd_session* s, Request* r) {
     const size_t sbytes = (size_t)n * r->m * sizeof(double);
     double* a_states = (double*)(s->arena_base + r->off);
     int32_t* a_stats = r->user_stats ? (int32_t*)(s->arena_base + r->off + align256(sbytes)) : nullptr;
-    LaunchArgs a = r->pr.args;
-    a.states = a_states;
-    a.stats = a_stats;
-    a.counter = s->counters + 2 * r->slot;
-    a.nfail = a.counter + 1;
+    Prepared pr = r->pr;
+    pr.args.states = a_states;
+    pr.args.stats = a_stats;
+    pr.args.counter = s->counters + 2 * r->slot;
+    pr.args.nfail = pr.args.counter + 1;
     if (hipMemcpyAsync(a_states, r->user_states, sbytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return false;
+    DevCtx* ctx = current_ctx();
+    if (!ctx || enqueue_order(*ctx, pr, st) != 0) return false;
+    const LaunchArgs& a = pr.args;
     if (launch_reset(a.counter, 2, st) != hipSuccess) return false;
-    if (r->pr.entry->launch(a, r->pr.grid, st) != hipSuccess) return false;
+    if (pr.entry->launch(a, pr.grid, st) != hipSuccess) return false;
     if (hipMemcpyAsync(r->user_states, a_states, sbytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return false;
     if (a_stats &&
         hipMemcpyAsync(r->user_stats, a_stats, (size_t)n * RD_NSTATS * sizeof(int32_t),

@@ -198,3 +198,17 @@ def test_graph_replay_matches_eager(rd):
         # unrelated eager work between replays
         torch.cuda.synchronize()
         _ = (u0 * 2.0).sum().item()
+
+
+def test_claim_order_does_not_change_results(rd):
+    """Longest-first claim order (cost-bucket sort) vs storage order: every
+    cell's arithmetic is the same, so results and counters are bitwise equal."""
+    w = W.oregonator_2d()
+    say("claim order 1 vs 0, n", w.n)
+    a, sa, _ = run_gpu(rd, w, order=1)
+    b, sb, _ = run_gpu(rd, w, order=0)
+    assert np.array_equal(a, b) and np.array_equal(sa, sb)
+    say("claim order, mixed precision")
+    a, sa, _ = run_gpu(rd, w, order=1, precision=1)
+    b, sb, _ = run_gpu(rd, w, order=0, precision=1, schedule=1)
+    assert np.array_equal(a, b) and np.array_equal(sa, sb)
