@@ -39,7 +39,7 @@ namespace rd {
 
 enum : int { ST_OK = 0, ST_MAXSTEPS = 1, ST_HSMALL = 2, ST_SINGULAR = 3,
              ST_NONFINITE = 4, ST_NEWTON = 5 };
-enum : int { PH_IDLE = 0, PH_START = 1, PH_NEWTON = 2 };
+enum : int { PH_IDLE = 0, PH_START = 1, PH_NEWTON = 2, PH_END = 3 };
 enum : int { NW_CONTINUE = 0, NW_CONVERGED = 1, NW_FAILED = 2 };
 
 /* flag bits */
@@ -244,7 +244,7 @@ struct SmallCell {
     LT e1[M][M], e2r[M][M], e2i[M][M];
     double t, h, ih, h_old, h_acc, qerr_acc, eta, nprev;
     unsigned p1, p2, flags;
-    int phase, status, k, nsing;
+    int phase, status, k, nsing, outcome;
     /* counters (paper Appendix A: f evaluations per node) */
     int nstep, naccept, nreject, nfev, njac, ndec, nsol, nnewt;
     LdsCol<BLOCK> lds;

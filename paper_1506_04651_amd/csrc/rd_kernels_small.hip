@@ -25,20 +25,36 @@
 
 namespace rd {
 
-/* One pass: a Newton iteration for lanes in PH_NEWTON (and the step end for
- * the lanes whose Newton loop ended), then the step start for lanes that need
- * one -- so a lane that ends a step starts the next one in the same pass. */
-template <class Model, typename LT, bool FIXED, int BLOCK>
+/* One pass of the scheduling loop.  Lanes in PH_NEWTON take one Newton
+ * iteration; a lane whose Newton loop ends moves to PH_END.  The step-end
+ * block (error estimate, control) and the step-start block (Jacobian,
+ * factorization, start values) together cost about three Newton iterations
+ * and run with only the lanes that need them active, so they are batched:
+ * they run once at least FSMIN lanes of the wave wait for them, or when no
+ * lane is left iterating.  FSMIN = 1 runs them every pass.  Batching delays
+ * individual lanes but never changes what a cell computes. */
+template <class Model, typename LT, bool FIXED, int BLOCK, int FSMIN>
 __device__ __forceinline__ void advance(SmallCell<Model, LT, BLOCK>& cell, const Model& md,
                                         const StepParams& P) {
     if (cell.phase == PH_NEWTON) {
         const int o = cell.newton(md, P);
-        if (o != NW_CONTINUE) cell.template finish<FIXED>(md, P, o);
+        if (o != NW_CONTINUE) {
+            cell.outcome = o;
+            cell.phase = PH_END;
+        }
     }
+    const bool waits = cell.phase == PH_END || cell.phase == PH_START;
+    if (FSMIN > 1) {
+        const unsigned long long wmask = __ballot(waits);
+        if (wmask == 0ull) return;
+        if ((unsigned)__popcll(wmask) < (unsigned)FSMIN && __ballot(cell.phase == PH_NEWTON) != 0ull)
+            return;
+    }
+    if (cell.phase == PH_END) cell.template finish<FIXED>(md, P, cell.outcome);
     if (cell.phase == PH_START) cell.template start<FIXED>(md, P);
 }
 
-template <class Model, typename LT, bool FIXED, int BLOCK, int WPE>
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_onelaunch(LaunchArgs a) {
     using L = SmallLds<Model::M>;
@@ -49,7 +65,7 @@ k_onelaunch(LaunchArgs a) {
     SmallCell<Model, LT, BLOCK> cell;
     cell.lds.base = sh + threadIdx.x;
     cell.load(md, a.P, a.states, a.n, c);
-    while (cell.phase != PH_IDLE) advance<Model, LT, FIXED, BLOCK>(cell, md, a.P);
+    while (cell.phase != PH_IDLE) advance<Model, LT, FIXED, BLOCK, FSMIN>(cell, md, a.P);
     cell.store(a.states, a.stats, a.n, c);
     if (cell.status != ST_OK) atomicAdd(a.nfail, 1ull);
 }
@@ -60,7 +76,7 @@ k_onelaunch(LaunchArgs a) {
  * chunk (at least kClaimChunk positions) with a single atomic. */
 constexpr unsigned kClaimChunk = 16;
 
-template <class Model, typename LT, bool FIXED, int BLOCK, int WPE>
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_persistent(LaunchArgs a) {
     using L = SmallLds<Model::M>;
@@ -112,7 +128,7 @@ k_persistent(LaunchArgs a) {
             }
         }
         if (__ballot(alive) == 0ull) break;
-        advance<Model, LT, FIXED, BLOCK>(cell, md, a.P);
+        advance<Model, LT, FIXED, BLOCK, FSMIN>(cell, md, a.P);
     }
 }
 
@@ -126,48 +142,56 @@ hipError_t launch_reset(unsigned long long* p, int n, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <class Model, typename LT, bool FIXED, int BLOCK, int WPE>
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN>
 hipError_t launch_one(const LaunchArgs& a, int grid, hipStream_t s) {
     if (grid <= 0) grid = (int)((a.n + BLOCK - 1) / BLOCK);
-    hipLaunchKernelGGL((k_onelaunch<Model, LT, FIXED, BLOCK, WPE>), dim3(grid), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL((k_onelaunch<Model, LT, FIXED, BLOCK, WPE, FSMIN>), dim3(grid), dim3(BLOCK), 0,
+                       s, a);
     return hipGetLastError();
 }
 
-template <class Model, typename LT, bool FIXED, int BLOCK, int WPE>
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN>
 hipError_t launch_pers(const LaunchArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_persistent<Model, LT, FIXED, BLOCK, WPE>), dim3(grid), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL((k_persistent<Model, LT, FIXED, BLOCK, WPE, FSMIN>), dim3(grid), dim3(BLOCK), 0,
+                       s, a);
     return hipGetLastError();
 }
 
-#define RD_ONE(KIND, MODEL, M, PREC, LT, FIXED, VAR, BLOCK, WPE, NAME)                          \
-    {KIND, M, PREC, 1, FIXED, VAR, BLOCK, BLOCK, NAME, &launch_one<MODEL, LT, FIXED, BLOCK, WPE>, \
-     (const void*)&k_onelaunch<MODEL, LT, FIXED, BLOCK, WPE>}
-#define RD_PERS(KIND, MODEL, M, PREC, LT, FIXED, VAR, BLOCK, WPE, NAME)                          \
-    {KIND, M, PREC, 0, FIXED, VAR, BLOCK, BLOCK, NAME, &launch_pers<MODEL, LT, FIXED, BLOCK, WPE>, \
-     (const void*)&k_persistent<MODEL, LT, FIXED, BLOCK, WPE>}
+#define RD_ONE(KIND, MODEL, M, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, NAME)                       \
+    {KIND, M, PREC, 1, FIXED, VAR, BLOCK, BLOCK, NAME,                                          \
+     &launch_one<MODEL, LT, FIXED, BLOCK, WPE, FS>,                                             \
+     (const void*)&k_onelaunch<MODEL, LT, FIXED, BLOCK, WPE, FS>}
+#define RD_PERS(KIND, MODEL, M, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, NAME)                      \
+    {KIND, M, PREC, 0, FIXED, VAR, BLOCK, BLOCK, NAME,                                          \
+     &launch_pers<MODEL, LT, FIXED, BLOCK, WPE, FS>,                                            \
+     (const void*)&k_persistent<MODEL, LT, FIXED, BLOCK, WPE, FS>}
 
 /* model kinds (same numbering as the public header) */
 enum { K_OREG = 1, K_KIN = 2, K_NAG = 3, K_LIN = 4, K_ROB = 5 };
 
-#define RD_MODEL_SET(KIND, MODEL, M, TAG)                                                   \
-    RD_ONE(KIND, MODEL, M, 0, double, false, 1, 256, 1, TAG ".fp64.onelaunch.b256"),        \
-    RD_ONE(KIND, MODEL, M, 1, float, false, 1, 256, 1, TAG ".mixed.onelaunch.b256"),        \
-    RD_PERS(KIND, MODEL, M, 0, double, false, 1, 256, 1, TAG ".fp64.persistent.b256"),      \
-    RD_PERS(KIND, MODEL, M, 1, float, false, 1, 256, 1, TAG ".mixed.persistent.b256"),      \
-    RD_ONE(KIND, MODEL, M, 0, double, true, 1, 256, 1, TAG ".fp64.onelaunch.fixed"),        \
-    RD_PERS(KIND, MODEL, M, 0, double, true, 1, 256, 1, TAG ".fp64.persistent.fixed")
+#define RD_MODEL_SET(KIND, MODEL, M, TAG)                                                     \
+    RD_ONE(KIND, MODEL, M, 0, double, false, 1, 256, 1, 1, TAG ".fp64.onelaunch.b256"),       \
+    RD_ONE(KIND, MODEL, M, 1, float, false, 1, 256, 1, 1, TAG ".mixed.onelaunch.b256"),       \
+    RD_PERS(KIND, MODEL, M, 0, double, false, 1, 128, 1, 32, TAG ".fp64.persistent.b128.fs32"), \
+    RD_PERS(KIND, MODEL, M, 1, float, false, 1, 128, 1, 32, TAG ".mixed.persistent.b128.fs32"), \
+    RD_ONE(KIND, MODEL, M, 0, double, true, 1, 256, 1, 1, TAG ".fp64.onelaunch.fixed"),       \
+    RD_PERS(KIND, MODEL, M, 0, double, true, 1, 256, 1, 1, TAG ".fp64.persistent.fixed")
+
+#define RD_TUNE_SET(KIND, MODEL, M, PREC, LT, TAG)                                            \
+    RD_PERS(KIND, MODEL, M, PREC, LT, false, 2, 128, 1, 1, TAG ".persistent.b128.fs1"),       \
+    RD_PERS(KIND, MODEL, M, PREC, LT, false, 3, 128, 1, 24, TAG ".persistent.b128.fs24"),     \
+    RD_PERS(KIND, MODEL, M, PREC, LT, false, 4, 128, 1, 40, TAG ".persistent.b128.fs40"),     \
+    RD_PERS(KIND, MODEL, M, PREC, LT, false, 5, 128, 1, 48, TAG ".persistent.b128.fs48"),     \
+    RD_PERS(KIND, MODEL, M, PREC, LT, false, 6, 128, 1, 56, TAG ".persistent.b128.fs56"),     \
+    RD_PERS(KIND, MODEL, M, PREC, LT, false, 7, 256, 1, 40, TAG ".persistent.b256.fs40"),     \
+    RD_PERS(KIND, MODEL, M, PREC, LT, false, 8, 64, 1, 40, TAG ".persistent.b64.fs40"),       \
+    RD_ONE(KIND, MODEL, M, PREC, LT, false, 2, 256, 1, 16, TAG ".onelaunch.b256.fs16"),       \
+    RD_ONE(KIND, MODEL, M, PREC, LT, false, 3, 256, 1, 32, TAG ".onelaunch.b256.fs32")
 
 static const KernelEntry g_small_table[] = {
     RD_MODEL_SET(K_OREG, Oregonator, 3, "oregonator"),
-    /* tuning variants: block size and waves-per-SIMD hint */
-    RD_PERS(K_OREG, Oregonator, 3, 0, double, false, 2, 128, 1, "oregonator.fp64.persistent.b128"),
-    RD_PERS(K_OREG, Oregonator, 3, 0, double, false, 3, 256, 3, "oregonator.fp64.persistent.b256.w3"),
-    RD_PERS(K_OREG, Oregonator, 3, 0, double, false, 5, 256, 4, "oregonator.fp64.persistent.b256.w4"),
-    RD_PERS(K_OREG, Oregonator, 3, 0, double, false, 4, 64, 1, "oregonator.fp64.persistent.b64"),
-    RD_PERS(K_OREG, Oregonator, 3, 1, float, false, 2, 128, 1, "oregonator.mixed.persistent.b128"),
-    RD_PERS(K_OREG, Oregonator, 3, 1, float, false, 3, 256, 3, "oregonator.mixed.persistent.b256.w3"),
-    RD_PERS(K_OREG, Oregonator, 3, 1, float, false, 5, 256, 4, "oregonator.mixed.persistent.b256.w4"),
-    RD_PERS(K_OREG, Oregonator, 3, 1, float, false, 4, 64, 1, "oregonator.mixed.persistent.b64"),
+    RD_TUNE_SET(K_OREG, Oregonator, 3, 0, double, "oregonator.fp64"),
+    RD_TUNE_SET(K_OREG, Oregonator, 3, 1, float, "oregonator.mixed"),
     RD_MODEL_SET(K_ROB, Robertson, 3, "robertson"),
     RD_MODEL_SET(K_NAG, Nagumo, 1, "nagumo"),
     RD_MODEL_SET(K_LIN, Linear<1>, 1, "linear1"),
