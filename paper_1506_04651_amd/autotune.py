@@ -62,6 +62,8 @@ def tune(states0, dt, rtol, atol, kind, params, precision=FP64, schedule=PERSIST
     res = {"ms": {}, "names": {}, "rejected": []}
     ref = None
     for v in range(1, nv + 1):
+        if api.variant_name(kind, m, precision, schedule, v) is None:
+            continue
         ms, out = time_variant(states0, dt, rtol, atol, kind, params, precision, schedule, v, reps)
         name = api.variant_name(kind, m, precision, schedule, v)
         if ref is None:

@@ -25,10 +25,15 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=o
          "-Wall", "-Wno-unused-result", "-I", INCLUDE, "-I", CSRC]
 
 
+# the 16-lane group kernels unroll 16-step LU loops completely; the default
+# pragma threshold would stop short and leave the cell state in scratch
+EXTRA = {"rd_kernels_group.hip": ["-mllvm", "-pragma-unroll-threshold=200000"]}
+
+
 def _compile(src, verbose):
     path = os.path.join(CSRC, src)
     obj = os.path.join(BUILD, src + ".o")
-    cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", path, "-o", obj]
+    cmd = [HIPCC] + FLAGS + EXTRA.get(src, []) + ["-x", "hip", "-c", path, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -74,6 +74,9 @@ static int default_variant(int kind, int m, int precision, int schedule) {
 
 const KernelEntry* find_kernel(int kind, int m, int precision, int schedule, int fixed,
                                int variant) {
+    /* kinetics and linear models with 5..16 species run on the 16-lane group
+     * kernels, registered under m = 16 */
+    if ((kind == RD_KINETICS || kind == RD_LINEAR) && m > 4 && m <= RD_MAX_M) m = 16;
     if (fixed) variant = 1;
     else if (variant <= 0) variant = default_variant(kind, m, precision, schedule);
     for (const KernelEntry& e : all_kernels())
@@ -171,7 +174,7 @@ int persistent_grid(const DevCtx& c, const KernelEntry* e, int64_t n) {
         per_cu < 1)
         per_cu = 1;
     const int64_t resident = (int64_t)per_cu * c.cu_count;
-    const int64_t needed = (n + e->block - 1) / e->block;
+    const int64_t needed = (n + e->cells_per_block - 1) / e->cells_per_block;
     int64_t g = needed < resident ? needed : resident;
     if (g < 1) g = 1;
     return (int)g;
@@ -264,7 +267,7 @@ void make_step_params(double dt, double rtol, double atol, const rd_options& o, 
     P->max_steps = o.max_steps;
     P->kmax = o.newton_max;
     P->fixed_steps = o.fixed_steps;
-    P->pad = 0;
+    P->m = 0;
 }
 
 static bool options_valid(const rd_options& o) {
@@ -305,6 +308,7 @@ int prepare(double* states, int64_t n, int32_t m, double dt, double rtol, double
     out->entry = e;
     out->order = o.order;
     make_step_params(dt, rtol, atol, o, &out->args.P);
+    out->args.P.m = m;
     out->args.states = states;
     out->args.stats = stats;
     out->args.n = n;
@@ -316,8 +320,9 @@ int prepare(double* states, int64_t n, int32_t m, double dt, double rtol, double
     const double* dp = device_params(*c, model->kind, m, block, &err);
     if (!dp) return err ? err : RD_EDEVICE;
     out->args.params = dp;
-    out->grid = e->schedule == RD_PERSISTENT ? persistent_grid(*c, e, n)
-                                             : (int)((n + e->block - 1) / e->block);
+    out->grid = e->schedule == RD_PERSISTENT
+                    ? persistent_grid(*c, e, n)
+                    : (int)((n + e->cells_per_block - 1) / e->cells_per_block);
     return 0;
 }
 

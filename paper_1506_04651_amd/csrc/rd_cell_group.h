@@ -1,0 +1,526 @@
+/*
+ * rd_cell_group.h -- Radau5 for one cell held by a 16-lane group (m <= 16).
+ *
+ * Same method and the same decisions as the one-lane engine (rd_cell_small.h):
+ * 3-stage Radau IIA, simplified Newton on the transformed stage system with
+ * E1 = (gamma/h) I - J and E2 = ((alpha + i beta)/h) I - J, the error estimate
+ * filtered through E1, classical + predictive step control (Hairer & Wanner,
+ * §IV.8; paper §1 footnote and Appendix A).  Here lane q of the group owns
+ * component q of every vector and row q of every matrix:
+ *
+ *  - f(u): u_j reaches every lane of the group by DPP row broadcast; the
+ *    model's rows (shared by all cells) are read from LDS.
+ *  - LU with partial pivoting across lanes: at column k the group finds the
+ *    largest |a_ik| (i >= k) by a butterfly max; rows are exchanged between
+ *    lanes only when that beats the diagonal (the exchange is skipped for the
+ *    whole wave when no group needs it), and row k is broadcast by DPP to the
+ *    lanes below it.  After factorization lane k holds the k-th pivot row,
+ *    and `org` records which original row it came from (to permute the RHS).
+ *  - triangular solves: 2 x m broadcast steps (forward, then backward).
+ *  - norms: butterfly sums, bitwise identical in all lanes, so every lane of
+ *    the group takes the same control decisions; the per-cell scalars (t, h,
+ *    flags, counters) are replicated in the 16 lanes.
+ *
+ * Lanes q >= M (when m < 16) hold zero rows and zero vectors and never take
+ * part in pivoting, so they do not change any result.
+ */
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rd_constants.h"
+#include "rd_group.h"
+#include "rd_launch.h"
+#include "rd_cell_small.h" /* status / phase / flag enums, UROUND, finite_d */
+
+namespace rd {
+
+__device__ __forceinline__ float absv(float x) { return __builtin_fabsf(x); }
+__device__ __forceinline__ double absv(double x) { return __builtin_fabs(x); }
+
+/* LDS table of the model, zero padded to 16 x 16: row q holds K[q][0..16)
+ * then G[q][0..16); the stride is padded so the 16 rows fall in different
+ * banks. */
+struct GroupTable {
+    static constexpr int STRIDE = 2 * kGroup + 2;
+    static constexpr int DOUBLES = kGroup * STRIDE;
+};
+
+/* f_i = sum_j K_ij u_j - u_i sum_k G_ik u_k; J_ij = K_ij - u_i G_ij - d_ij (G u)_i */
+struct GroupKinetics {
+    static constexpr bool HAS_G = true;
+};
+/* f = K u; J = K */
+struct GroupLinear {
+    static constexpr bool HAS_G = false;
+};
+
+template <class Model, typename LT>
+struct GroupCell {
+    static constexpr int M = kGroup; /* loops run over the 16 lanes; rows >= m are zero */
+    static constexpr bool HAS_G = Model::HAS_G;
+    int m;           /* species (run time, 1..16) */
+    double inv3m, invm;
+
+    /* lane-q components */
+    double y, f0, isc, w1, w2, w3, z1o, z2o, z3o, uJ, gJ;
+    LT e1[M], e2r[M], e2i[M];
+    int org1, org2;
+    const double* kg; /* LDS row q: K then G */
+    int q;
+    bool act;         /* q < m */
+    /* per-cell scalars, replicated across the group */
+    double t, h, ih, h_old, h_acc, qerr_acc, eta, nprev;
+    unsigned flags;
+    int phase, status, k, nsing, outcome;
+    int nstep, naccept, nreject, nfev, njac, ndec, nsol, nnewt;
+
+    __device__ __forceinline__ bool has(unsigned f) const { return (flags & f) != 0u; }
+    __device__ __forceinline__ void set(unsigned f, bool v) { flags = v ? (flags | f) : (flags & ~f); }
+
+    /* f_q(u) and (G u)_q; every lane of the group must be active */
+    __device__ __forceinline__ double rhs(double u, double& gu) const {
+        double lin = 0.0, loss = 0.0;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const double uj = bcast_dyn(u, j);
+            lin += kg[j] * uj;
+            if (HAS_G) loss += kg[M + j] * uj;
+        }
+        gu = loss;
+        return HAS_G ? lin - u * loss : lin;
+    }
+
+    __device__ __forceinline__ void load(const StepParams& P, const double* __restrict__ states,
+                                         int64_t n, int64_t c) {
+        y = act ? states[(int64_t)q * n + c] : 0.0;
+        nstep = naccept = nreject = njac = ndec = nsol = nnewt = 0;
+        nfev = 1;
+        double gu;
+        f0 = rhs(y, gu);
+        status = ST_OK;
+        const bool fin = grp_bits(finite_d(y) && finite_d(f0)) == 0xFFFFu;
+        t = 0.0;
+        h = P.fixed_steps > 0 ? P.dt / P.fixed_steps : fmin(P.h0 > 0.0 ? P.h0 : P.dt, P.dt);
+        h_old = h_acc = qerr_acc = nprev = 0.0;
+        eta = 1.0;
+        k = 0;
+        nsing = 0;
+        flags = F_FIRST | F_JSTALE;
+        w1 = 0.0;
+        w2 = 0.0;
+        w3 = 0.0;
+        z1o = 0.0;
+        z2o = 0.0;
+        z3o = 0.0;
+        phase = fin ? PH_START : PH_IDLE;
+        if (!fin) status = ST_NONFINITE;
+    }
+
+    __device__ __forceinline__ void store(double* __restrict__ states, int32_t* __restrict__ stats,
+                                          int64_t n, int64_t c) const {
+        if (act) states[(int64_t)q * n + c] = y;
+        if (stats && q == 0) {
+            stats[0 * n + c] = status;
+            stats[1 * n + c] = nstep;
+            stats[2 * n + c] = naccept;
+            stats[3 * n + c] = nreject;
+            stats[4 * n + c] = nfev;
+            stats[5 * n + c] = njac;
+            stats[6 * n + c] = ndec;
+            stats[7 * n + c] = nsol;
+            stats[8 * n + c] = nnewt;
+        }
+    }
+
+    /* J_qj at the stored Jacobian point (uJ, gJ = (G u)_q at that point) */
+    __device__ __forceinline__ double jac(int j) const {
+        double v = kg[j];
+        if (HAS_G) {
+            v -= uJ * kg[M + j];
+            if (j == q) v -= gJ;
+        }
+        return act ? v : 0.0;
+    }
+
+    /* ---- LU of E1 (real) with partial pivoting across the group ---- */
+    __device__ __forceinline__ bool lu_real(LT (&a)[M], int& org) {
+        bool ok = true;
+        org = q;
+#pragma unroll
+        for (int kk = 0; kk < M; ++kk) {
+            if (kk < m) {
+                const bool below = act && q > kk;
+                const LT mag = below ? absv(a[kk]) : LT(0);
+                const LT gmax = grp_max(mag);
+                LT akk = bcast_dyn(a[kk], kk);
+                const bool need = gmax > absv(akk);
+                if (__ballot(need) != 0ull) {
+                    const unsigned cand = grp_bits(below && mag == gmax);
+                    const int p = (need && cand) ? __ffs(cand) - 1 : kk;
+                    const int src = (q == kk) ? p : (q == p ? kk : q);
+#pragma unroll
+                    for (int j = 0; j < M; ++j) a[j] = grp_shfl(a[j], src);
+                    org = grp_shfl(org, src);
+                    akk = bcast_dyn(a[kk], kk);
+                }
+                ok = ok && (akk != LT(0));
+                const LT inv = LT(1) / akk;
+                const LT l = a[kk] * inv;
+                a[kk] = (q == kk) ? inv : (below ? l : a[kk]);
+#pragma unroll
+                for (int j = kk + 1; j < M; ++j) {
+                    const LT rkj = bcast_dyn(a[j], kk);
+                    a[j] = below ? a[j] - l * rkj : a[j];
+                }
+            }
+        }
+        return ok;
+    }
+
+    /* ---- LU of E2 (complex) ---- */
+    __device__ __forceinline__ bool lu_cplx(LT (&ar)[M], LT (&ai)[M], int& org) {
+        bool ok = true;
+        org = q;
+#pragma unroll
+        for (int kk = 0; kk < M; ++kk) {
+            if (kk < m) {
+                const bool below = act && q > kk;
+                const LT mag = below ? ar[kk] * ar[kk] + ai[kk] * ai[kk] : LT(0);
+                const LT gmax = grp_max(mag);
+                LT pr = bcast_dyn(ar[kk], kk), pi = bcast_dyn(ai[kk], kk);
+                const bool need = gmax > pr * pr + pi * pi;
+                if (__ballot(need) != 0ull) {
+                    const unsigned cand = grp_bits(below && mag == gmax);
+                    const int p = (need && cand) ? __ffs(cand) - 1 : kk;
+                    const int src = (q == kk) ? p : (q == p ? kk : q);
+#pragma unroll
+                    for (int j = 0; j < M; ++j) {
+                        ar[j] = grp_shfl(ar[j], src);
+                        ai[j] = grp_shfl(ai[j], src);
+                    }
+                    org = grp_shfl(org, src);
+                    pr = bcast_dyn(ar[kk], kk);
+                    pi = bcast_dyn(ai[kk], kk);
+                }
+                ok = ok && !(pr == LT(0) && pi == LT(0));
+                const LT rn = LT(1) / (pr * pr + pi * pi);
+                const LT ir = pr * rn, ii = -pi * rn;
+                const LT xr = ar[kk], xi = ai[kk];
+                const LT lr = xr * ir - xi * ii, li = xr * ii + xi * ir;
+                ar[kk] = (q == kk) ? ir : (below ? lr : xr);
+                ai[kk] = (q == kk) ? ii : (below ? li : xi);
+#pragma unroll
+                for (int j = kk + 1; j < M; ++j) {
+                    const LT ur = bcast_dyn(ar[j], kk), ui = bcast_dyn(ai[j], kk);
+                    const LT nr = ar[j] - (lr * ur - li * ui);
+                    const LT ni = ai[j] - (lr * ui + li * ur);
+                    ar[j] = below ? nr : ar[j];
+                    ai[j] = below ? ni : ai[j];
+                }
+            }
+        }
+        return ok;
+    }
+
+    /* solve E1 x = b; lane q holds b_q on entry, x_q on return */
+    __device__ __forceinline__ LT solve_real(LT b) const {
+        b = grp_shfl(b, org1);
+#pragma unroll
+        for (int kk = 0; kk < M - 1; ++kk) {
+            if (kk < m - 1) {
+                const LT yk = bcast_dyn(b, kk);
+                b = (act && q > kk) ? b - e1[kk] * yk : b;
+            }
+        }
+#pragma unroll
+        for (int kk = M - 1; kk >= 0; --kk) {
+            if (kk < m) {
+                b = (q == kk) ? b * e1[kk] : b;
+                const LT xk = bcast_dyn(b, kk);
+                b = (q < kk) ? b - e1[kk] * xk : b;
+            }
+        }
+        return act ? b : LT(0);
+    }
+
+    __device__ __forceinline__ void solve_cplx(LT& br, LT& bi) const {
+        br = grp_shfl(br, org2);
+        bi = grp_shfl(bi, org2);
+#pragma unroll
+        for (int kk = 0; kk < M - 1; ++kk) {
+            if (kk < m - 1) {
+                const LT yr = bcast_dyn(br, kk), yi = bcast_dyn(bi, kk);
+                const LT lr = e2r[kk], li = e2i[kk];
+                const bool u = act && q > kk;
+                const LT nr = br - (lr * yr - li * yi), ni = bi - (lr * yi + li * yr);
+                br = u ? nr : br;
+                bi = u ? ni : bi;
+            }
+        }
+#pragma unroll
+        for (int kk = M - 1; kk >= 0; --kk) {
+            if (kk < m) {
+                const LT dr = e2r[kk], di = e2i[kk];
+                const bool d = q == kk;
+                const LT sr = br, si = bi;
+                br = d ? sr * dr - si * di : sr;
+                bi = d ? sr * di + si * dr : si;
+                const LT xr = bcast_dyn(br, kk), xi = bcast_dyn(bi, kk);
+                const bool u = q < kk;
+                const LT nr = br - (dr * xr - di * xi), ni = bi - (dr * xi + di * xr);
+                br = u ? nr : br;
+                bi = u ? ni : bi;
+            }
+        }
+        br = act ? br : LT(0);
+        bi = act ? bi : LT(0);
+    }
+
+    __device__ __forceinline__ bool factor() {
+        const double g = radau::GAMMA * ih, ar = radau::ALPHA * ih, bi = radau::BETA * ih;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const double mj = -jac(j);
+            const bool d = act && j == q;
+            e1[j] = (LT)(d ? g + mj : mj);
+            e2r[j] = (LT)(d ? ar + mj : mj);
+            e2i[j] = (LT)(d ? bi : 0.0);
+        }
+        const bool ok1 = lu_real(e1, org1);
+        const bool ok2 = lu_cplx(e2r, e2i, org2);
+        return ok1 && ok2;
+    }
+
+    template <bool FIXED>
+    __device__ __forceinline__ void start(const StepParams& P) {
+        if (!FIXED) {
+            if (nstep >= P.max_steps) { status = ST_MAXSTEPS; phase = PH_IDLE; return; }
+            if (h < P.h_min) { status = ST_HSMALL; phase = PH_IDLE; return; }
+            const bool last = t + 1.0001 * h >= P.dt;
+            if (last) {
+                const double hl = P.dt - t;
+                if (hl != h) flags &= ~F_LUOK;
+                h = hl;
+            }
+            set(F_LAST, last);
+        }
+        ih = 1.0 / h;
+        isc = act ? 1.0 / (P.atol + P.rtol * __builtin_fabs(y)) : 0.0;
+        if (FIXED || has(F_JSTALE)) {
+            double gu;
+            (void)rhs(y, gu);
+            uJ = y;
+            gJ = gu;
+            ++njac;
+            flags = (flags & ~(F_JSTALE | F_LUOK)) | F_JATY0;
+        }
+        if (FIXED || !has(F_LUOK)) {
+            ++ndec;
+            if (!factor()) {
+                if (FIXED || ++nsing >= 5) { status = ST_SINGULAR; phase = PH_IDLE; return; }
+                h *= 0.5;
+                phase = PH_START;
+                return;
+            }
+            nsing = 0;
+            flags |= F_LUOK;
+        }
+        /* start values (zero on the cell's first step); every branch ends in
+         * the same single assignment of w1, w2, w3 */
+        double za = 0.0, zb = 0.0, zc = 0.0;
+        if (has(F_OLD)) {
+            const double r = h / h_old;
+            const double s1 = -1.0, s2 = radau::C1 - 1.0, s3 = radau::C2 - 1.0;
+            const double cs[3] = {radau::C1 * r, radau::C2 * r, r};
+            double Lw[3][3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const double s = cs[i];
+                const double d1 = s - s1, d2 = s - s2, d3 = s - s3, d4 = s;
+                Lw[i][0] = d2 * d3 * d4 * radau::LAG_INV0;
+                Lw[i][1] = d1 * d3 * d4 * radau::LAG_INV1;
+                Lw[i][2] = d1 * d2 * d4 * radau::LAG_INV2;
+            }
+            const double v0 = -z3o, v1 = z1o - z3o, v2 = z2o - z3o;
+            za = Lw[0][0] * v0 + Lw[0][1] * v1 + Lw[0][2] * v2;
+            zb = Lw[1][0] * v0 + Lw[1][1] * v1 + Lw[1][2] * v2;
+            zc = Lw[2][0] * v0 + Lw[2][1] * v1 + Lw[2][2] * v2;
+        }
+        w1 = radau::TI11 * za + radau::TI12 * zb + radau::TI13 * zc;
+        w2 = radau::TI21 * za + radau::TI22 * zb + radau::TI23 * zc;
+        w3 = radau::TI31 * za + radau::TI32 * zb + radau::TI33 * zc;
+        k = 0;
+        nprev = 0.0;
+        phase = PH_NEWTON;
+    }
+
+    __device__ __forceinline__ int newton(const StepParams& P) {
+        ++k;
+        ++nnewt;
+        double G1, G2, G3, gu;
+        {
+            const double z = radau::T11 * w1 + radau::T12 * w2 + radau::T13 * w3;
+            const double F = rhs(y + z, gu);
+            G1 = radau::TI11 * F;
+            G2 = radau::TI21 * F;
+            G3 = radau::TI31 * F;
+        }
+        {
+            const double z = radau::T21 * w1 + radau::T22 * w2 + radau::T23 * w3;
+            const double F = rhs(y + z, gu);
+            G1 += radau::TI12 * F;
+            G2 += radau::TI22 * F;
+            G3 += radau::TI32 * F;
+        }
+        {
+            const double z = w1 + w2;
+            const double F = rhs(y + z, gu);
+            G1 += radau::TI13 * F;
+            G2 += radau::TI23 * F;
+            G3 += radau::TI33 * F;
+        }
+        nfev += 3;
+        const double g = radau::GAMMA * ih, al = radau::ALPHA * ih, be = radau::BETA * ih;
+        const LT r1 = solve_real((LT)(G1 - g * w1));
+        LT r2 = (LT)(G2 - al * w2 + be * w3), r3 = (LT)(G3 - be * w2 - al * w3);
+        solve_cplx(r2, r3);
+        ++nsol;
+        const double d1 = (double)r1, d2 = (double)r2, d3 = (double)r3;
+        w1 += d1;
+        w2 += d2;
+        w3 += d3;
+        const double dz1 = radau::T11 * d1 + radau::T12 * d2 + radau::T13 * d3;
+        const double dz2 = radau::T21 * d1 + radau::T22 * d2 + radau::T23 * d3;
+        const double dz3 = d1 + d2;
+        const double s1 = dz1 * isc, s2 = dz2 * isc, s3 = dz3 * isc;
+        const double acc = grp_sum(s1 * s1 + s2 * s2 + s3 * s3);
+        const double nk = __builtin_sqrt(acc * inv3m);
+        if (!finite_d(nk)) return NW_FAILED;
+        const double tol = P.newton_tol;
+        if (k >= 2) {
+            const double th = nk / nprev;
+            if (th >= 0.99) return NW_FAILED;
+            const double om = 1.0 - th;
+            eta = th / om;
+            double tp = 1.0;
+            for (int j = 0; j < P.kmax - k; ++j) tp *= th;
+            if (tp * nk > tol * om) return NW_FAILED;
+            set(F_KEEPJ, th <= 1e-3);
+        } else {
+            set(F_KEEPJ, true);
+        }
+        if (eta * nk <= tol) return NW_CONVERGED;
+        nprev = nk;
+        return k >= P.kmax ? NW_FAILED : NW_CONTINUE;
+    }
+
+    __device__ __forceinline__ double estimate(double fb, double& e) {
+        constexpr double DW1 = radau::D1 * radau::T11 + radau::D2 * radau::T21 + radau::D3;
+        constexpr double DW2 = radau::D1 * radau::T12 + radau::D2 * radau::T22 + radau::D3;
+        constexpr double DW3 = radau::D1 * radau::T13 + radau::D2 * radau::T23;
+        const LT v = solve_real((LT)(fb + (DW1 * w1 + DW2 * w2 + DW3 * w3) * ih));
+        ++nsol;
+        e = (double)v;
+        const double s = e * isc;
+        return __builtin_sqrt(grp_sum(s * s) * invm);
+    }
+
+    template <bool FIXED>
+    __device__ __forceinline__ void finish(const StepParams& P, int oc) {
+        if (FIXED) {
+            if (oc == NW_FAILED) { status = ST_NEWTON; phase = PH_IDLE; return; }
+            ++nstep;
+            ++naccept;
+            z1o = radau::T11 * w1 + radau::T12 * w2 + radau::T13 * w3;
+            z2o = radau::T21 * w1 + radau::T22 * w2 + radau::T23 * w3;
+            z3o = w1 + w2;
+            y += z3o;
+            double gu;
+            f0 = rhs(y, gu);
+            ++nfev;
+            flags |= F_OLD;
+            if (grp_bits(finite_d(y)) != 0xFFFFu) { status = ST_NONFINITE; phase = PH_IDLE; return; }
+            h_old = h;
+            eta = pow(fmax(eta, UROUND), 0.8);
+            phase = (naccept >= P.fixed_steps) ? PH_IDLE : PH_START;
+            return;
+        }
+        if (oc == NW_FAILED) {
+            ++nstep;
+            ++nreject;
+            h *= 0.5;
+            flags = (flags | F_REJECT) & ~F_LUOK;
+            if (!has(F_JATY0)) flags |= F_JSTALE;
+            phase = PH_START;
+            return;
+        }
+        double e;
+        double err = estimate(f0, e);
+        if (err >= 1.0 && (flags & (F_FIRST | F_REJECT))) {
+            double gu;
+            const double fe = rhs(y + e, gu);
+            ++nfev;
+            err = estimate(fe, e);
+        }
+        if (!finite_d(err)) { status = ST_NONFINITE; phase = PH_IDLE; return; }
+        ++nstep;
+        const double kmx = (double)P.kmax;
+        const double fac = 0.9 * (2.0 * kmx + 1.0) / (2.0 * kmx + (double)k);
+        const double qerr = __builtin_sqrt(__builtin_sqrt(err));
+        const double ratio = (err == 0.0) ? 8.0 : fmin(8.0, fmax(0.2, fac / qerr));
+        double h_new = h * ratio;
+        if (err < 1.0) {
+            if (has(F_ACC)) {
+                const double r2 = (err == 0.0)
+                    ? 8.0
+                    : fmin(8.0, fmax(0.2, fac * (h / h_acc) * qerr_acc / (qerr * qerr)));
+                h_new = fmin(h_new, h * r2);
+            }
+            const double zz1 = radau::T11 * w1 + radau::T12 * w2 + radau::T13 * w3;
+            const double zz2 = radau::T21 * w1 + radau::T22 * w2 + radau::T23 * w3;
+            const double zz3 = w1 + w2;
+            const double y1 = y + zz3;
+            double gu;
+            const double f1 = rhs(y1, gu);
+            ++nfev;
+            if (grp_bits(finite_d(y1) && finite_d(f1)) != 0xFFFFu) {
+                status = ST_NONFINITE;
+                phase = PH_IDLE;
+                return;
+            }
+            h_acc = h;
+            qerr_acc = __builtin_sqrt(__builtin_sqrt(fmax(err, 1e-2)));
+            y = y1;
+            f0 = f1;
+            z1o = zz1;
+            z2o = zz2;
+            z3o = zz3;
+            t = has(F_LAST) ? P.dt : t + h;
+            h_old = h;
+            eta = pow(fmax(eta, UROUND), 0.8);
+            ++naccept;
+            if (has(F_REJECT)) h_new = fmin(h_new, h);
+            const bool keep_j = has(F_KEEPJ);
+            flags = (flags & ~(F_FIRST | F_REJECT | F_JATY0 | F_JSTALE)) | F_OLD | F_ACC |
+                    (keep_j ? 0u : F_JSTALE);
+            if (keep_j) {
+                const double qq = h_new / h;
+                if (qq >= 1.0 && qq <= 1.2) h_new = h;
+            }
+            const double hn = fmin(h_new, P.dt - t);
+            if (hn != h) flags &= ~F_LUOK;
+            h = hn;
+            phase = (t < P.dt) ? PH_START : PH_IDLE;
+        } else {
+            ++nreject;
+            const double hn = has(F_FIRST) ? 0.1 * h : h_new;
+            if (hn != h) flags &= ~F_LUOK;
+            h = hn;
+            flags |= F_REJECT;
+            phase = PH_START;
+        }
+    }
+};
+
+}  // namespace rd

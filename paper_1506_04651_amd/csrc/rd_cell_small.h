@@ -49,6 +49,8 @@ enum : unsigned { F_FIRST = 1u, F_REJECT = 2u, F_JSTALE = 4u, F_JATY0 = 8u, F_LU
 constexpr double UROUND = 2.220446049250313e-16;
 
 __device__ __forceinline__ bool finite_d(double x) { return __builtin_isfinite(x); }
+__device__ __forceinline__ float fabs_t(float x) { return __builtin_fabsf(x); }
+__device__ __forceinline__ double fabs_t(double x) { return __builtin_fabs(x); }
 
 /* ---------------- small dense LU with partial pivoting ------------------ */
 /* Factor a in place (unit-lower L below the diagonal, reciprocal of U's
@@ -62,10 +64,10 @@ __device__ __forceinline__ bool lu_real(T (&a)[M][M], unsigned& piv) {
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         int p = k;
-        T best = __builtin_fabs(a[k][k]);
+        T best = fabs_t(a[k][k]);
 #pragma unroll
         for (int i = k + 1; i < M; ++i) {
-            const T v = __builtin_fabs(a[i][k]);
+            const T v = fabs_t(a[i][k]);
             const bool gt = v > best;
             best = gt ? v : best;
             p = gt ? i : p;

@@ -1,16 +1,197 @@
 /*
- * rd_kernels_group.hip -- reaction-step kernels for larger systems, where a
- * group of lanes shares one cell.
+ * rd_kernels_group.hip -- reaction-step kernels for 5 <= m <= 16 (the
+ * synthetic stiff kinetics and linear test models): a 16-lane group of a
+ * wave64 shares one cell, four cells per wave.
+ *
+ * Schedules as for one-lane cells: one launch per batch (a group owns one
+ * cell), or persistent work stealing in which an idle group claims the next
+ * position of the claim order through its wave's claim queue.  The step-end /
+ * step-start block is batched across the wave's groups (at least FSMIN groups
+ * waiting, or no group left iterating), which changes when a cell advances,
+ * never what it computes.
  */
 #include <hip/hip_runtime.h>
 
+#include "rd_cell_group.h"
 #include "rd_launch.h"
 
 namespace rd {
 
+constexpr unsigned kGroupClaimChunk = 4; /* cells */
+
+/* Model rows into LDS, zero padded to 16 x 16 (K then G per row). */
+template <class Model>
+__device__ __forceinline__ void load_table(double* tab, const double* __restrict__ p, int m, int block) {
+    for (int i = threadIdx.x; i < GroupTable::DOUBLES; i += block) {
+        const int row = i / GroupTable::STRIDE, col = i % GroupTable::STRIDE;
+        double v = 0.0;
+        if (row < m) {
+            if (col < m) v = p[row * m + col];
+            else if (Model::HAS_G && col >= kGroup && col < kGroup + m) v = p[m * m + row * m + (col - kGroup)];
+        }
+        tab[i] = v;
+    }
+    __syncthreads();
+}
+
+template <class Model, typename LT>
+__device__ __forceinline__ void init_cell(GroupCell<Model, LT>& cell, const double* tab, int m) {
+    cell.q = (int)grp_lane();
+    cell.m = m;
+    cell.act = cell.q < m;
+    cell.inv3m = 1.0 / (3.0 * m);
+    cell.invm = 1.0 / m;
+    cell.kg = tab + cell.q * GroupTable::STRIDE;
+    cell.phase = PH_IDLE;
+    cell.status = ST_OK;
+    cell.uJ = cell.gJ = 0.0;
+}
+
+template <class Model, typename LT, bool FIXED, int FSMIN>
+__device__ __forceinline__ void advance_group(GroupCell<Model, LT>& cell, const StepParams& P) {
+    /* keep the LDS table reads inside the loop (no hoisting into registers) */
+    /* keep the LDS model rows out of registers: they are re-read, not hoisted */
+    __asm__ volatile("" ::: "memory");
+    if (cell.phase == PH_NEWTON) {
+        const int o = cell.newton(P);
+        if (o != NW_CONTINUE) {
+            cell.outcome = o;
+            cell.phase = PH_END;
+        }
+    }
+    const bool waits = cell.phase == PH_END || cell.phase == PH_START;
+    if (FSMIN > 1) {
+        const unsigned long long wmask = __ballot(waits);
+        if (wmask == 0ull) return;
+        if ((unsigned)__popcll(wmask) < (unsigned)(FSMIN * kGroup) &&
+            __ballot(cell.phase == PH_NEWTON) != 0ull)
+            return;
+    }
+    if (cell.phase == PH_END) cell.template finish<FIXED>(P, cell.outcome);
+    if (cell.phase == PH_START) cell.template start<FIXED>(P);
+}
+
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
+k_group_onelaunch(LaunchArgs a, int m) {
+    __shared__ double tab[GroupTable::DOUBLES];
+    load_table<Model>(tab, a.params, m, BLOCK);
+    const int64_t c = (int64_t)blockIdx.x * (BLOCK / kGroup) + threadIdx.x / kGroup;
+    if (c >= a.n) return;
+    GroupCell<Model, LT> cell;
+    init_cell(cell, tab, m);
+    cell.load(a.P, a.states, a.n, c);
+    while (cell.phase != PH_IDLE) advance_group<Model, LT, FIXED, FSMIN>(cell, a.P);
+    cell.store(a.states, a.stats, a.n, c);
+    if (cell.status != ST_OK && cell.q == 0) atomicAdd(a.nfail, 1ull);
+}
+
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
+k_group_persistent(LaunchArgs a, int m) {
+    __shared__ double tab[GroupTable::DOUBLES];
+    load_table<Model>(tab, a.params, m, BLOCK);
+    GroupCell<Model, LT> cell;
+    init_cell(cell, tab, m);
+    int64_t c = -1;
+    bool alive = true;
+    const unsigned lane = __lane_id();
+    const unsigned long long below = (1ull << lane) - 1ull;
+    unsigned long long qnext = 0, qend = 0; /* wave-uniform claim queue, in cells */
+    for (;;) {
+        const bool need = alive && cell.phase == PH_IDLE; /* group-uniform */
+        if (need && c >= 0) {
+            cell.store(a.states, a.stats, a.n, c);
+            if (cell.status != ST_OK && cell.q == 0) atomicAdd(a.nfail, 1ull);
+            c = -1;
+        }
+        const unsigned long long mask = __ballot(need);
+        if (mask) {
+            const unsigned cnt = (unsigned)__popcll(mask) / kGroup;
+            const unsigned rank = (unsigned)__popcll(mask & below) / kGroup;
+            const unsigned long long avail = qend - qnext;
+            unsigned long long pos;
+            if (avail >= cnt) {
+                pos = qnext + rank;
+                qnext += cnt;
+            } else {
+                const unsigned take = (cnt - (unsigned)avail) > kGroupClaimChunk
+                                          ? cnt - (unsigned)avail : kGroupClaimChunk;
+                const int leader = __ffsll((long long)mask) - 1;
+                unsigned long long base = 0;
+                if (lane == (unsigned)leader) base = atomicAdd(a.counter, (unsigned long long)take);
+                base = __shfl(base, leader);
+                pos = rank < avail ? qnext + rank : base + (rank - avail);
+                qnext = base + (cnt - avail);
+                qend = base + take;
+            }
+            if (need) {
+                if (pos < (unsigned long long)a.n) {
+                    c = a.order ? (int64_t)a.order[pos] : (int64_t)pos;
+                    cell.load(a.P, a.states, a.n, c);
+                } else {
+                    alive = false;
+                }
+            }
+        }
+        if (__ballot(alive) == 0ull) break;
+        advance_group<Model, LT, FIXED, FSMIN>(cell, a.P);
+    }
+}
+
+/* the species count travels in StepParams::m */
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN>
+hipError_t launch_group_one(const LaunchArgs& a, int grid, hipStream_t s) {
+    constexpr int cells = BLOCK / kGroup;
+    if (grid <= 0) grid = (int)((a.n + cells - 1) / cells);
+    hipLaunchKernelGGL((k_group_onelaunch<Model, LT, FIXED, BLOCK, WPE, FSMIN>), dim3(grid),
+                       dim3(BLOCK), 0, s, a, (int)a.P.m);
+    return hipGetLastError();
+}
+
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN>
+hipError_t launch_group_pers(const LaunchArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_group_persistent<Model, LT, FIXED, BLOCK, WPE, FSMIN>), dim3(grid),
+                       dim3(BLOCK), 0, s, a, (int)a.P.m);
+    return hipGetLastError();
+}
+
+#define RD_GONE(KIND, MODEL, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, NAME)                          \
+    {KIND, 16, PREC, 1, FIXED, VAR, BLOCK, BLOCK / kGroup, NAME,                                 \
+     &launch_group_one<MODEL, LT, FIXED, BLOCK, WPE, FS>,                                        \
+     (const void*)&k_group_onelaunch<MODEL, LT, FIXED, BLOCK, WPE, FS>}
+#define RD_GPERS(KIND, MODEL, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, NAME)                         \
+    {KIND, 16, PREC, 0, FIXED, VAR, BLOCK, BLOCK / kGroup, NAME,                                 \
+     &launch_group_pers<MODEL, LT, FIXED, BLOCK, WPE, FS>,                                       \
+     (const void*)&k_group_persistent<MODEL, LT, FIXED, BLOCK, WPE, FS>}
+
+/* m is marked 16 in the table: these kernels serve every 5 <= m <= 16 */
+static const KernelEntry g_group_table[] = {
+    RD_GONE(2, GroupKinetics, 0, double, false, 1, 256, 1, 1, "kinetics.g16.fp64.onelaunch.b256"),
+    RD_GONE(2, GroupKinetics, 1, float, false, 1, 256, 1, 1, "kinetics.g16.mixed.onelaunch.b256"),
+    RD_GPERS(2, GroupKinetics, 0, double, false, 1, 256, 2, 2, "kinetics.g16.fp64.persistent.b256.w2.fs2"),
+    RD_GPERS(2, GroupKinetics, 1, float, false, 1, 256, 2, 2, "kinetics.g16.mixed.persistent.b256.w2.fs2"),
+    RD_GPERS(2, GroupKinetics, 0, double, false, 2, 256, 1, 2, "kinetics.g16.fp64.persistent.b256.fs2"),
+    RD_GPERS(2, GroupKinetics, 1, float, false, 2, 256, 1, 2, "kinetics.g16.mixed.persistent.b256.fs2"),
+    RD_GPERS(2, GroupKinetics, 0, double, false, 3, 256, 2, 1, "kinetics.g16.fp64.persistent.b256.w2.fs1"),
+    RD_GPERS(2, GroupKinetics, 1, float, false, 3, 256, 2, 1, "kinetics.g16.mixed.persistent.b256.w2.fs1"),
+    RD_GPERS(2, GroupKinetics, 0, double, false, 4, 256, 2, 3, "kinetics.g16.fp64.persistent.b256.w2.fs3"),
+    RD_GPERS(2, GroupKinetics, 1, float, false, 4, 256, 2, 3, "kinetics.g16.mixed.persistent.b256.w2.fs3"),
+    RD_GPERS(2, GroupKinetics, 0, double, false, 5, 256, 3, 2, "kinetics.g16.fp64.persistent.b256.w3.fs2"),
+    RD_GPERS(2, GroupKinetics, 1, float, false, 5, 256, 3, 2, "kinetics.g16.mixed.persistent.b256.w3.fs2"),
+    RD_GONE(2, GroupKinetics, 0, double, true, 1, 256, 1, 1, "kinetics.g16.fp64.onelaunch.fixed"),
+    RD_GPERS(2, GroupKinetics, 0, double, true, 1, 256, 1, 1, "kinetics.g16.fp64.persistent.fixed"),
+    RD_GONE(4, GroupLinear, 0, double, false, 1, 256, 1, 1, "linear.g16.fp64.onelaunch.b256"),
+    RD_GONE(4, GroupLinear, 1, float, false, 1, 256, 1, 1, "linear.g16.mixed.onelaunch.b256"),
+    RD_GPERS(4, GroupLinear, 0, double, false, 1, 256, 1, 2, "linear.g16.fp64.persistent.b256.fs2"),
+    RD_GPERS(4, GroupLinear, 1, float, false, 1, 256, 1, 2, "linear.g16.mixed.persistent.b256.fs2"),
+    RD_GONE(4, GroupLinear, 0, double, true, 1, 256, 1, 1, "linear.g16.fp64.onelaunch.fixed"),
+    RD_GPERS(4, GroupLinear, 0, double, true, 1, 256, 1, 1, "linear.g16.fp64.persistent.fixed"),
+};
+
 const KernelEntry* group_kernel_table(int* count) {
-    *count = 0;
-    return nullptr;
+    *count = (int)(sizeof(g_group_table) / sizeof(g_group_table[0]));
+    return g_group_table;
 }
 
 }  // namespace rd

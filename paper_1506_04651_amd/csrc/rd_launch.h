@@ -11,7 +11,7 @@ namespace rd {
 /* Per-call integration constants (tolerances already transformed). */
 struct StepParams {
     double dt, rtol, atol, newton_tol, h0, h_min;
-    int32_t max_steps, kmax, fixed_steps, pad;
+    int32_t max_steps, kmax, fixed_steps, m; /* m: species per cell */
 };
 
 struct LaunchArgs {

@@ -1,0 +1,153 @@
+"""GPU parity of the 16-lane-group kernels (5 <= m <= 16): synthetic stiff
+kinetics (the m = 16 workload and other m), linear test models, failure codes,
+schedule equivalence and mixed precision, against the CPU FP64 oracle."""
+import numpy as np
+import pytest
+
+from paper_1506_04651_amd import workloads as W
+from tests.parity import compare, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rd():
+    import paper_1506_04651_amd as rd
+    rd.load()
+    assert torch.cuda.is_available()
+    return rd
+
+
+def run_gpu(rd, w, stats=True, **opts):
+    u = torch.tensor(w.states, dtype=torch.float64, device="cuda")
+    st = torch.zeros((9, w.n), dtype=torch.int32, device="cuda") if stats else None
+    ret = rd.reaction_step(u, w.dt, w.rtol, w.atol, w.kind, w.params, stats=st, **opts)
+    torch.cuda.synchronize()
+    return u.cpu().numpy(), (st.cpu().numpy() if stats else None), ret
+
+
+def run_oracle(orc, w, **opts):
+    return orc.reaction_step(w.states, w.dt, w.rtol, w.atol, w.kind, w.params, **opts)
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_kinetics16_parity(rd, orc, schedule):
+    w = W.kinetics16(n=2048)
+    say("kinetics16 fp64 schedule", schedule, "n", w.n)
+    y, st, ret = run_gpu(rd, w, schedule=schedule)
+    yo, sto, reto = run_oracle(orc, w)
+    assert ret == reto == 0
+    rep = compare(y, st, yo, sto, w.atol, label=f"kin16 sched{schedule}")
+    assert rep["max_err_same_trace"] <= 1e-8
+    assert rep["trace_divergent"] <= max(2, int(2e-3 * w.n))
+    assert rep["max_err_divergent"] <= 10 * w.rtol
+
+
+def test_kinetics16_full_batch_sampled(rd, orc):
+    """The full 1 048 576-cell batch in the benchmark's launch configuration;
+    a seeded sample of cells recomputed by the oracle."""
+    w = W.kinetics16()
+    say("kinetics16 full batch n", w.n)
+    y, st, ret = run_gpu(rd, w)
+    assert ret == 0
+    idx = W.sample_indices(w.n, 1024, 41)
+    s = w.subset(idx)
+    yo, sto, reto = run_oracle(orc, s)
+    assert reto == 0
+    rep = compare(y[:, idx], st[:, idx], yo, sto, w.atol, label="kin16 full sampled")
+    assert rep["max_err_same_trace"] <= 1e-8
+    assert rep["trace_divergent"] <= 4
+    # invariant of every cell at any size: with G >= 0 and 1^T K = 0 the total
+    # mass can only decrease, by the quadratic loss term
+    s0, s1 = w.states.sum(axis=0), y.sum(axis=0)
+    assert np.all(s1 <= s0 * (1 + 10 * w.rtol))
+
+
+@pytest.mark.parametrize("m", [5, 7, 12, 16])
+def test_kinetics_other_m(rd, orc, m):
+    w = W.kinetics16(n=384, m=m, seed=100 + m)
+    say("kinetics m", m)
+    for sched in (0, 1):
+        y, st, ret = run_gpu(rd, w, schedule=sched)
+        yo, sto, reto = run_oracle(orc, w)
+        assert ret == reto
+        rep = compare(y, st, yo, sto, w.atol, label=f"kin m{m} sched{sched}")
+        assert rep["max_err_same_trace"] <= 1e-8
+        assert rep["trace_divergent"] <= 3
+
+
+def test_linear_chain_exact_fixed_steps(rd, orc):
+    """y' = K y with K the 6 x 6 lower shift: solutions of degree 5 are
+    integrated exactly by Radau IIA (order 5); fixed steps on the group
+    kernel against the closed form and the oracle."""
+    m, T = 6, 1.7
+    K = np.zeros((m, m))
+    for i in range(m - 1):
+        K[i + 1, i] = 1.0
+    y0 = np.zeros((m, 8))
+    y0[0] = np.arange(1, 9)
+    w = W.Workload("chain", y0, W.KIND_LINEAR, K.ravel(), T, 1e-8, 1e-8)
+    exact = np.array([T ** k / np.prod(np.arange(1, k + 1)) for k in range(m)])[:, None] * y0[0]
+    for fixed in (1, 3):
+        say("linear chain fixed", fixed)
+        y, st, ret = run_gpu(rd, w, fixed_steps=fixed)
+        assert ret == 0
+        assert np.max(np.abs(y - exact)) <= 1e-13 * np.max(np.abs(exact))
+        yo, sto, _ = run_oracle(orc, w, fixed_steps=fixed)
+        assert np.array_equal(st[1:], sto[1:])
+
+
+def test_singular_five_in_a_row(rd, orc):
+    g = orc.constants()["gamma_hat"]
+    dt = 0.5
+    K = np.diag([g / (dt * 0.5 ** i) for i in range(5)])
+    w = W.Workload("sing5", np.ones((5, 7)), W.KIND_LINEAR, K.ravel(), dt, 1e-5, 1e-5)
+    say("singular m=5")
+    y, st, ret = run_gpu(rd, w)
+    yo, sto, reto = run_oracle(orc, w)
+    assert ret == reto == 7
+    assert np.all(st[0] == 3) and np.array_equal(st[6], sto[6])
+    assert np.array_equal(y, w.states)
+
+
+def test_group_nonfinite_and_maxsteps(rd, orc):
+    w = W.kinetics16(n=64, seed=9)
+    s = w.states.copy()
+    s[3, 10] = np.nan
+    bad = W.Workload("bad16", s, w.kind, w.params, w.dt, w.rtol, w.atol)
+    say("kinetics16 nonfinite")
+    y, st, ret = run_gpu(rd, bad)
+    yo, sto, reto = run_oracle(orc, bad)
+    assert ret == reto == 1 and np.array_equal(st[0], sto[0])
+    say("kinetics16 max_steps=5")
+    y, st, ret = run_gpu(rd, w, max_steps=5)
+    yo, sto, reto = run_oracle(orc, w, max_steps=5)
+    assert ret == reto and np.array_equal(st[0], sto[0])
+
+
+def test_group_schedules_and_order_bitwise(rd):
+    w = W.kinetics16(n=20000, seed=12)
+    say("kinetics16 schedule/order equivalence")
+    a, sa, _ = run_gpu(rd, w, schedule=0, order=1)
+    b, sb, _ = run_gpu(rd, w, schedule=0, order=0)
+    c, sc, _ = run_gpu(rd, w, schedule=1)
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+    assert np.array_equal(sa, sb) and np.array_equal(sa, sc)
+    for v in range(1, rd.variant_count(rd.KINETICS, 16, 0, 0) + 1):
+        d, sd, _ = run_gpu(rd, w, variant=v)
+        assert np.array_equal(a, d), v
+
+
+def test_kinetics16_mixed_precision_error_report(rd, orc):
+    """FP32 factors and solves inside the FP64 Newton iteration: per-cell
+    error against the FP64 oracle is reported; every cell must stay within the
+    tolerance scale of the solution (10 rtol)."""
+    w = W.kinetics16(n=2048)
+    say("kinetics16 mixed")
+    y, st, ret = run_gpu(rd, w, precision=1)
+    yo, sto, reto = run_oracle(orc, w)
+    assert ret == 0
+    rep = compare(y, st, yo, sto, w.atol, label="kin16 mixed")
+    assert rep["max_err"] <= 10 * w.rtol
