@@ -169,22 +169,22 @@ hipError_t launch_group_pers(const LaunchArgs& a, int grid, hipStream_t s) {
 static const KernelEntry g_group_table[] = {
     RD_GONE(2, GroupKinetics, 0, double, false, 1, 256, 1, 1, "kinetics.g16.fp64.onelaunch.b256"),
     RD_GONE(2, GroupKinetics, 1, float, false, 1, 256, 1, 1, "kinetics.g16.mixed.onelaunch.b256"),
-    RD_GPERS(2, GroupKinetics, 0, double, false, 1, 256, 2, 2, "kinetics.g16.fp64.persistent.b256.w2.fs2"),
-    RD_GPERS(2, GroupKinetics, 1, float, false, 1, 256, 2, 2, "kinetics.g16.mixed.persistent.b256.w2.fs2"),
+    RD_GPERS(2, GroupKinetics, 0, double, false, 1, 256, 2, 3, "kinetics.g16.fp64.persistent.b256.w2.fs3"),
+    RD_GPERS(2, GroupKinetics, 1, float, false, 1, 256, 2, 3, "kinetics.g16.mixed.persistent.b256.w2.fs3"),
     RD_GPERS(2, GroupKinetics, 0, double, false, 2, 256, 1, 2, "kinetics.g16.fp64.persistent.b256.fs2"),
     RD_GPERS(2, GroupKinetics, 1, float, false, 2, 256, 1, 2, "kinetics.g16.mixed.persistent.b256.fs2"),
     RD_GPERS(2, GroupKinetics, 0, double, false, 3, 256, 2, 1, "kinetics.g16.fp64.persistent.b256.w2.fs1"),
     RD_GPERS(2, GroupKinetics, 1, float, false, 3, 256, 2, 1, "kinetics.g16.mixed.persistent.b256.w2.fs1"),
-    RD_GPERS(2, GroupKinetics, 0, double, false, 4, 256, 2, 3, "kinetics.g16.fp64.persistent.b256.w2.fs3"),
-    RD_GPERS(2, GroupKinetics, 1, float, false, 4, 256, 2, 3, "kinetics.g16.mixed.persistent.b256.w2.fs3"),
+    RD_GPERS(2, GroupKinetics, 0, double, false, 4, 256, 2, 2, "kinetics.g16.fp64.persistent.b256.w2.fs2"),
+    RD_GPERS(2, GroupKinetics, 1, float, false, 4, 256, 2, 2, "kinetics.g16.mixed.persistent.b256.w2.fs2"),
     RD_GPERS(2, GroupKinetics, 0, double, false, 5, 256, 3, 2, "kinetics.g16.fp64.persistent.b256.w3.fs2"),
     RD_GPERS(2, GroupKinetics, 1, float, false, 5, 256, 3, 2, "kinetics.g16.mixed.persistent.b256.w3.fs2"),
     RD_GONE(2, GroupKinetics, 0, double, true, 1, 256, 1, 1, "kinetics.g16.fp64.onelaunch.fixed"),
     RD_GPERS(2, GroupKinetics, 0, double, true, 1, 256, 1, 1, "kinetics.g16.fp64.persistent.fixed"),
     RD_GONE(4, GroupLinear, 0, double, false, 1, 256, 1, 1, "linear.g16.fp64.onelaunch.b256"),
     RD_GONE(4, GroupLinear, 1, float, false, 1, 256, 1, 1, "linear.g16.mixed.onelaunch.b256"),
-    RD_GPERS(4, GroupLinear, 0, double, false, 1, 256, 1, 2, "linear.g16.fp64.persistent.b256.fs2"),
-    RD_GPERS(4, GroupLinear, 1, float, false, 1, 256, 1, 2, "linear.g16.mixed.persistent.b256.fs2"),
+    RD_GPERS(4, GroupLinear, 0, double, false, 1, 256, 2, 3, "linear.g16.fp64.persistent.b256.w2.fs3"),
+    RD_GPERS(4, GroupLinear, 1, float, false, 1, 256, 2, 3, "linear.g16.mixed.persistent.b256.w2.fs3"),
     RD_GONE(4, GroupLinear, 0, double, true, 1, 256, 1, 1, "linear.g16.fp64.onelaunch.fixed"),
     RD_GPERS(4, GroupLinear, 0, double, true, 1, 256, 1, 1, "linear.g16.fp64.persistent.fixed"),
 };

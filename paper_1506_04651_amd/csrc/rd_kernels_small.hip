@@ -170,23 +170,23 @@ hipError_t launch_pers(const LaunchArgs& a, int grid, hipStream_t s) {
 enum { K_OREG = 1, K_KIN = 2, K_NAG = 3, K_LIN = 4, K_ROB = 5 };
 
 #define RD_MODEL_SET(KIND, MODEL, M, TAG)                                                     \
-    RD_ONE(KIND, MODEL, M, 0, double, false, 1, 256, 1, 1, TAG ".fp64.onelaunch.b256"),       \
-    RD_ONE(KIND, MODEL, M, 1, float, false, 1, 256, 1, 1, TAG ".mixed.onelaunch.b256"),       \
-    RD_PERS(KIND, MODEL, M, 0, double, false, 1, 128, 1, 32, TAG ".fp64.persistent.b128.fs32"), \
-    RD_PERS(KIND, MODEL, M, 1, float, false, 1, 128, 1, 32, TAG ".mixed.persistent.b128.fs32"), \
+    RD_ONE(KIND, MODEL, M, 0, double, false, 1, 256, 1, 32, TAG ".fp64.onelaunch.b256.fs32"), \
+    RD_ONE(KIND, MODEL, M, 1, float, false, 1, 256, 1, 32, TAG ".mixed.onelaunch.b256.fs32"), \
+    RD_PERS(KIND, MODEL, M, 0, double, false, 1, 128, 1, 40, TAG ".fp64.persistent.b128.fs40"), \
+    RD_PERS(KIND, MODEL, M, 1, float, false, 1, 128, 1, 40, TAG ".mixed.persistent.b128.fs40"), \
     RD_ONE(KIND, MODEL, M, 0, double, true, 1, 256, 1, 1, TAG ".fp64.onelaunch.fixed"),       \
     RD_PERS(KIND, MODEL, M, 0, double, true, 1, 256, 1, 1, TAG ".fp64.persistent.fixed")
 
 #define RD_TUNE_SET(KIND, MODEL, M, PREC, LT, TAG)                                            \
     RD_PERS(KIND, MODEL, M, PREC, LT, false, 2, 128, 1, 1, TAG ".persistent.b128.fs1"),       \
     RD_PERS(KIND, MODEL, M, PREC, LT, false, 3, 128, 1, 24, TAG ".persistent.b128.fs24"),     \
-    RD_PERS(KIND, MODEL, M, PREC, LT, false, 4, 128, 1, 40, TAG ".persistent.b128.fs40"),     \
+    RD_PERS(KIND, MODEL, M, PREC, LT, false, 4, 128, 1, 32, TAG ".persistent.b128.fs32"),     \
     RD_PERS(KIND, MODEL, M, PREC, LT, false, 5, 128, 1, 48, TAG ".persistent.b128.fs48"),     \
     RD_PERS(KIND, MODEL, M, PREC, LT, false, 6, 128, 1, 56, TAG ".persistent.b128.fs56"),     \
     RD_PERS(KIND, MODEL, M, PREC, LT, false, 7, 256, 1, 40, TAG ".persistent.b256.fs40"),     \
     RD_PERS(KIND, MODEL, M, PREC, LT, false, 8, 64, 1, 40, TAG ".persistent.b64.fs40"),       \
     RD_ONE(KIND, MODEL, M, PREC, LT, false, 2, 256, 1, 16, TAG ".onelaunch.b256.fs16"),       \
-    RD_ONE(KIND, MODEL, M, PREC, LT, false, 3, 256, 1, 32, TAG ".onelaunch.b256.fs32")
+    RD_ONE(KIND, MODEL, M, PREC, LT, false, 3, 256, 1, 1, TAG ".onelaunch.b256.fs1")
 
 static const KernelEntry g_small_table[] = {
     RD_MODEL_SET(K_OREG, Oregonator, 3, "oregonator"),
