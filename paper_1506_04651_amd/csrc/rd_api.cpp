@@ -264,6 +264,8 @@ void make_step_params(double dt, double rtol, double atol, const rd_options& o, 
     P->newton_tol = std::max(10.0 * uround / rt, std::min(0.03, std::sqrt(rt)));
     P->h0 = o.h0;
     P->h_min = o.h_min > 0.0 ? o.h_min : 1e-14 * dt;
+    for (int k = 0; k <= kMaxFacTable; ++k)
+        P->fac[k] = 0.9 * (2.0 * o.newton_max + 1.0) / (2.0 * o.newton_max + (double)k);
     P->max_steps = o.max_steps;
     P->kmax = o.newton_max;
     P->fixed_steps = o.fixed_steps;

@@ -165,7 +165,7 @@ struct GroupCell {
                     akk = bcast_dyn(a[kk], kk);
                 }
                 ok = ok && (akk != LT(0));
-                const LT inv = LT(1) / akk;
+                const LT inv = rcp(akk);
                 const LT l = a[kk] * inv;
                 a[kk] = (q == kk) ? inv : (below ? l : a[kk]);
 #pragma unroll
@@ -204,7 +204,7 @@ struct GroupCell {
                     pi = bcast_dyn(ai[kk], kk);
                 }
                 ok = ok && !(pr == LT(0) && pi == LT(0));
-                const LT rn = LT(1) / (pr * pr + pi * pi);
+                const LT rn = rcp(pr * pr + pi * pi);
                 const LT ir = pr * rn, ii = -pi * rn;
                 const LT xr = ar[kk], xi = ai[kk];
                 const LT lr = xr * ir - xi * ii, li = xr * ii + xi * ir;
@@ -305,8 +305,8 @@ struct GroupCell {
             }
             set(F_LAST, last);
         }
-        ih = 1.0 / h;
-        isc = act ? 1.0 / (P.atol + P.rtol * __builtin_fabs(y)) : 0.0;
+        ih = rcp(h);
+        isc = act ? rcp(P.atol + P.rtol * __builtin_fabs(y)) : 0.0;
         if (FIXED || has(F_JSTALE)) {
             double gu;
             (void)rhs(y, gu);
@@ -330,7 +330,7 @@ struct GroupCell {
          * the same single assignment of w1, w2, w3 */
         double za = 0.0, zb = 0.0, zc = 0.0;
         if (has(F_OLD)) {
-            const double r = h / h_old;
+            const double r = h * rcp(h_old);
             const double s1 = -1.0, s2 = radau::C1 - 1.0, s3 = radau::C2 - 1.0;
             const double cs[3] = {radau::C1 * r, radau::C2 * r, r};
             double Lw[3][3];
@@ -465,8 +465,9 @@ struct GroupCell {
         }
         if (!finite_d(err)) { status = ST_NONFINITE; phase = PH_IDLE; return; }
         ++nstep;
-        const double kmx = (double)P.kmax;
-        const double fac = 0.9 * (2.0 * kmx + 1.0) / (2.0 * kmx + (double)k);
+        const double fac = k <= kMaxFacTable
+                               ? P.fac[k]
+                               : 0.9 * (2.0 * P.kmax + 1.0) / (2.0 * P.kmax + (double)k);
         const double qerr = __builtin_sqrt(__builtin_sqrt(err));
         const double ratio = (err == 0.0) ? 8.0 : fmin(8.0, fmax(0.2, fac / qerr));
         double h_new = h * ratio;
@@ -505,8 +506,8 @@ struct GroupCell {
             flags = (flags & ~(F_FIRST | F_REJECT | F_JATY0 | F_JSTALE)) | F_OLD | F_ACC |
                     (keep_j ? 0u : F_JSTALE);
             if (keep_j) {
-                const double qq = h_new / h;
-                if (qq >= 1.0 && qq <= 1.2) h_new = h;
+                /* h_new / h in [1, 1.2] */
+                if (h_new >= h && h_new <= 1.2 * h) h_new = h;
             }
             const double hn = fmin(h_new, P.dt - t);
             if (hn != h) flags &= ~F_LUOK;

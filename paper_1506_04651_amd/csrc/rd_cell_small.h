@@ -49,6 +49,18 @@ enum : unsigned { F_FIRST = 1u, F_REJECT = 2u, F_JSTALE = 4u, F_JATY0 = 8u, F_LU
 constexpr double UROUND = 2.220446049250313e-16;
 
 __device__ __forceinline__ bool finite_d(double x) { return __builtin_isfinite(x); }
+
+/* 1/a: hardware reciprocal estimate refined by two Newton-Raphson steps
+ * (error well below one ulp of the correctly rounded quotient for normal a);
+ * zero, infinite and denormal a take the IEEE division. */
+__device__ __forceinline__ double rcp(double a) {
+    double r = __builtin_amdgcn_rcp(a);
+    r = __builtin_fma(__builtin_fma(-a, r, 1.0), r, r);
+    r = __builtin_fma(__builtin_fma(-a, r, 1.0), r, r);
+    const double aa = __builtin_fabs(a);
+    return (aa >= 2.2250738585072014e-308 && aa <= 1e300) ? r : 1.0 / a;
+}
+__device__ __forceinline__ float rcp(float a) { return 1.0f / a; }
 __device__ __forceinline__ float fabs_t(float x) { return __builtin_fabsf(x); }
 __device__ __forceinline__ double fabs_t(double x) { return __builtin_fabs(x); }
 
@@ -73,18 +85,20 @@ __device__ __forceinline__ bool lu_real(T (&a)[M][M], unsigned& piv) {
             p = gt ? i : p;
         }
         piv |= (unsigned)p << (2 * k);
+        if (__ballot(p != k) != 0ull) {
 #pragma unroll
-        for (int i = k + 1; i < M; ++i) {
-            const bool s = (p == i);
+            for (int i = k + 1; i < M; ++i) {
+                const bool s = (p == i);
 #pragma unroll
-            for (int j = 0; j < M; ++j) {
-                const T ak = a[k][j], ai = a[i][j];
-                a[k][j] = s ? ai : ak;
-                a[i][j] = s ? ak : ai;
+                for (int j = 0; j < M; ++j) {
+                    const T ak = a[k][j], ai = a[i][j];
+                    a[k][j] = s ? ai : ak;
+                    a[i][j] = s ? ak : ai;
+                }
             }
         }
         ok = ok && (a[k][k] != T(0));
-        const T inv = T(1) / a[k][k];
+        const T inv = rcp(a[k][k]);
         a[k][k] = inv;
 #pragma unroll
         for (int i = k + 1; i < M; ++i) {
@@ -97,17 +111,29 @@ __device__ __forceinline__ bool lu_real(T (&a)[M][M], unsigned& piv) {
     return ok;
 }
 
+/* packed pivot word of the identity permutation: step k chose row k */
+template <int M>
+__device__ __forceinline__ constexpr unsigned piv_identity() {
+    unsigned v = 0;
+    for (int k = 0; k < M; ++k) v |= (unsigned)k << (2 * k);
+    return v;
+}
+
 template <int M, typename T>
 __device__ __forceinline__ void lu_solve_real(const T (&a)[M][M], unsigned piv, T (&b)[M]) {
+    /* row interchanges are rare for these iteration matrices: the selects run
+     * only when some lane of the wave actually pivoted */
+    if (__ballot(piv != piv_identity<M>()) != 0ull) {
 #pragma unroll
-    for (int k = 0; k < M - 1; ++k) {
-        const int p = (piv >> (2 * k)) & 3;
+        for (int k = 0; k < M - 1; ++k) {
+            const int p = (piv >> (2 * k)) & 3;
 #pragma unroll
-        for (int i = k + 1; i < M; ++i) {
-            const bool s = (p == i);
-            const T bk = b[k], bi = b[i];
-            b[k] = s ? bi : bk;
-            b[i] = s ? bk : bi;
+            for (int i = k + 1; i < M; ++i) {
+                const bool s = (p == i);
+                const T bk = b[k], bi = b[i];
+                b[k] = s ? bi : bk;
+                b[i] = s ? bk : bi;
+            }
         }
     }
 #pragma unroll
@@ -140,6 +166,7 @@ __device__ __forceinline__ bool lu_cplx(T (&ar)[M][M], T (&ai)[M][M], unsigned& 
             p = gt ? i : p;
         }
         piv |= (unsigned)p << (2 * k);
+        if (__ballot(p != k) != 0ull)
 #pragma unroll
         for (int i = k + 1; i < M; ++i) {
             const bool s = (p == i);
@@ -156,7 +183,7 @@ __device__ __forceinline__ bool lu_cplx(T (&ar)[M][M], T (&ai)[M][M], unsigned& 
         }
         const T pr = ar[k][k], pi = ai[k][k];
         ok = ok && !(pr == T(0) && pi == T(0));
-        const T rn = T(1) / (pr * pr + pi * pi);
+        const T rn = rcp(pr * pr + pi * pi);
         const T ir = pr * rn, ii = -pi * rn; /* 1/(pr + i pi) */
         ar[k][k] = ir;
         ai[k][k] = ii;
@@ -180,19 +207,21 @@ __device__ __forceinline__ bool lu_cplx(T (&ar)[M][M], T (&ai)[M][M], unsigned& 
 template <int M, typename T>
 __device__ __forceinline__ void lu_solve_cplx(const T (&ar)[M][M], const T (&ai)[M][M],
                                               unsigned piv, T (&br)[M], T (&bi)[M]) {
+    if (__ballot(piv != piv_identity<M>()) != 0ull) {
 #pragma unroll
-    for (int k = 0; k < M - 1; ++k) {
-        const int p = (piv >> (2 * k)) & 3;
+        for (int k = 0; k < M - 1; ++k) {
+            const int p = (piv >> (2 * k)) & 3;
 #pragma unroll
-        for (int i = k + 1; i < M; ++i) {
-            const bool s = (p == i);
-            T x = br[k], y = br[i];
-            br[k] = s ? y : x;
-            br[i] = s ? x : y;
-            x = bi[k];
-            y = bi[i];
-            bi[k] = s ? y : x;
-            bi[i] = s ? x : y;
+            for (int i = k + 1; i < M; ++i) {
+                const bool s = (p == i);
+                T x = br[k], y = br[i];
+                br[k] = s ? y : x;
+                br[i] = s ? x : y;
+                x = bi[k];
+                y = bi[i];
+                bi[k] = s ? y : x;
+                bi[i] = s ? x : y;
+            }
         }
     }
 #pragma unroll
@@ -327,9 +356,9 @@ struct SmallCell {
             }
             set(F_LAST, last);
         }
-        ih = 1.0 / h;
+        ih = rcp(h);
 #pragma unroll
-        for (int r = 0; r < M; ++r) isc[r] = 1.0 / (P.atol + P.rtol * __builtin_fabs(y[r]));
+        for (int r = 0; r < M; ++r) isc[r] = rcp(P.atol + P.rtol * __builtin_fabs(y[r]));
         if (FIXED || has(F_JSTALE)) {
             double J[M][M];
             md.jac(y, J);
@@ -355,7 +384,7 @@ struct SmallCell {
          * step continued to the new stage points (nodes s = -1, c1-1, c2-1, 0
          * in units of h_old; values -z3, z1 - z3, z2 - z3, 0), then W = T^-1 Z. */
         if (has(F_OLD)) {
-            const double r = h / h_old;
+            const double r = h * rcp(h_old);
             const double s1 = -1.0, s2 = radau::C1 - 1.0, s3 = radau::C2 - 1.0;
             const double cs[3] = {radau::C1 * r, radau::C2 * r, r};
             double Lw[3][3];
@@ -532,8 +561,9 @@ struct SmallCell {
         }
         if (!finite_d(err)) { status = ST_NONFINITE; phase = PH_IDLE; return; }
         ++nstep;
-        const double kmx = (double)P.kmax;
-        const double fac = 0.9 * (2.0 * kmx + 1.0) / (2.0 * kmx + (double)k);
+        const double fac = k <= kMaxFacTable
+                               ? P.fac[k]
+                               : 0.9 * (2.0 * P.kmax + 1.0) / (2.0 * P.kmax + (double)k);
         const double qerr = __builtin_sqrt(__builtin_sqrt(err));
         const double ratio = (err == 0.0) ? 8.0 : fmin(8.0, fmax(0.2, fac / qerr));
         double h_new = h * ratio;
@@ -578,8 +608,8 @@ struct SmallCell {
             flags = (flags & ~(F_FIRST | F_REJECT | F_JATY0 | F_JSTALE)) | F_OLD | F_ACC |
                     (keep_j ? 0u : F_JSTALE);
             if (keep_j) {
-                const double qq = h_new / h;
-                if (qq >= 1.0 && qq <= 1.2) h_new = h;
+                /* h_new / h in [1, 1.2] */
+                if (h_new >= h && h_new <= 1.2 * h) h_new = h;
             }
             const double hn = fmin(h_new, P.dt - t);
             if (hn != h) flags &= ~F_LUOK;

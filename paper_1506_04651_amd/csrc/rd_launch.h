@@ -11,8 +11,12 @@ namespace rd {
 /* Per-call integration constants (tolerances already transformed). */
 struct StepParams {
     double dt, rtol, atol, newton_tol, h0, h_min;
+    /* step-size safety factor by Newton iterations used, computed on the
+     * host: fac[k] = 0.9 (2 kmax + 1) / (2 kmax + k), k = 0..kMaxTable */
+    double fac[8];
     int32_t max_steps, kmax, fixed_steps, m; /* m: species per cell */
 };
+constexpr int kMaxFacTable = 7;
 
 struct LaunchArgs {
     double* states;                 /* [m][n] device, in place                  */
