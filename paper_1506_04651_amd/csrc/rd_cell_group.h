@@ -70,7 +70,7 @@ struct GroupCell {
     int q;
     bool act;         /* q < m */
     /* per-cell scalars, replicated across the group */
-    double t, h, ih, h_old, h_acc, qerr_acc, eta, nprev;
+    double t, h, ih, h_old, ih_acc, qerr_acc, eta, inprev;
     unsigned flags;
     int phase, status, k, nsing, outcome;
     int nstep, naccept, nreject, nfev, njac, ndec, nsol, nnewt;
@@ -102,7 +102,7 @@ struct GroupCell {
         const bool fin = grp_bits(finite_d(y) && finite_d(f0)) == 0xFFFFu;
         t = 0.0;
         h = P.fixed_steps > 0 ? P.dt / P.fixed_steps : fmin(P.h0 > 0.0 ? P.h0 : P.dt, P.dt);
-        h_old = h_acc = qerr_acc = nprev = 0.0;
+        h_old = ih_acc = qerr_acc = inprev = 0.0;
         eta = 1.0;
         k = 0;
         nsing = 0;
@@ -351,7 +351,7 @@ struct GroupCell {
         w2 = radau::TI21 * za + radau::TI22 * zb + radau::TI23 * zc;
         w3 = radau::TI31 * za + radau::TI32 * zb + radau::TI33 * zc;
         k = 0;
-        nprev = 0.0;
+        inprev = 0.0;
         phase = PH_NEWTON;
     }
 
@@ -395,14 +395,14 @@ struct GroupCell {
         const double dz3 = d1 + d2;
         const double s1 = dz1 * isc, s2 = dz2 * isc, s3 = dz3 * isc;
         const double acc = grp_sum(s1 * s1 + s2 * s2 + s3 * s3);
-        const double nk = __builtin_sqrt(acc * inv3m);
+        const double nk = sqrt_f(acc * inv3m);
         if (!finite_d(nk)) return NW_FAILED;
         const double tol = P.newton_tol;
         if (k >= 2) {
-            const double th = nk / nprev;
+            const double th = nk * inprev;
             if (th >= 0.99) return NW_FAILED;
             const double om = 1.0 - th;
-            eta = th / om;
+            eta = th * rcp_nr(om);
             double tp = 1.0;
             for (int j = 0; j < P.kmax - k; ++j) tp *= th;
             if (tp * nk > tol * om) return NW_FAILED;
@@ -411,7 +411,7 @@ struct GroupCell {
             set(F_KEEPJ, true);
         }
         if (eta * nk <= tol) return NW_CONVERGED;
-        nprev = nk;
+        inprev = rcp(nk); /* nk > 0: nk == 0 converges above */
         return k >= P.kmax ? NW_FAILED : NW_CONTINUE;
     }
 
@@ -423,7 +423,7 @@ struct GroupCell {
         ++nsol;
         e = (double)v;
         const double s = e * isc;
-        return __builtin_sqrt(grp_sum(s * s) * invm);
+        return sqrt_f(grp_sum(s * s) * invm);
     }
 
     template <bool FIXED>
@@ -442,7 +442,7 @@ struct GroupCell {
             flags |= F_OLD;
             if (grp_bits(finite_d(y)) != 0xFFFFu) { status = ST_NONFINITE; phase = PH_IDLE; return; }
             h_old = h;
-            eta = pow(fmax(eta, UROUND), 0.8);
+            eta = pow08(fmax(eta, UROUND));
             phase = (naccept >= P.fixed_steps) ? PH_IDLE : PH_START;
             return;
         }
@@ -468,14 +468,16 @@ struct GroupCell {
         const double fac = k <= kMaxFacTable
                                ? P.fac[k]
                                : 0.9 * (2.0 * P.kmax + 1.0) / (2.0 * P.kmax + (double)k);
-        const double qerr = __builtin_sqrt(__builtin_sqrt(err));
-        const double ratio = (err == 0.0) ? 8.0 : fmin(8.0, fmax(0.2, fac / qerr));
+        /* s = err^(-1/4); the classical factor is fac / err^(1/4) = fac s */
+        const double s = rroot4(err == 0.0 ? 1.0 : err);
+        const double ratio = (err == 0.0) ? 8.0 : fmin(8.0, fmax(0.2, fac * s));
         double h_new = h * ratio;
         if (err < 1.0) {
             if (has(F_ACC)) {
+                /* predictive: fac (h / h_acc) err_acc^(1/4) / err^(1/2) */
                 const double r2 = (err == 0.0)
                     ? 8.0
-                    : fmin(8.0, fmax(0.2, fac * (h / h_acc) * qerr_acc / (qerr * qerr)));
+                    : fmin(8.0, fmax(0.2, fac * (h * ih_acc) * qerr_acc * (s * s)));
                 h_new = fmin(h_new, h * r2);
             }
             const double zz1 = radau::T11 * w1 + radau::T12 * w2 + radau::T13 * w3;
@@ -490,8 +492,9 @@ struct GroupCell {
                 phase = PH_IDLE;
                 return;
             }
-            h_acc = h;
-            qerr_acc = __builtin_sqrt(__builtin_sqrt(fmax(err, 1e-2)));
+            ih_acc = ih;
+            /* max(err, 1e-2)^(1/4); (1e-2)^(1/4) = sqrt(0.1) */
+            qerr_acc = err >= 1e-2 ? rcp_nr(s) : 0.31622776601683794;
             y = y1;
             f0 = f1;
             z1o = zz1;
@@ -499,7 +502,7 @@ struct GroupCell {
             z3o = zz3;
             t = has(F_LAST) ? P.dt : t + h;
             h_old = h;
-            eta = pow(fmax(eta, UROUND), 0.8);
+            eta = pow08(fmax(eta, UROUND));
             ++naccept;
             if (has(F_REJECT)) h_new = fmin(h_new, h);
             const bool keep_j = has(F_KEEPJ);

@@ -32,6 +32,7 @@
 #include <stdint.h>
 
 #include "rd_constants.h"
+#include "rd_fastmath.h"
 #include "rd_launch.h"
 #include "rd_models.h"
 
@@ -50,17 +51,6 @@ constexpr double UROUND = 2.220446049250313e-16;
 
 __device__ __forceinline__ bool finite_d(double x) { return __builtin_isfinite(x); }
 
-/* 1/a: hardware reciprocal estimate refined by two Newton-Raphson steps
- * (error well below one ulp of the correctly rounded quotient for normal a);
- * zero, infinite and denormal a take the IEEE division. */
-__device__ __forceinline__ double rcp(double a) {
-    double r = __builtin_amdgcn_rcp(a);
-    r = __builtin_fma(__builtin_fma(-a, r, 1.0), r, r);
-    r = __builtin_fma(__builtin_fma(-a, r, 1.0), r, r);
-    const double aa = __builtin_fabs(a);
-    return (aa >= 2.2250738585072014e-308 && aa <= 1e300) ? r : 1.0 / a;
-}
-__device__ __forceinline__ float rcp(float a) { return 1.0f / a; }
 __device__ __forceinline__ float fabs_t(float x) { return __builtin_fabsf(x); }
 __device__ __forceinline__ double fabs_t(double x) { return __builtin_fabs(x); }
 
@@ -273,7 +263,7 @@ struct SmallCell {
     double y[M], f0[M], isc[M];
     double w[3][M];
     LT e1[M][M], e2r[M][M], e2i[M][M];
-    double t, h, ih, h_old, h_acc, qerr_acc, eta, nprev;
+    double t, h, ih, h_old, ih_acc, qerr_acc, eta, inprev;
     unsigned p1, p2, flags;
     int phase, status, k, nsing, outcome;
     /* counters (paper Appendix A: f evaluations per node) */
@@ -297,7 +287,7 @@ struct SmallCell {
         for (int r = 0; r < M; ++r) fin = fin && finite_d(y[r]) && finite_d(f0[r]);
         t = 0.0;
         h = P.fixed_steps > 0 ? P.dt / P.fixed_steps : fmin(P.h0 > 0.0 ? P.h0 : P.dt, P.dt);
-        h_old = h_acc = qerr_acc = nprev = 0.0;
+        h_old = ih_acc = qerr_acc = inprev = 0.0;
         eta = 1.0;
         k = 0;
         nsing = 0;
@@ -414,7 +404,7 @@ struct SmallCell {
                 for (int q = 0; q < M; ++q) w[i][q] = 0.0;
         }
         k = 0;
-        nprev = 0.0;
+        inprev = 0.0;
         phase = PH_NEWTON;
     }
 
@@ -476,7 +466,7 @@ struct SmallCell {
             const double s1 = dz1 * isc[q], s2 = dz2 * isc[q], s3 = dz3 * isc[q];
             acc += s1 * s1 + s2 * s2 + s3 * s3;
         }
-        const double nk = __builtin_sqrt(acc * (1.0 / (3 * M)));
+        const double nk = sqrt_f(acc * (1.0 / (3 * M)));
         if (!finite_d(nk)) return NW_FAILED;
         const double tol = P.newton_tol;
         if (k >= 2) {
@@ -484,10 +474,10 @@ struct SmallCell {
              * theta / (1 - theta); too slow if theta^(kmax-k) / (1 - theta)
              * n_k > tol, tested as theta^(kmax-k) n_k > tol (1 - theta) since
              * 1 - theta > 0.01 here */
-            const double th = nk / nprev;
+            const double th = nk * inprev;
             if (th >= 0.99) return NW_FAILED;
             const double om = 1.0 - th;
-            eta = th / om;
+            eta = th * rcp_nr(om);
             double tp = 1.0;
             for (int j = 0; j < P.kmax - k; ++j) tp *= th;
             if (tp * nk > tol * om) return NW_FAILED;
@@ -496,7 +486,8 @@ struct SmallCell {
             set(F_KEEPJ, true);
         }
         if (eta * nk <= tol) return NW_CONVERGED;
-        nprev = nk;
+        /* nk > 0 here (nk == 0 converges above) */
+        inprev = rcp(nk);
         return k >= P.kmax ? NW_FAILED : NW_CONTINUE;
     }
 
@@ -519,7 +510,7 @@ struct SmallCell {
             const double s = e[q] * isc[q];
             acc += s * s;
         }
-        return __builtin_sqrt(acc * (1.0 / M));
+        return sqrt_f(acc * (1.0 / M));
     }
 
     /* After the Newton loop ends: error test, step-size control, accept or
@@ -536,7 +527,7 @@ struct SmallCell {
             for (int q = 0; q < M; ++q) fin = fin && finite_d(y[q]);
             if (!fin) { status = ST_NONFINITE; phase = PH_IDLE; return; }
             h_old = h;
-            eta = pow(fmax(eta, UROUND), 0.8);
+            eta = pow08(fmax(eta, UROUND));
             phase = (naccept >= P.fixed_steps) ? PH_IDLE : PH_START;
             return;
         }
@@ -564,14 +555,16 @@ struct SmallCell {
         const double fac = k <= kMaxFacTable
                                ? P.fac[k]
                                : 0.9 * (2.0 * P.kmax + 1.0) / (2.0 * P.kmax + (double)k);
-        const double qerr = __builtin_sqrt(__builtin_sqrt(err));
-        const double ratio = (err == 0.0) ? 8.0 : fmin(8.0, fmax(0.2, fac / qerr));
+        /* s = err^(-1/4); the classical factor is fac / err^(1/4) = fac s */
+        const double s = rroot4(err == 0.0 ? 1.0 : err);
+        const double ratio = (err == 0.0) ? 8.0 : fmin(8.0, fmax(0.2, fac * s));
         double h_new = h * ratio;
         if (err < 1.0) {
             if (has(F_ACC)) {
+                /* predictive: fac (h / h_acc) err_acc^(1/4) / err^(1/2) */
                 const double r2 = (err == 0.0)
                     ? 8.0
-                    : fmin(8.0, fmax(0.2, fac * (h / h_acc) * qerr_acc / (qerr * qerr)));
+                    : fmin(8.0, fmax(0.2, fac * (h * ih_acc) * qerr_acc * (s * s)));
                 h_new = fmin(h_new, h * r2);
             }
             double zs[3][M];
@@ -589,8 +582,9 @@ struct SmallCell {
 #pragma unroll
             for (int q = 0; q < M; ++q) fin = fin && finite_d(y1[q]) && finite_d(f1[q]);
             if (!fin) { status = ST_NONFINITE; phase = PH_IDLE; return; }
-            h_acc = h;
-            qerr_acc = __builtin_sqrt(__builtin_sqrt(fmax(err, 1e-2)));
+            ih_acc = ih;
+            /* max(err, 1e-2)^(1/4); (1e-2)^(1/4) = sqrt(0.1) */
+            qerr_acc = err >= 1e-2 ? rcp_nr(s) : 0.31622776601683794;
 #pragma unroll
             for (int q = 0; q < M; ++q) {
                 y[q] = y1[q];
@@ -601,7 +595,7 @@ struct SmallCell {
             }
             t = has(F_LAST) ? P.dt : t + h;
             h_old = h;
-            eta = pow(fmax(eta, UROUND), 0.8);
+            eta = pow08(fmax(eta, UROUND));
             ++naccept;
             if (has(F_REJECT)) h_new = fmin(h_new, h);
             const bool keep_j = has(F_KEEPJ);

@@ -1,0 +1,101 @@
+/*
+ * rd_fastmath.h -- short FP64 forms of the few non-polynomial operations the
+ * step control needs (reciprocal, square root, err^(-1/4), x^0.8).
+ *
+ * Each takes a hardware estimate (v_rcp_f64, v_rsq_f64, or the FP32
+ * v_log_f32 / v_exp_f32 pair) and refines it with Newton steps in FP64, which
+ * converge quadratically; two steps from an estimate good to ~1e-7 leave an
+ * error of a few units in the last place, the size of the rounding
+ * differences that already separate any two orderings of the same arithmetic.
+ * Arguments outside the range where the estimate is safe (zero, denormal,
+ * huge, non-finite) take the library operation instead; that branch runs only
+ * when some lane of the wave needs it.
+ */
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace rd {
+
+constexpr double kFastLo = 1e-280, kFastHi = 1e280; /* refined forms valid inside */
+constexpr float kSeedLo = 1e-30f, kSeedHi = 1e30f;  /* FP32 seeds valid inside */
+
+/* 1/a for |a| in [kFastLo, kFastHi]: v_rcp_f64 and two Newton steps
+ * r <- r + r (1 - a r). */
+__device__ __forceinline__ double rcp_nr(double a) {
+    double r = __builtin_amdgcn_rcp(a);
+    r = __builtin_fma(__builtin_fma(-a, r, 1.0), r, r);
+    r = __builtin_fma(__builtin_fma(-a, r, 1.0), r, r);
+    return r;
+}
+
+__device__ __forceinline__ double rcp(double a) {
+    double r = rcp_nr(a);
+    const double aa = __builtin_fabs(a);
+    const bool ok = aa >= kFastLo && aa <= kFastHi;
+    if (__ballot(!ok) != 0ull) r = ok ? r : 1.0 / a;
+    return r;
+}
+/* FP32: v_rcp_f32 and one Newton step, IEEE division outside [1e-36, 1e36]. */
+__device__ __forceinline__ float rcp(float a) {
+    float r = __builtin_amdgcn_rcpf(a);
+    r = __builtin_fmaf(__builtin_fmaf(-a, r, 1.0f), r, r);
+    const float aa = __builtin_fabsf(a);
+    const bool ok = aa >= 1e-36f && aa <= 1e36f;
+    if (__ballot(!ok) != 0ull) r = ok ? r : 1.0f / a;
+    return r;
+}
+
+/* sqrt(x), x >= 0: v_rsq_f64 refined twice (r <- r + r (1 - x r^2) / 2), then
+ * s = x r with one residual correction s <- s + (r / 2) (x - s^2). */
+__device__ __forceinline__ double sqrt_nr(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    r = __builtin_fma(__builtin_fma(-hx * r, r, 0.5), r, r);
+    r = __builtin_fma(__builtin_fma(-hx * r, r, 0.5), r, r);
+    double s = x * r;
+    s = __builtin_fma(__builtin_fma(-s, s, x), 0.5 * r, s);
+    return s;
+}
+__device__ __forceinline__ double sqrt_f(double x) {
+    double s = sqrt_nr(x);
+    const bool ok = x >= kFastLo && x <= kFastHi;
+    if (__ballot(!ok) != 0ull) s = ok ? s : __builtin_sqrt(x);
+    return s;
+}
+
+/* x^(-1/4), x > 0: FP32 seed 2^(-log2(x)/4), then two Newton steps on
+ * y^-4 = x:  y <- y + (y / 4) (1 - x y^4). */
+__device__ __forceinline__ double rroot4(double x) {
+    const float xf = (float)x;
+    double y = (double)__builtin_amdgcn_exp2f(-0.25f * __builtin_amdgcn_logf(xf));
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double y2 = y * y;
+        const double e = __builtin_fma(-x * y2, y2, 1.0);
+        y = __builtin_fma(0.25 * y, e, y);
+    }
+    const bool ok = x >= (double)kSeedLo && x <= (double)kSeedHi;
+    if (__ballot(!ok) != 0ull) y = ok ? y : 1.0 / __builtin_sqrt(__builtin_sqrt(x));
+    return y;
+}
+
+/* x^p with p the double nearest 0.8 (= 4/5 + 2^-53 * 2/5), x > 0: FP32 seed
+ * 2^(0.8 log2 x), two Newton steps on y^5 = x^4 (y <- 0.8 y + 0.2 (x/y)^4),
+ * which give x^(4/5), then the factor x^(p - 4/5) = 1 + (p - 4/5) ln x. */
+__device__ __forceinline__ double pow08(double x) {
+    constexpr double kDeltaLn2 = 0.4 / 9007199254740992.0 * 0.6931471805599453; /* (p - 4/5) ln 2 */
+    const float lg = __builtin_amdgcn_logf((float)x);
+    double y = (double)__builtin_amdgcn_exp2f(0.8f * lg);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double r = x * rcp_nr(y);
+        const double r2 = r * r;
+        y = __builtin_fma(0.2 * r2, r2, 0.8 * y);
+    }
+    y = __builtin_fma(y, kDeltaLn2 * (double)lg, y);
+    const bool ok = x >= (double)kSeedLo && x <= (double)kSeedHi;
+    if (__ballot(!ok) != 0ull) y = ok ? y : pow(x, 0.8);
+    return y;
+}
+
+}  // namespace rd
