@@ -11,7 +11,9 @@
  *  - f(u): u_j reaches every lane of the group by DPP row broadcast; the
  *    model's rows (shared by all cells) are read from LDS.
  *  - LU with partial pivoting across lanes: at column k the group finds the
- *    largest |a_ik| (i >= k) by a butterfly max; rows are exchanged between
+ *    largest |a_ik| (i > k) by a DPP butterfly max over an ordering key of the
+ *    magnitude (pivot within a factor 1 + 2^-20 of the largest in FP64, exact
+ *    in FP32); rows are exchanged between
  *    lanes only when that beats the diagonal (the exchange is skipped for the
  *    whole wave when no group needs it), and row k is broadcast by DPP to the
  *    lanes below it.  After factorization lane k holds the k-th pivot row,
@@ -37,6 +39,8 @@ namespace rd {
 
 __device__ __forceinline__ float absv(float x) { return __builtin_fabsf(x); }
 __device__ __forceinline__ double absv(double x) { return __builtin_fabs(x); }
+__device__ __forceinline__ float fmaf_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaf_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 /* LDS table of the model, zero padded to 16 x 16: row q holds K[q][0..16)
  * then G[q][0..16); the stride is padded so the 16 rows fall in different
@@ -143,7 +147,9 @@ struct GroupCell {
         return act ? v : 0.0;
     }
 
-    /* ---- LU of E1 (real) with partial pivoting across the group ---- */
+    /* ---- LU of E1 (real) with partial pivoting across the group ----
+     * Lanes that do not eliminate at step kk carry a zero multiplier, so the
+     * row update a_j <- a_j - l r_j runs in every lane without a select. */
     __device__ __forceinline__ bool lu_real(LT (&a)[M], int& org) {
         bool ok = true;
         org = q;
@@ -151,12 +157,12 @@ struct GroupCell {
         for (int kk = 0; kk < M; ++kk) {
             if (kk < m) {
                 const bool below = act && q > kk;
-                const LT mag = below ? absv(a[kk]) : LT(0);
-                const LT gmax = grp_max(mag);
+                const unsigned key = below ? mag_key(absv(a[kk])) : 0u;
+                const unsigned kmax = grp_max_u(key);
                 LT akk = bcast_dyn(a[kk], kk);
-                const bool need = gmax > absv(akk);
+                const bool need = kmax > mag_key(absv(akk));
                 if (__ballot(need) != 0ull) {
-                    const unsigned cand = grp_bits(below && mag == gmax);
+                    const unsigned cand = grp_bits(below && key == kmax);
                     const int p = (need && cand) ? __ffs(cand) - 1 : kk;
                     const int src = (q == kk) ? p : (q == p ? kk : q);
 #pragma unroll
@@ -166,13 +172,10 @@ struct GroupCell {
                 }
                 ok = ok && (akk != LT(0));
                 const LT inv = rcp(akk);
-                const LT l = a[kk] * inv;
+                const LT l = below ? a[kk] * inv : LT(0);
                 a[kk] = (q == kk) ? inv : (below ? l : a[kk]);
 #pragma unroll
-                for (int j = kk + 1; j < M; ++j) {
-                    const LT rkj = bcast_dyn(a[j], kk);
-                    a[j] = below ? a[j] - l * rkj : a[j];
-                }
+                for (int j = kk + 1; j < M; ++j) a[j] = fmaf_t(-l, bcast_dyn(a[j], kk), a[j]);
             }
         }
         return ok;
@@ -186,12 +189,12 @@ struct GroupCell {
         for (int kk = 0; kk < M; ++kk) {
             if (kk < m) {
                 const bool below = act && q > kk;
-                const LT mag = below ? ar[kk] * ar[kk] + ai[kk] * ai[kk] : LT(0);
-                const LT gmax = grp_max(mag);
+                const unsigned key = below ? mag_key(ar[kk] * ar[kk] + ai[kk] * ai[kk]) : 0u;
+                const unsigned kmax = grp_max_u(key);
                 LT pr = bcast_dyn(ar[kk], kk), pi = bcast_dyn(ai[kk], kk);
-                const bool need = gmax > pr * pr + pi * pi;
+                const bool need = kmax > mag_key(pr * pr + pi * pi);
                 if (__ballot(need) != 0ull) {
-                    const unsigned cand = grp_bits(below && mag == gmax);
+                    const unsigned cand = grp_bits(below && key == kmax);
                     const int p = (need && cand) ? __ffs(cand) - 1 : kk;
                     const int src = (q == kk) ? p : (q == p ? kk : q);
 #pragma unroll
@@ -207,16 +210,15 @@ struct GroupCell {
                 const LT rn = rcp(pr * pr + pi * pi);
                 const LT ir = pr * rn, ii = -pi * rn;
                 const LT xr = ar[kk], xi = ai[kk];
-                const LT lr = xr * ir - xi * ii, li = xr * ii + xi * ir;
+                const LT lr = below ? xr * ir - xi * ii : LT(0);
+                const LT li = below ? xr * ii + xi * ir : LT(0);
                 ar[kk] = (q == kk) ? ir : (below ? lr : xr);
                 ai[kk] = (q == kk) ? ii : (below ? li : xi);
 #pragma unroll
                 for (int j = kk + 1; j < M; ++j) {
                     const LT ur = bcast_dyn(ar[j], kk), ui = bcast_dyn(ai[j], kk);
-                    const LT nr = ar[j] - (lr * ur - li * ui);
-                    const LT ni = ai[j] - (lr * ui + li * ur);
-                    ar[j] = below ? nr : ar[j];
-                    ai[j] = below ? ni : ai[j];
+                    ar[j] = fmaf_t(-lr, ur, fmaf_t(li, ui, ar[j]));
+                    ai[j] = fmaf_t(-lr, ui, fmaf_t(-li, ur, ai[j]));
                 }
             }
         }
@@ -225,7 +227,7 @@ struct GroupCell {
 
     /* solve E1 x = b; lane q holds b_q on entry, x_q on return */
     __device__ __forceinline__ LT solve_real(LT b) const {
-        b = grp_shfl(b, org1);
+        if (__ballot(org1 != q) != 0ull) b = grp_shfl(b, org1);
 #pragma unroll
         for (int kk = 0; kk < M - 1; ++kk) {
             if (kk < m - 1) {
@@ -245,8 +247,10 @@ struct GroupCell {
     }
 
     __device__ __forceinline__ void solve_cplx(LT& br, LT& bi) const {
-        br = grp_shfl(br, org2);
-        bi = grp_shfl(bi, org2);
+        if (__ballot(org2 != q) != 0ull) {
+            br = grp_shfl(br, org2);
+            bi = grp_shfl(bi, org2);
+        }
 #pragma unroll
         for (int kk = 0; kk < M - 1; ++kk) {
             if (kk < m - 1) {

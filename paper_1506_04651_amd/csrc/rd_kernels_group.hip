@@ -75,13 +75,15 @@ template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_group_onelaunch(LaunchArgs a, int m) {
     __shared__ double tab[GroupTable::DOUBLES];
+    __shared__ StepParams sP;
+    stage_params(sP, a.P);
     load_table<Model>(tab, a.params, m, BLOCK);
     const int64_t c = (int64_t)blockIdx.x * (BLOCK / kGroup) + threadIdx.x / kGroup;
     if (c >= a.n) return;
     GroupCell<Model, LT> cell;
     init_cell(cell, tab, m);
-    cell.load(a.P, a.states, a.n, c);
-    while (cell.phase != PH_IDLE) advance_group<Model, LT, FIXED, FSMIN>(cell, a.P);
+    cell.load(sP, a.states, a.n, c);
+    while (cell.phase != PH_IDLE) advance_group<Model, LT, FIXED, FSMIN>(cell, sP);
     cell.store(a.states, a.stats, a.n, c);
     if (cell.status != ST_OK && cell.q == 0) atomicAdd(a.nfail, 1ull);
 }
@@ -90,6 +92,8 @@ template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_group_persistent(LaunchArgs a, int m) {
     __shared__ double tab[GroupTable::DOUBLES];
+    __shared__ StepParams sP;
+    stage_params(sP, a.P);
     load_table<Model>(tab, a.params, m, BLOCK);
     GroupCell<Model, LT> cell;
     init_cell(cell, tab, m);
@@ -128,14 +132,14 @@ k_group_persistent(LaunchArgs a, int m) {
             if (need) {
                 if (pos < (unsigned long long)a.n) {
                     c = a.order ? (int64_t)a.order[pos] : (int64_t)pos;
-                    cell.load(a.P, a.states, a.n, c);
+                    cell.load(sP, a.states, a.n, c);
                 } else {
                     alive = false;
                 }
             }
         }
         if (__ballot(alive) == 0ull) break;
-        advance_group<Model, LT, FIXED, FSMIN>(cell, a.P);
+        advance_group<Model, LT, FIXED, FSMIN>(cell, sP);
     }
 }
 

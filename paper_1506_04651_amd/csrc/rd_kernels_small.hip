@@ -59,13 +59,18 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE,
 k_onelaunch(LaunchArgs a) {
     using L = SmallLds<Model::M>;
     __shared__ double sh[L::ROWS * BLOCK];
+    __shared__ StepParams sP;
+    stage_params(sP, a.P);
     const int64_t c = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (c >= a.n) return;
     const Model md(a.params);
     SmallCell<Model, LT, BLOCK> cell;
     cell.lds.base = sh + threadIdx.x;
-    cell.load(md, a.P, a.states, a.n, c);
-    while (cell.phase != PH_IDLE) advance<Model, LT, FIXED, BLOCK, FSMIN>(cell, md, a.P);
+    cell.load(md, sP, a.states, a.n, c);
+    while (cell.phase != PH_IDLE) {
+        __asm__ volatile("" ::: "memory"); /* re-read sP from LDS each pass */
+        advance<Model, LT, FIXED, BLOCK, FSMIN>(cell, md, sP);
+    }
     cell.store(a.states, a.stats, a.n, c);
     if (cell.status != ST_OK) atomicAdd(a.nfail, 1ull);
 }
@@ -81,6 +86,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE,
 k_persistent(LaunchArgs a) {
     using L = SmallLds<Model::M>;
     __shared__ double sh[L::ROWS * BLOCK];
+    __shared__ StepParams sP;
+    stage_params(sP, a.P);
     const Model md(a.params);
     SmallCell<Model, LT, BLOCK> cell;
     cell.lds.base = sh + threadIdx.x;
@@ -121,14 +128,15 @@ k_persistent(LaunchArgs a) {
             if (need) {
                 if (pos < (unsigned long long)a.n) {
                     c = a.order ? (int64_t)a.order[pos] : (int64_t)pos;
-                    cell.load(md, a.P, a.states, a.n, c);
+                    cell.load(md, sP, a.states, a.n, c);
                 } else {
                     alive = false;
                 }
             }
         }
         if (__ballot(alive) == 0ull) break;
-        advance<Model, LT, FIXED, BLOCK, FSMIN>(cell, md, a.P);
+        __asm__ volatile("" ::: "memory"); /* re-read sP from LDS each pass */
+        advance<Model, LT, FIXED, BLOCK, FSMIN>(cell, md, sP);
     }
 }
 

@@ -18,6 +18,18 @@ struct StepParams {
 };
 constexpr int kMaxFacTable = 7;
 
+/* Copy the step parameters into the block's LDS (every thread must call it).
+ * Kernels read them from there on each pass instead of holding the whole
+ * block in scalar registers across the scheduling loop. */
+__device__ __forceinline__ void stage_params(StepParams& dst, const StepParams& src) {
+    constexpr int W = (int)(sizeof(StepParams) / sizeof(int32_t));
+    static_assert(sizeof(StepParams) % sizeof(int32_t) == 0, "word-sized StepParams");
+    const int32_t* s = reinterpret_cast<const int32_t*>(&src);
+    int32_t* d = reinterpret_cast<int32_t*>(&dst);
+    for (int i = threadIdx.x; i < W; i += blockDim.x) d[i] = s[i];
+    __syncthreads();
+}
+
 struct LaunchArgs {
     double* states;                 /* [m][n] device, in place                  */
     const int32_t* order;           /* claim order (persistent), or null        */
