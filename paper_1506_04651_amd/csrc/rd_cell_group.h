@@ -10,15 +10,20 @@
  *
  *  - f(u): u_j reaches every lane of the group by DPP row broadcast; the
  *    model's rows (shared by all cells) are read from LDS.
- *  - LU with partial pivoting across lanes: at column k the group finds the
- *    largest |a_ik| (i > k) by a DPP butterfly max over an ordering key of the
+ *  - E1 and E2 are inverted explicitly, by Gauss-Jordan elimination with
+ *    partial pivoting across lanes: at column k the group finds the largest
+ *    |a_ik| (i > k) by a DPP butterfly max over an ordering key of the
  *    magnitude (pivot within a factor 1 + 2^-20 of the largest in FP64, exact
- *    in FP32); rows are exchanged between
- *    lanes only when that beats the diagonal (the exchange is skipped for the
- *    whole wave when no group needs it), and row k is broadcast by DPP to the
- *    lanes below it.  After factorization lane k holds the k-th pivot row,
- *    and `org` records which original row it came from (to permute the RHS).
- *  - triangular solves: 2 x m broadcast steps (forward, then backward).
+ *    in FP32); rows are exchanged between lanes only when that beats the
+ *    diagonal (the exchange is skipped for the whole wave when no group needs
+ *    it), and the pivot row is broadcast by DPP to all other lanes, which
+ *    eliminate column k from their rows.  The simplified Newton iteration
+ *    solves with the same two matrices several times per factorization, and
+ *    with the inverse each solve is one matrix-vector product (m broadcast
+ *    steps with every lane busy) instead of a forward and a backward
+ *    substitution in which the lanes outside the triangle idle.  The inverse
+ *    only changes how the Newton increments are rounded, not the iteration
+ *    they belong to.
  *  - norms: butterfly sums, bitwise identical in all lanes, so every lane of
  *    the group takes the same control decisions; the per-cell scalars (t, h,
  *    flags, counters) are replicated in the 16 lanes.
@@ -68,7 +73,8 @@ struct GroupCell {
 
     /* lane-q components */
     double y, f0, isc, w1, w2, w3, z1o, z2o, z3o, uJ, gJ;
-    LT e1[M], e2r[M], e2i[M];
+    LT e1[M], e2r[M], e2i[M]; /* rows of the Gauss-Jordan inverses (see gj_real) */
+    LT d1, d2r, d2i;          /* reciprocal pivots */
     int org1, org2;
     const double* kg; /* LDS row q: K then G */
     int q;
@@ -147,12 +153,19 @@ struct GroupCell {
         return act ? v : 0.0;
     }
 
-    /* ---- LU of E1 (real) with partial pivoting across the group ----
-     * Lanes that do not eliminate at step kk carry a zero multiplier, so the
-     * row update a_j <- a_j - l r_j runs in every lane without a select. */
-    __device__ __forceinline__ bool lu_real(LT (&a)[M], int& org) {
+    /* ---- inverse of E1 (real) by Gauss-Jordan with partial pivoting ----
+     * Step kk: the pivot row (after the exchange, lane kk) is left unscaled;
+     * every other lane q subtracts f_q = a_q,kk / p_kk times it from its own
+     * row (f = 0 in the pivot lane, so the update runs in all lanes without a
+     * select) and stores -f_q in column kk, the pivot lane stores 1 there and
+     * keeps d = 1 / p_kk.  At the end lane q holds row q of R with
+     * (P E)^{-1} = diag(d) R, P the row exchanges (org: source row of lane q).
+     * The pivots, and so the singularity test, are those of the LU
+     * factorization with the same pivoting. */
+    __device__ __forceinline__ bool gj_real(LT (&a)[M], LT& d, int& org) {
         bool ok = true;
         org = q;
+        d = LT(0);
 #pragma unroll
         for (int kk = 0; kk < M; ++kk) {
             if (kk < m) {
@@ -172,19 +185,23 @@ struct GroupCell {
                 }
                 ok = ok && (akk != LT(0));
                 const LT inv = rcp(akk);
-                const LT l = below ? a[kk] * inv : LT(0);
-                a[kk] = (q == kk) ? inv : (below ? l : a[kk]);
+                const bool piv = q == kk;
+                const LT f = piv ? LT(0) : a[kk] * inv;
 #pragma unroll
-                for (int j = kk + 1; j < M; ++j) a[j] = fmaf_t(-l, bcast_dyn(a[j], kk), a[j]);
+                for (int j = 0; j < M; ++j)
+                    if (j != kk) a[j] = fmaf_t(-f, bcast_dyn(a[j], kk), a[j]);
+                a[kk] = piv ? LT(1) : -f;
+                d = piv ? inv : d;
             }
         }
         return ok;
     }
 
-    /* ---- LU of E2 (complex) ---- */
-    __device__ __forceinline__ bool lu_cplx(LT (&ar)[M], LT (&ai)[M], int& org) {
+    /* ---- inverse of E2 (complex), same scheme in complex arithmetic ---- */
+    __device__ __forceinline__ bool gj_cplx(LT (&ar)[M], LT (&ai)[M], LT& dr, LT& di, int& org) {
         bool ok = true;
         org = q;
+        dr = di = LT(0);
 #pragma unroll
         for (int kk = 0; kk < M; ++kk) {
             if (kk < m) {
@@ -208,42 +225,36 @@ struct GroupCell {
                 }
                 ok = ok && !(pr == LT(0) && pi == LT(0));
                 const LT rn = rcp(pr * pr + pi * pi);
-                const LT ir = pr * rn, ii = -pi * rn;
+                const LT ir = pr * rn, ii = -pi * rn; /* 1 / (pr + i pi) */
+                const bool piv = q == kk;
                 const LT xr = ar[kk], xi = ai[kk];
-                const LT lr = below ? xr * ir - xi * ii : LT(0);
-                const LT li = below ? xr * ii + xi * ir : LT(0);
-                ar[kk] = (q == kk) ? ir : (below ? lr : xr);
-                ai[kk] = (q == kk) ? ii : (below ? li : xi);
+                const LT fr = piv ? LT(0) : xr * ir - xi * ii;
+                const LT fi = piv ? LT(0) : xr * ii + xi * ir;
 #pragma unroll
-                for (int j = kk + 1; j < M; ++j) {
-                    const LT ur = bcast_dyn(ar[j], kk), ui = bcast_dyn(ai[j], kk);
-                    ar[j] = fmaf_t(-lr, ur, fmaf_t(li, ui, ar[j]));
-                    ai[j] = fmaf_t(-lr, ui, fmaf_t(-li, ur, ai[j]));
+                for (int j = 0; j < M; ++j) {
+                    if (j != kk) {
+                        const LT ur = bcast_dyn(ar[j], kk), ui = bcast_dyn(ai[j], kk);
+                        ar[j] = fmaf_t(-fr, ur, fmaf_t(fi, ui, ar[j]));
+                        ai[j] = fmaf_t(-fr, ui, fmaf_t(-fi, ur, ai[j]));
+                    }
                 }
+                ar[kk] = piv ? LT(1) : -fr;
+                ai[kk] = piv ? LT(0) : -fi;
+                dr = piv ? ir : dr;
+                di = piv ? ii : di;
             }
         }
         return ok;
     }
 
-    /* solve E1 x = b; lane q holds b_q on entry, x_q on return */
+    /* x = E1^{-1} b = diag(d) R (P b); lane q holds b_q on entry, x_q on return */
     __device__ __forceinline__ LT solve_real(LT b) const {
         if (__ballot(org1 != q) != 0ull) b = grp_shfl(b, org1);
+        LT acc = LT(0);
 #pragma unroll
-        for (int kk = 0; kk < M - 1; ++kk) {
-            if (kk < m - 1) {
-                const LT yk = bcast_dyn(b, kk);
-                b = (act && q > kk) ? b - e1[kk] * yk : b;
-            }
-        }
-#pragma unroll
-        for (int kk = M - 1; kk >= 0; --kk) {
-            if (kk < m) {
-                b = (q == kk) ? b * e1[kk] : b;
-                const LT xk = bcast_dyn(b, kk);
-                b = (q < kk) ? b - e1[kk] * xk : b;
-            }
-        }
-        return act ? b : LT(0);
+        for (int j = 0; j < M; ++j)
+            if (j < m) acc = fmaf_t(e1[j], bcast_dyn(b, j), acc);
+        return acc * d1;
     }
 
     __device__ __forceinline__ void solve_cplx(LT& br, LT& bi) const {
@@ -251,34 +262,17 @@ struct GroupCell {
             br = grp_shfl(br, org2);
             bi = grp_shfl(bi, org2);
         }
+        LT sr = LT(0), si = LT(0);
 #pragma unroll
-        for (int kk = 0; kk < M - 1; ++kk) {
-            if (kk < m - 1) {
-                const LT yr = bcast_dyn(br, kk), yi = bcast_dyn(bi, kk);
-                const LT lr = e2r[kk], li = e2i[kk];
-                const bool u = act && q > kk;
-                const LT nr = br - (lr * yr - li * yi), ni = bi - (lr * yi + li * yr);
-                br = u ? nr : br;
-                bi = u ? ni : bi;
+        for (int j = 0; j < M; ++j) {
+            if (j < m) {
+                const LT ur = bcast_dyn(br, j), ui = bcast_dyn(bi, j);
+                sr = fmaf_t(e2r[j], ur, fmaf_t(-e2i[j], ui, sr));
+                si = fmaf_t(e2r[j], ui, fmaf_t(e2i[j], ur, si));
             }
         }
-#pragma unroll
-        for (int kk = M - 1; kk >= 0; --kk) {
-            if (kk < m) {
-                const LT dr = e2r[kk], di = e2i[kk];
-                const bool d = q == kk;
-                const LT sr = br, si = bi;
-                br = d ? sr * dr - si * di : sr;
-                bi = d ? sr * di + si * dr : si;
-                const LT xr = bcast_dyn(br, kk), xi = bcast_dyn(bi, kk);
-                const bool u = q < kk;
-                const LT nr = br - (dr * xr - di * xi), ni = bi - (dr * xi + di * xr);
-                br = u ? nr : br;
-                bi = u ? ni : bi;
-            }
-        }
-        br = act ? br : LT(0);
-        bi = act ? bi : LT(0);
+        br = sr * d2r - si * d2i;
+        bi = sr * d2i + si * d2r;
     }
 
     __device__ __forceinline__ bool factor() {
@@ -291,8 +285,8 @@ struct GroupCell {
             e2r[j] = (LT)(d ? ar + mj : mj);
             e2i[j] = (LT)(d ? bi : 0.0);
         }
-        const bool ok1 = lu_real(e1, org1);
-        const bool ok2 = lu_cplx(e2r, e2i, org2);
+        const bool ok1 = gj_real(e1, d1, org1);
+        const bool ok2 = gj_cplx(e2r, e2i, d2r, d2i, org2);
         return ok1 && ok2;
     }
 
