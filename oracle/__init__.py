@@ -16,7 +16,7 @@ import numpy as np
 
 from .build import LIB, build_oracle
 
-OREGONATOR, KINETICS, NAGUMO, LINEAR, ROBERTSON = 1, 2, 3, 4, 5
+OREGONATOR, KINETICS, NAGUMO, LINEAR, ROBERTSON, BYTECODE = 1, 2, 3, 4, 5, 6
 NSTATS = 9
 STAT_NAMES = ("status", "nstep", "naccept", "nreject", "nfev", "njac", "ndec",
               "nsol", "nnewt")
@@ -31,7 +31,9 @@ class _Model(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("tol_transform", ctypes.c_int32), ("max_steps", ctypes.c_int32),
                 ("newton_max", ctypes.c_int32), ("fixed_steps", ctypes.c_int32),
-                ("h0", ctypes.c_double), ("h_min", ctypes.c_double)]
+                ("h0", ctypes.c_double), ("h_min", ctypes.c_double),
+                ("jacobian", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("h_cells", ctypes.POINTER(ctypes.c_double))]
 
 
 _lib = None
@@ -77,17 +79,19 @@ def _model(kind, m, params):
 
 
 def _options(tol_transform=1, max_steps=100000, newton_max=7, fixed_steps=0,
-             h0=0.0, h_min=0.0):
+             h0=0.0, h_min=0.0, jacobian=0, h_cells=None):
+    hp = _dptr(h_cells) if h_cells is not None else None
     return _Options(int(tol_transform), int(max_steps), int(newton_max),
-                    int(fixed_steps), float(h0), float(h_min))
+                    int(fixed_steps), float(h0), float(h_min), int(jacobian), 0, hp)
 
 
-def reaction_step(states, dt, rtol, atol, kind, params, nthreads=0, **opts):
+def reaction_step(states, dt, rtol, atol, kind, params, nthreads=0, h_cells=None, **opts):
     """Integrate every column of ``states`` ([m, n] float64) over [0, dt].
 
     Returns ``(y, stats, ret)``: the new states (a copy), the [9, n] int32
     counters, and the library's return value (number of failed cells, or a
-    negative call-level error).
+    negative call-level error).  ``h_cells`` (float64 [n], optional) is the
+    per-cell warm-start step size, updated in place.
     """
     lib = load()
     y = np.array(states, dtype=np.float64, order="C", copy=True)
@@ -96,7 +100,11 @@ def reaction_step(states, dt, rtol, atol, kind, params, nthreads=0, **opts):
     m, n = y.shape
     stats = np.zeros((NSTATS, n), dtype=np.int32)
     mdl, keep = _model(kind, m, params)
-    o = _options(**opts)
+    if h_cells is not None:
+        if not (isinstance(h_cells, np.ndarray) and h_cells.dtype == np.float64
+                and h_cells.flags.c_contiguous and h_cells.shape == (n,)):
+            raise ValueError("h_cells must be a contiguous float64 array of n values")
+    o = _options(h_cells=h_cells, **opts)
     ret = lib.rdo_reaction_step(
         _dptr(y), n, m, float(dt), float(rtol), float(atol), ctypes.byref(mdl),
         ctypes.byref(o), stats.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
@@ -124,11 +132,12 @@ def single_step(y0, h, rtol, atol, kind, params, tol_transform=1, newton_max=7):
     return y1, (float(err[0]), float(err[1])), int(info[0]), bool(info[1])
 
 
-def model_eval(kind, params, y):
-    """f(y) and the Jacobian J(y) ([m, m]) as the oracle's model code computes them."""
+def model_eval(kind, params, y, m=None):
+    """f(y) and the Jacobian J(y) ([m, m]) as the oracle's model code computes
+    them (bytecode models: forward differences)."""
     lib = load()
     y = np.ascontiguousarray(y, dtype=np.float64)
-    m = y.size
+    m = y.size if m is None else m
     f = np.zeros(m)
     J = np.zeros((m, m))
     mdl, keep = _model(kind, m, params)

@@ -91,6 +91,44 @@ struct Model {
     int kind;
     int m;
     std::vector<double> p;
+    bool fd = false; /* Jacobian by forward differences */
+
+    /* bytecode model: an interpreter of the documented register program
+     * (rdo.h), one instruction at a time */
+    void run_bytecode(const double* y, double* out) const {
+        double r[RDO_BC_REGS];
+        const int L = (int)p[0], C = (int)p[1];
+        for (int i = 0; i < m; ++i) r[i] = y[i];
+        for (int c = 0; c < C; ++c) r[m + c] = p[2 + c];
+        for (int k = 0; k < L; ++k) {
+            const double* ins = &p[2 + C + 4 * k];
+            const int op = (int)ins[0], d = (int)ins[1], a = (int)ins[2], b = (int)ins[3];
+            switch (op) {
+            case RDO_BC_ADD: r[d] = r[a] + r[b]; break;
+            case RDO_BC_SUB: r[d] = r[a] - r[b]; break;
+            case RDO_BC_MUL: r[d] = r[a] * r[b]; break;
+            case RDO_BC_DIV: r[d] = r[a] / r[b]; break;
+            case RDO_BC_NEG: r[d] = -r[a]; break;
+            case RDO_BC_EXP: r[d] = std::exp(r[a]); break;
+            case RDO_BC_LOG: r[d] = std::log(r[a]); break;
+            case RDO_BC_POW: r[d] = std::pow(r[a], r[b]); break;
+            case RDO_BC_OUT: out[d] = r[a]; break;
+            }
+        }
+    }
+
+    /* Forward-difference Jacobian at y, given fy = f(y):
+     * column j = (f(y + d_j e_j) - f(y)) / d_j, d_j = sqrt(u max(1e-5, |y_j|)) */
+    void jac_fd(const double* y, const double* fy, double* J) const {
+        std::vector<double> yp(y, y + m), fp(m);
+        for (int j = 0; j < m; ++j) {
+            const double dj = std::sqrt(2.220446049250313e-16 * std::max(1e-5, std::fabs(y[j])));
+            yp[j] = y[j] + dj;
+            f(yp.data(), fp.data());
+            for (int i = 0; i < m; ++i) J[i * m + j] = (fp[i] - fy[i]) / dj;
+            yp[j] = y[j];
+        }
+    }
 
     /* right-hand side f(y) */
     void f(const double* y, double* out) const {
@@ -134,6 +172,9 @@ struct Model {
             }
             break;
         }
+        case RDO_BYTECODE:
+            run_bytecode(y, out);
+            break;
         case RDO_ROBERTSON: {
             const double k1 = p[0], k2 = p[1], k3 = p[2];
             out[0] = -k1 * y[0] + k2 * y[1] * y[2];
@@ -186,6 +227,49 @@ struct Model {
     }
 };
 
+/* Validation of a bytecode program against the rules stated in rdo.h. */
+bool bytecode_from_abi(const rdo_model* mm, Model& out) {
+    const int m = mm->m;
+    if (m < 1 || m > 4 || !mm->params || mm->n_params < 2) return false;
+    const double* p = mm->params;
+    auto is_int = [](double v, double lo, double hi) {
+        return std::isfinite(v) && v == std::floor(v) && v >= lo && v <= hi;
+    };
+    if (!is_int(p[0], 1, 4096) || !is_int(p[1], 0, RDO_BC_REGS)) return false;
+    const int L = (int)p[0], C = (int)p[1];
+    if (m + C > RDO_BC_REGS) return false;
+    const int64_t need = 2 + (int64_t)C + 4LL * L;
+    if (mm->n_params < need) return false;
+    for (int c = 0; c < C; ++c)
+        if (!std::isfinite(p[2 + c])) return false;
+    bool written[RDO_BC_REGS] = {};
+    for (int i = 0; i < m + C; ++i) written[i] = true;
+    std::vector<int> outs(m, 0);
+    for (int k = 0; k < L; ++k) {
+        const double* ins = p + 2 + C + 4 * k;
+        if (!is_int(ins[0], RDO_BC_ADD, RDO_BC_OUT)) return false;
+        for (int f = 1; f < 4; ++f)
+            if (!is_int(ins[f], 0, RDO_BC_REGS - 1)) return false;
+        const int op = (int)ins[0], d = (int)ins[1], a = (int)ins[2], b = (int)ins[3];
+        const bool binary = op == RDO_BC_ADD || op == RDO_BC_SUB || op == RDO_BC_MUL ||
+                            op == RDO_BC_DIV || op == RDO_BC_POW;
+        if (!written[a] || (binary && !written[b])) return false;
+        if (op == RDO_BC_OUT) {
+            if (d >= m || outs[d]++) return false;
+        } else {
+            if (d < m + C) return false;
+            written[d] = true;
+        }
+    }
+    for (int i = 0; i < m; ++i)
+        if (outs[i] != 1) return false;
+    out.kind = RDO_BYTECODE;
+    out.m = m;
+    out.p.assign(p, p + need);
+    out.fd = true;
+    return true;
+}
+
 bool model_from_abi(const rdo_model* mm, Model& out) {
     if (!mm || mm->m < 1) return false;
     const int m = mm->m;
@@ -196,6 +280,7 @@ bool model_from_abi(const rdo_model* mm, Model& out) {
     case RDO_NAGUMO:     if (m != 1) return false; need = 1; break;
     case RDO_LINEAR:     need = (int64_t)m * m; break;
     case RDO_ROBERTSON:  if (m != 3) return false; need = 3; break;
+    case RDO_BYTECODE:   return bytecode_from_abi(mm, out);
     default: return false;
     }
     if (mm->n_params < need || !mm->params) return false;
@@ -290,6 +375,8 @@ struct Opts {
     double h0 = 0.0;
     double h_min = 0.0;
     int tol_transform = 1;
+    int jacobian = 0;
+    double* h_cells = nullptr;
 };
 
 /* ------------------------------------------------------------------------ */
@@ -433,12 +520,32 @@ public:
         return err;
     }
 
+    /* J at y (f0 = f(y)): analytic, or forward differences (m more f
+     * evaluations) */
+    void jacobian(const double* y, Stats& st) {
+        if (M.fd) {
+            M.jac_fd(y, f0.data(), J.data());
+            st.nfev += m;
+        } else {
+            M.jac(y, J.data());
+        }
+        st.njac++;
+    }
+
     void scale(const double* y0) {
         for (int r = 0; r < m; ++r) sc[r] = T.atol + T.rtol * std::fabs(y0[r]);
     }
 
-    /* Adaptive integration of one cell over [0, dt]; y is updated in place. */
-    void integrate(double* y, double dt, Stats& st) {
+    /* Adaptive integration of one cell over [0, dt]; y is updated in place.
+     * h_io: null, or the cell's warm-start step size (in: used as the first
+     * trial step when > 0; out: see rdo.h). */
+    void integrate(double* y, double dt, Stats& st, double* h_io = nullptr) {
+        double h_pre = 0.0;
+        integrate_(y, dt, st, h_pre, h_io && *h_io > 0.0 ? *h_io : 0.0);
+        if (h_io) *h_io = h_pre;
+    }
+
+    void integrate_(double* y, double dt, Stats& st, double& h_pre, double h_in) {
         const double h_min = O.h_min > 0.0 ? O.h_min : 1e-14 * dt;
         M.f(y, f0.data());
         st.nfev++;
@@ -447,11 +554,13 @@ public:
             return;
         }
         if (O.fixed_steps > 0) {
+            h_pre = dt / O.fixed_steps;
             fixed(y, dt, st);
             return;
         }
         double t = 0.0;
-        double h = std::min(O.h0 > 0.0 ? O.h0 : dt, dt);
+        double h = std::min(h_in > 0.0 ? h_in : (O.h0 > 0.0 ? O.h0 : dt), dt);
+        h_pre = h;
         bool first = true, reject = false;
         bool J_stale = true;   /* J must be recomputed before the next attempt */
         bool J_at_y0 = false;  /* J was evaluated at the current y0 */
@@ -465,14 +574,14 @@ public:
         int n_singular = 0;
 
         while (t < dt) {
+            h_pre = h;
             if (st.nstep >= O.max_steps) { st.status = RDO_MAXSTEPS; return; }
             if (h < h_min) { st.status = RDO_H_TOO_SMALL; return; }
             bool last = false;
             if (t + 1.0001 * h >= dt) { h = dt - t; last = true; }
             scale(y);
             if (J_stale) {
-                M.jac(y, J.data());
-                st.njac++;
+                jacobian(y, st);
                 J_stale = false;
                 J_at_y0 = true;
                 have_lu = false;
@@ -562,8 +671,7 @@ public:
         bool have_old = false;
         for (int s = 0; s < N; ++s) {
             scale(y);
-            M.jac(y, J.data());
-            st.njac++;
+            jacobian(y, st);
             st.ndec++;
             if (!factor(h)) { st.status = RDO_SINGULAR; return; }
             start_values(h, have_old, h);
@@ -601,8 +709,11 @@ bool options_from_abi(const rdo_options* o, Opts& out) {
     out.fixed_steps = o->fixed_steps;
     out.h0 = o->h0;
     out.h_min = o->h_min;
+    out.jacobian = o->jacobian;
+    out.h_cells = o->h_cells;
     if (out.max_steps < 1 || out.kmax < 1 || out.kmax > 50 || out.fixed_steps < 0)
         return false;
+    if (out.jacobian != 0 && out.jacobian != 1) return false;
     if (!(out.h0 >= 0.0) || !(out.h_min >= 0.0)) return false;
     return true;
 }
@@ -622,6 +733,7 @@ extern "C" int64_t rdo_reaction_step(double* states, int64_t n, int32_t m,
     if (!model_from_abi(model, md)) return RDO_EINVAL;
     Opts op;
     if (!options_from_abi(opts, op)) return RDO_EINVAL;
+    if (op.jacobian) md.fd = true;
     if (n == 0) return 0;
     if (!states) return RDO_EINVAL;
     const Tols tl = make_tols(rtol, atol, op.tol_transform);
@@ -644,7 +756,7 @@ extern "C" int64_t rdo_reaction_step(double* states, int64_t n, int32_t m,
             for (int64_t c = start; c < end; ++c) {
                 for (int r = 0; r < m; ++r) y[r] = states[(size_t)r * n + c];
                 Stats st;
-                cell.integrate(y.data(), dt, st);
+                cell.integrate(y.data(), dt, st, op.h_cells ? op.h_cells + c : nullptr);
                 for (int r = 0; r < m; ++r) states[(size_t)r * n + c] = y[r];
                 if (st.status != 0) ++my_failed;
                 if (stats) {
@@ -688,7 +800,7 @@ extern "C" int32_t rdo_single_step(const double* y0, int32_t m, double h,
     std::vector<double> y(y0, y0 + m);
     md.f(y.data(), cell.f0.data());
     cell.scale(y.data());
-    md.jac(y.data(), cell.J.data());
+    cell.jacobian(y.data(), st);
     if (!cell.factor(h)) return RDO_EINVAL;
     cell.start_values(h, false, h);
     double eta = 1.0, theta = 0.0;
@@ -710,7 +822,15 @@ extern "C" int32_t rdo_model_eval(const rdo_model* model, const double* y,
     Model md;
     if (!model_from_abi(model, md) || !y) return RDO_EINVAL;
     if (f) md.f(y, f);
-    if (J) md.jac(y, J);
+    if (J) {
+        if (md.fd) {
+            std::vector<double> fy(md.m);
+            md.f(y, fy.data());
+            md.jac_fd(y, fy.data(), J);
+        } else {
+            md.jac(y, J);
+        }
+    }
     return 0;
 }
 

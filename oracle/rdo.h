@@ -30,8 +30,26 @@ enum {
     RDO_KINETICS   = 2, /* any m, params {K[m*m] row-major, G[m*m] row-major}  */
     RDO_NAGUMO     = 3, /* m=1, params {k}                                      */
     RDO_LINEAR     = 4, /* any m, params {K[m*m] row-major}: f(u) = K u          */
-    RDO_ROBERTSON  = 5  /* m=3, params {k1, k2, k3}                             */
+    RDO_ROBERTSON  = 5, /* m=3, params {k1, k2, k3}                             */
+    RDO_BYTECODE   = 6  /* m=1..4, f given as a register program, see below      */
 };
+
+/*
+ * Bytecode model (a user-supplied f without compiled code).  params =
+ *   [L, C, c_0 .. c_{C-1}, then L instructions of 4 doubles (op, d, a, b)]
+ * over 32 FP64 registers r[0..32): r[0..m) hold u (read only), r[m..m+C) the
+ * constants, the rest are temporaries.  Ops:
+ *   1 ADD r[d] = r[a] + r[b]    2 SUB r[d] = r[a] - r[b]   3 MUL r[d] = r[a] * r[b]
+ *   4 DIV r[d] = r[a] / r[b]    5 NEG r[d] = -r[a]         6 EXP r[d] = exp(r[a])
+ *   7 LOG r[d] = log(r[a])      8 POW r[d] = r[a] ^ r[b]   9 OUT f_d = r[a]
+ * A program is valid when every field is an integer in range, d >= m+C for
+ * ops 1-8, every register is written before it is read, and OUT writes each
+ * of f_0 .. f_{m-1} exactly once.  Its Jacobian is always taken by finite
+ * differences.
+ */
+#define RDO_BC_REGS 32
+enum { RDO_BC_ADD = 1, RDO_BC_SUB, RDO_BC_MUL, RDO_BC_DIV, RDO_BC_NEG, RDO_BC_EXP,
+       RDO_BC_LOG, RDO_BC_POW, RDO_BC_OUT };
 
 typedef struct {
     int32_t kind;
@@ -47,6 +65,16 @@ typedef struct {
     int32_t fixed_steps;   /* 0: adaptive; N>0: N equal steps, no error control      */
     double  h0;            /* first trial step; 0 means dt                           */
     double  h_min;         /* 0 means 1e-14 * dt                                     */
+    int32_t jacobian;      /* 0 analytic (bytecode: always 1); 1 forward differences:
+                              column j = (f(u + d_j e_j) - f(u)) / d_j with
+                              d_j = sqrt(uround * max(1e-5, |u_j|)), m extra f
+                              evaluations per Jacobian (counted in nfev)           */
+    int32_t pad_;
+    double* h_cells;       /* null, or [n]: per-cell step size in and out.  In: a
+                              value > 0 replaces h0 for that cell.  Out: the step
+                              size the controller held before it shortened the final
+                              step to end at dt (fixed-step mode: dt / N; a failed
+                              cell: the last step size tried)                      */
 } rdo_options;
 
 /* per-cell status codes */
@@ -65,7 +93,7 @@ enum { RDO_EINVAL = -1 };
  * Advance every cell over [0, dt] in place.
  *   states   [m][n] float64, overwritten with u(dt) (failed cells keep their
  *            last accepted state)
- *   opts     nullable -> defaults {1, 100000, 7, 0, 0, 0}
+ *   opts     nullable -> defaults {1, 100000, 7, 0, 0, 0, 0, 0, null}
  *   stats    nullable, [RDO_NSTATS][n] int32
  *   nthreads 0 -> all hardware threads
  * Returns the number of cells with a nonzero status, or RDO_EINVAL (nothing

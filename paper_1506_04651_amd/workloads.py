@@ -26,6 +26,10 @@ KIND_KINETICS = 2
 KIND_NAGUMO = 3
 KIND_LINEAR = 4
 KIND_ROBERTSON = 5
+KIND_BYTECODE = 6
+
+# register-program opcodes of the bytecode model (format in include/rd.h)
+BC_ADD, BC_SUB, BC_MUL, BC_DIV, BC_NEG, BC_EXP, BC_LOG, BC_POW, BC_OUT = range(1, 10)
 
 # Oregonator (BZ) constants of the benchmark: da/dt = (-q a - a b + f c)/mu,
 # db/dt = (q a - a b + b(1-b))/eps, dc/dt = b - c.  The paper prints q = 0.02
@@ -260,6 +264,62 @@ def serving_stream(n_requests: int = 2000, seed: int = 5, mean_gap: float = 5e-3
     return out
 
 
+def _program(m, consts, code):
+    """Flatten (constants, [(op, d, a, b), ...]) into the bytecode params."""
+    out = [float(len(code)), float(len(consts))] + [float(c) for c in consts]
+    for ins in code:
+        out += [float(v) for v in ins]
+    return np.array(out)
+
+
+def oregonator_program(params=OREG_PARAMS) -> np.ndarray:
+    """The BZ right-hand side (paper §1, model II) as a register program,
+    operation for operation the same as the closed form
+    f1 = ((-q) a - a b + f c) / mu, f2 = (q a - a b + b (1 - b)) / eps,
+    f3 = b - c  (registers: 0 a, 1 b, 2 c, 3 -q, 4 q, 5 f, 6 mu, 7 eps, 8 one)."""
+    eps, mu, f, q = (float(v) for v in params)
+    consts = [-q, q, f, mu, eps, 1.0]
+    code = [(BC_MUL, 9, 3, 0), (BC_MUL, 10, 0, 1), (BC_SUB, 11, 9, 10), (BC_MUL, 12, 5, 2),
+            (BC_ADD, 13, 11, 12), (BC_DIV, 14, 13, 6), (BC_OUT, 0, 14, 0),
+            (BC_MUL, 15, 4, 0), (BC_SUB, 16, 15, 10), (BC_SUB, 17, 8, 1), (BC_MUL, 18, 1, 17),
+            (BC_ADD, 19, 16, 18), (BC_DIV, 20, 19, 7), (BC_OUT, 1, 20, 0),
+            (BC_SUB, 21, 1, 2), (BC_OUT, 2, 21, 0)]
+    return _program(3, consts, code)
+
+
+def robertson_program(k=(0.04, 1e4, 3e7)) -> np.ndarray:
+    """Robertson kinetics as a register program: f1 = (-k1) u1 + k2 u2 u3,
+    f2 = k1 u1 - k2 u2 u3 - k3 u2 u2, f3 = k3 u2 u2
+    (registers: 0..2 u, 3 -k1, 4 k1, 5 k2, 6 k3)."""
+    k1, k2, k3 = (float(v) for v in k)
+    consts = [-k1, k1, k2, k3]
+    code = [(BC_MUL, 7, 5, 1), (BC_MUL, 8, 7, 2),          # k2 u2 u3
+            (BC_MUL, 9, 6, 1), (BC_MUL, 10, 9, 1),         # k3 u2 u2
+            (BC_MUL, 11, 3, 0), (BC_ADD, 12, 11, 8), (BC_OUT, 0, 12, 0),
+            (BC_MUL, 13, 4, 0), (BC_SUB, 14, 13, 8), (BC_SUB, 15, 14, 10), (BC_OUT, 1, 15, 0),
+            (BC_OUT, 2, 10, 0)]
+    return _program(3, consts, code)
+
+
+def nagumo_program(k=1.0) -> np.ndarray:
+    """NAGUMO (paper §1, model I) f = k u^2 (1 - u) as ((k u) u) (1 - u)
+    (registers: 0 u, 1 k, 2 one)."""
+    code = [(BC_MUL, 3, 1, 0), (BC_MUL, 4, 3, 0), (BC_SUB, 5, 2, 0), (BC_MUL, 6, 4, 5),
+            (BC_OUT, 0, 6, 0)]
+    return _program(1, [float(k), 1.0], code)
+
+
+def oregonator_2d_paper(side: int = 1024, seed: int = 6, dt: float = 1.0 / 64,
+                        rtol: float = 1e-5, atol: float = 1e-8) -> Workload:
+    """The spiral-front field with the paper's BZ constants (q = 0.02, §1)
+    on a 1024 x 1024 grid: the setting of the paper's complexity histogram
+    (Appendix A)."""
+    w = oregonator_2d(side=side, seed=seed, dt=dt, rtol=rtol, atol=atol,
+                      params=OREG_PARAMS_PAPER)
+    w.name = f"oregonator_2d_paper_q_{side}x{side}"
+    return w
+
+
 def sample_indices(n: int, k: int, seed: int) -> np.ndarray:
     """k distinct sorted cell indices in [0, n)."""
     rng = np.random.default_rng(seed)
@@ -272,4 +332,5 @@ CONFIGS = {
     "oregonator_2d": oregonator_2d,
     "oregonator_3d": oregonator_3d,
     "kinetics16": kinetics16,
+    "oregonator_2d_paper": oregonator_2d_paper,
 }
