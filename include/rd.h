@@ -57,8 +57,31 @@ enum {
                           f_i = sum_j K_ij u_j - u_i sum_k G_ik u_k              */
     RD_NAGUMO = 3,     /* m = 1, params {k}: f = k u^2 (1 - u) (paper §1, I)      */
     RD_LINEAR = 4,     /* m in {1..16}, params {K[m*m]}: f = K u (tests)         */
-    RD_ROBERTSON = 5   /* m = 3, params {k1, k2, k3}: Robertson kinetics (tests)  */
+    RD_ROBERTSON = 5,  /* m = 3, params {k1, k2, k3}: Robertson kinetics (tests)  */
+    RD_BYTECODE = 6    /* m in {1..4}: f supplied at run time as a register program
+                          (below); its Jacobian is always taken by finite
+                          differences                                             */
 };
+
+/*
+ * Bytecode model.  params = [L, C, c_0 .. c_{C-1}, then L instructions of 4
+ * doubles (op, d, a, b)], all integer-valued except the constants, over 32
+ * FP64 registers r[0..32): r[0..m) hold u (read only), r[m..m+C) the
+ * constants, the rest are temporaries.  Ops:
+ *   1 ADD r[d] = r[a] + r[b]    2 SUB r[d] = r[a] - r[b]   3 MUL r[d] = r[a] * r[b]
+ *   4 DIV r[d] = r[a] / r[b]    5 NEG r[d] = -r[a]         6 EXP r[d] = exp(r[a])
+ *   7 LOG r[d] = log(r[a])      8 POW r[d] = r[a] ^ r[b]   9 OUT f_d = r[a]
+ * Valid when 1 <= L <= 4096, m + C <= 32, d >= m + C for ops 1-8, every
+ * register is written before it is read, and OUT writes each f_0 .. f_{m-1}
+ * exactly once; anything else is RD_EINVAL.  Evaluation follows the program
+ * order exactly (no reassociation, no contraction), so a program reproduces
+ * a hand-written f operation for operation.
+ */
+enum { RD_BC_ADD = 1, RD_BC_SUB, RD_BC_MUL, RD_BC_DIV, RD_BC_NEG, RD_BC_EXP, RD_BC_LOG,
+       RD_BC_POW, RD_BC_OUT };
+#define RD_BC_REGS 32
+
+enum { RD_JAC_ANALYTIC = 0, RD_JAC_FD = 1 };   /* jacobian */
 
 enum { RD_FP64 = 0, RD_MIXED = 1 };            /* precision */
 enum { RD_PERSISTENT = 0, RD_ONE_LAUNCH = 1 };  /* schedule  */
@@ -99,6 +122,19 @@ typedef struct {
     int32_t order;         /* claim order of the persistent schedule: 1 (default)
                               longest first, by a per-cell cost estimate (bucketed
                               scaled initial rate |f(u0)| dt / sc); 0 cell order  */
+    int32_t jacobian;      /* RD_JAC_ANALYTIC (default) or RD_JAC_FD: forward
+                              differences, column j = (f(u + d_j e_j) - f(u)) / d_j,
+                              d_j = sqrt(uround max(1e-5, |u_j|)), m more f
+                              evaluations per Jacobian (counted in nfev); m <= 4
+                              models only.  RD_BYTECODE always uses RD_JAC_FD.     */
+    double* h_cells;       /* null (default), or DEVICE [n_cells] float64: per-cell
+                              step size, in and out (warm start across split
+                              steps).  In: a value > 0 is that cell's first trial
+                              step (in place of h0, capped at dt).  Out: the step
+                              size the controller held before it shortened the final
+                              step to end at dt; dt/N in fixed-step mode; for a
+                              failed cell the step size of its last attempt (0 if
+                              none).  Not accepted by sessions.                     */
 } rd_options;
 
 /* Fill *opts with the defaults above. */

@@ -10,13 +10,15 @@ and streams only.
     u = torch.tensor(states, dtype=torch.float64, device="cuda")   # [m, n]
     nfail = rd.reaction_step(u, dt, rtol, atol, rd.OREGONATOR, params)
 """
-from ._lib import (FP64, KINETICS, LINEAR, MIXED, NAGUMO, ONE_LAUNCH, OREGONATOR,
-                   PERSISTENT, ROBERTSON, STAT_NAMES, NSTATS, load, last_error)
+from ._lib import (BYTECODE, FP64, JAC_ANALYTIC, JAC_FD, KINETICS, LINEAR, MIXED, NAGUMO,
+                   ONE_LAUNCH, OREGONATOR, PERSISTENT, ROBERTSON, STAT_NAMES, NSTATS, load,
+                   last_error)
 from .api import (RdError, Session, last_kernel_ms, persistent_grid, reaction_step,
                   request_bytes, set_default_variant, variant_count, variant_name)
 
 __all__ = ["FP64", "MIXED", "PERSISTENT", "ONE_LAUNCH", "OREGONATOR", "KINETICS",
-           "NAGUMO", "LINEAR", "ROBERTSON", "STAT_NAMES", "NSTATS", "load",
+           "NAGUMO", "LINEAR", "ROBERTSON", "BYTECODE", "JAC_ANALYTIC", "JAC_FD",
+           "STAT_NAMES", "NSTATS", "load",
            "last_error", "RdError", "Session", "reaction_step", "last_kernel_ms",
            "persistent_grid", "request_bytes", "variant_count", "variant_name",
            "set_default_variant"]

@@ -10,7 +10,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librd.so")
 
-OREGONATOR, KINETICS, NAGUMO, LINEAR, ROBERTSON = 1, 2, 3, 4, 5
+OREGONATOR, KINETICS, NAGUMO, LINEAR, ROBERTSON, BYTECODE = 1, 2, 3, 4, 5, 6
+JAC_ANALYTIC, JAC_FD = 0, 1
 FP64, MIXED = 0, 1
 PERSISTENT, ONE_LAUNCH = 0, 1
 NSTATS = 9
@@ -31,7 +32,8 @@ class RdOptions(ctypes.Structure):
                 ("newton_max", ctypes.c_int32), ("fixed_steps", ctypes.c_int32),
                 ("h0", ctypes.c_double), ("h_min", ctypes.c_double),
                 ("variant", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("order", ctypes.c_int32)]
+                ("order", ctypes.c_int32), ("jacobian", ctypes.c_int32),
+                ("h_cells", ctypes.c_void_p)]
 
 
 class RdRequestInfo(ctypes.Structure):

@@ -30,9 +30,11 @@ def _model(kind: int, m: int, params):
 
 def make_options(precision=FP64, schedule=PERSISTENT, tol_transform=1, max_steps=100000,
                  newton_max=7, fixed_steps=0, h0=0.0, h_min=0.0, variant=0,
-                 use_graph=False, order=1) -> RdOptions:
+                 use_graph=False, order=1, jacobian=0, h_cells_ptr=None) -> RdOptions:
     o = RdOptions()
     o.order = int(order)
+    o.jacobian = int(jacobian)
+    o.h_cells = h_cells_ptr
     o.precision, o.schedule, o.tol_transform = int(precision), int(schedule), int(tol_transform)
     o.max_steps, o.newton_max, o.fixed_steps = int(max_steps), int(newton_max), int(fixed_steps)
     o.h0, o.h_min, o.variant, o.use_graph = float(h0), float(h_min), int(variant), int(use_graph)
@@ -64,18 +66,26 @@ def _stream_handle(stream):
 
 
 def reaction_step(states, dt, rtol, atol, kind, params, *, stats=None, stream=None,
-                  async_=False, **opts) -> int:
+                  async_=False, h_cells=None, **opts) -> int:
     """Advance every cell (column) of ``states`` [m, n] float64 (device) over
     [0, dt] in place.  Returns the number of cells with a nonzero status
     (0 when async_).  Keyword options as in rd_options (precision, schedule,
     tol_transform, max_steps, newton_max, fixed_steps, h0, h_min, variant,
-    use_graph)."""
+    use_graph, order, jacobian).  ``h_cells``: optional float64 CUDA tensor [n],
+    the per-cell warm-start step size, read and updated in place."""
+    import torch
     lib = _lib.load()
     _check_states(states)
     m, n = int(states.shape[0]), int(states.shape[1])
     sp = _check_stats(stats, n)
+    hp = None
+    if h_cells is not None:
+        if not isinstance(h_cells, torch.Tensor) or h_cells.dtype != torch.float64 or \
+                not h_cells.is_cuda or tuple(h_cells.shape) != (n,) or not h_cells.is_contiguous():
+            raise ValueError(f"h_cells must be a contiguous float64 CUDA tensor of shape [{n}]")
+        hp = h_cells.data_ptr()
     mdl, keep = _model(kind, m, params)
-    o = make_options(**opts)
+    o = make_options(h_cells_ptr=hp, **opts)
     ret = lib.rd_reaction_step_ex(ctypes.c_void_p(states.data_ptr()), n, m, float(dt),
                                   float(rtol), float(atol), ctypes.byref(mdl), ctypes.byref(o),
                                   ctypes.c_void_p(sp) if sp else None, _stream_handle(stream),

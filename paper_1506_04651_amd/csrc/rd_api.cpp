@@ -24,6 +24,7 @@ namespace rd {
 
 const KernelEntry* small_kernel_table(int* count);
 const KernelEntry* group_kernel_table(int* count);
+const KernelEntry* fd_kernel_table(int* count);
 
 /* ---------------------------------------------------------------- errors */
 static thread_local char g_err[512] = "";
@@ -53,6 +54,8 @@ static std::vector<KernelEntry>& all_kernels() {
         out.insert(out.end(), t, t + n);
         t = group_kernel_table(&n);
         out.insert(out.end(), t, t + n);
+        t = fd_kernel_table(&n);
+        out.insert(out.end(), t, t + n);
         return out;
     }();
     return v;
@@ -72,16 +75,22 @@ static int default_variant(int kind, int m, int precision, int schedule) {
     return it == g_default_variant.end() ? 1 : it->second;
 }
 
+/* The kind's own Jacobian: analytic, except for the bytecode model. */
+static int native_jac(int kind) { return kind == RD_BYTECODE ? RD_JAC_FD : RD_JAC_ANALYTIC; }
+
 const KernelEntry* find_kernel(int kind, int m, int precision, int schedule, int fixed,
-                               int variant) {
+                               int variant, int jac) {
     /* kinetics and linear models with 5..16 species run on the 16-lane group
      * kernels, registered under m = 16 */
     if ((kind == RD_KINETICS || kind == RD_LINEAR) && m > 4 && m <= RD_MAX_M) m = 16;
-    if (fixed) variant = 1;
+    if (jac < 0) jac = native_jac(kind);
+    /* tuned defaults and variant ids refer to the kind's own Jacobian; the
+     * finite-difference kernels of analytic models come in one variant */
+    if (fixed || jac != native_jac(kind)) variant = 1;
     else if (variant <= 0) variant = default_variant(kind, m, precision, schedule);
     for (const KernelEntry& e : all_kernels())
-        if (e.kind == kind && e.m == m && e.precision == precision && e.schedule == schedule &&
-            e.fixed == fixed && e.variant == variant)
+        if (e.kind == kind && e.jac == jac && e.m == m && e.precision == precision &&
+            e.schedule == schedule && e.fixed == fixed && e.variant == variant)
             return &e;
     return nullptr;
 }
@@ -187,6 +196,57 @@ static bool all_finite(const double* p, int64_t k) {
     return true;
 }
 
+/* Bytecode program: check it against the rules of the public header and pack
+ * it for the device interpreter: [L, C] as integers in 64-bit slots, the
+ * constants, then one slot per instruction holding op | d << 8 | a << 16 |
+ * b << 24. */
+static bool bytecode_block(const rd_model* md, int32_t m, std::vector<double>& block) {
+    const double* p = md->params;
+    if (m < 1 || m > 4 || md->n_params < 2) return false;
+    auto whole = [](double v, double lo, double hi) {
+        return std::isfinite(v) && std::floor(v) == v && v >= lo && v <= hi;
+    };
+    if (!whole(p[0], 1, 4096) || !whole(p[1], 0, RD_BC_REGS)) return false;
+    const int L = (int)p[0], C = (int)p[1];
+    if (m + C > RD_BC_REGS || md->n_params < 2 + (int64_t)C + 4LL * L) return false;
+    if (!all_finite(p + 2, C)) return false;
+    bool defined[RD_BC_REGS] = {};
+    for (int r = 0; r < m + C; ++r) defined[r] = true;
+    int out_count[4] = {0, 0, 0, 0};
+    std::vector<long long> words;
+    words.reserve(L);
+    for (int k = 0; k < L; ++k) {
+        const double* ins = p + 2 + C + 4 * k;
+        if (!whole(ins[0], RD_BC_ADD, RD_BC_OUT) || !whole(ins[1], 0, RD_BC_REGS - 1) ||
+            !whole(ins[2], 0, RD_BC_REGS - 1) || !whole(ins[3], 0, RD_BC_REGS - 1))
+            return false;
+        const int op = (int)ins[0], d = (int)ins[1], a = (int)ins[2], b = (int)ins[3];
+        const bool two = op == RD_BC_ADD || op == RD_BC_SUB || op == RD_BC_MUL ||
+                         op == RD_BC_DIV || op == RD_BC_POW;
+        if (!defined[a] || (two && !defined[b])) return false;
+        if (op == RD_BC_OUT) {
+            if (d >= m || out_count[d]++ != 0) return false;
+        } else {
+            if (d < m + C) return false;
+            defined[d] = true;
+        }
+        words.push_back((long long)(op | (d << 8) | (a << 16) | ((long long)b << 24)));
+    }
+    for (int i = 0; i < m; ++i)
+        if (out_count[i] != 1) return false;
+    auto as_double = [](long long w) {
+        double v;
+        std::memcpy(&v, &w, sizeof(v));
+        return v;
+    };
+    block.clear();
+    block.push_back(as_double(L));
+    block.push_back(as_double(C));
+    block.insert(block.end(), p + 2, p + 2 + C);
+    for (long long w : words) block.push_back(as_double(w));
+    return true;
+}
+
 bool model_block(const rd_model* md, int32_t m, std::vector<double>& block) {
     if (!md || md->m != m || !md->params) return false;
     const double* p = md->params;
@@ -215,6 +275,8 @@ bool model_block(const rd_model* md, int32_t m, std::vector<double>& block) {
             return false;
         block.assign(p, p + 2 * (size_t)m * m);
         return true;
+    case RD_BYTECODE:
+        return bytecode_block(md, m, block);
     default:
         return false;
     }
@@ -277,7 +339,8 @@ static bool options_valid(const rd_options& o) {
            (o.schedule == RD_PERSISTENT || o.schedule == RD_ONE_LAUNCH) && o.max_steps >= 1 &&
            o.newton_max >= 1 && o.newton_max <= 50 && o.fixed_steps >= 0 && o.h0 >= 0.0 &&
            o.h_min >= 0.0 && std::isfinite(o.h0) && std::isfinite(o.h_min) && o.variant >= 0 &&
-           (o.order == 0 || o.order == 1);
+           (o.order == 0 || o.order == 1) &&
+           (o.jacobian == RD_JAC_ANALYTIC || o.jacobian == RD_JAC_FD);
 }
 
 int prepare(double* states, int64_t n, int32_t m, double dt, double rtol, double atol,
@@ -300,11 +363,12 @@ int prepare(double* states, int64_t n, int32_t m, double dt, double rtol, double
         set_error("fixed-step mode is available in FP64 only");
         return RD_EINVAL;
     }
+    const int jac = model->kind == RD_BYTECODE ? RD_JAC_FD : o.jacobian;
     const KernelEntry* e = find_kernel(model->kind, m, o.precision, o.schedule, o.fixed_steps > 0,
-                                       o.variant);
+                                       o.variant, jac);
     if (!e) {
-        set_error("no kernel for kind %d, m %d, precision %d, schedule %d, variant %d", model->kind, m,
-                  o.precision, o.schedule, o.variant);
+        set_error("no kernel for kind %d, m %d, precision %d, schedule %d, variant %d, jacobian %d",
+                  model->kind, m, o.precision, o.schedule, o.variant, jac);
         return RD_EINVAL;
     }
     out->entry = e;
@@ -313,6 +377,7 @@ int prepare(double* states, int64_t n, int32_t m, double dt, double rtol, double
     out->args.P.m = m;
     out->args.states = states;
     out->args.stats = stats;
+    out->args.hcell = o.h_cells;
     out->args.n = n;
     if (n == 0) return 0;
     DevCtx* c = current_ctx();
@@ -350,6 +415,7 @@ struct GraphKey {
     const KernelEntry* entry;
     double* states;
     int32_t* stats;
+    double* hcell;
     const double* params;
     int64_t n;
     int grid;
@@ -383,6 +449,7 @@ static int launch_prepared(Prepared& pr, hipStream_t s, bool use_graph, unsigned
         key.entry = pr.entry;
         key.states = pr.args.states;
         key.stats = pr.args.stats;
+        key.hcell = pr.args.hcell;
         key.params = pr.args.params;
         key.n = pr.args.n;
         key.grid = pr.grid;
@@ -464,6 +531,8 @@ void rd_default_options(rd_options* o) {
     o->variant = 0;
     o->use_graph = 0;
     o->order = 1;
+    o->jacobian = RD_JAC_ANALYTIC;
+    o->h_cells = nullptr;
 }
 
 int64_t rd_reaction_step_ex(double* states, int64_t n_cells, int32_t m, double dt, double rtol,
@@ -501,15 +570,16 @@ double rd_last_kernel_ms(void) {
 int32_t rd_variant_count(int32_t kind, int32_t m, int32_t precision, int32_t schedule) {
     int best = 0;
     for (const KernelEntry& e : all_kernels())
-        if (e.kind == kind && e.m == m && e.precision == precision && e.schedule == schedule &&
-            !e.fixed && e.variant > best)
+        if (e.kind == kind && e.jac == native_jac(kind) && e.m == m && e.precision == precision &&
+            e.schedule == schedule && !e.fixed && e.variant > best)
             best = e.variant;
     return best;
 }
 
 const char* rd_variant_name(int32_t kind, int32_t m, int32_t precision, int32_t schedule,
                             int32_t variant) {
-    const KernelEntry* e = find_kernel(kind, m, precision, schedule, 0, variant <= 0 ? 0 : variant);
+    const KernelEntry* e =
+        find_kernel(kind, m, precision, schedule, 0, variant <= 0 ? 0 : variant, -1);
     return e ? e->name : nullptr;
 }
 
@@ -527,7 +597,7 @@ int32_t rd_set_default_variant(int32_t kind, int32_t m, int32_t precision, int32
 
 int32_t rd_persistent_grid(int32_t kind, int32_t m, int32_t precision, int32_t variant,
                            int64_t n_cells) {
-    const KernelEntry* e = find_kernel(kind, m, precision, RD_PERSISTENT, 0, variant);
+    const KernelEntry* e = find_kernel(kind, m, precision, RD_PERSISTENT, 0, variant, -1);
     if (!e) { set_error("no such kernel"); return RD_EINVAL; }
     DevCtx* c = current_ctx();
     if (!c) return RD_EDEVICE;

@@ -81,6 +81,7 @@ struct GroupCell {
     bool act;         /* q < m */
     /* per-cell scalars, replicated across the group */
     double t, h, ih, h_old, ih_acc, qerr_acc, eta, inprev;
+    double h_pre; /* step size before the last-step shortening (warm start out) */
     unsigned flags;
     int phase, status, k, nsing, outcome;
     int nstep, naccept, nreject, nfev, njac, ndec, nsol, nnewt;
@@ -102,7 +103,7 @@ struct GroupCell {
     }
 
     __device__ __forceinline__ void load(const StepParams& P, const double* __restrict__ states,
-                                         int64_t n, int64_t c) {
+                                         int64_t n, int64_t c, const double* __restrict__ hcell) {
         y = act ? states[(int64_t)q * n + c] : 0.0;
         nstep = naccept = nreject = njac = ndec = nsol = nnewt = 0;
         nfev = 1;
@@ -111,7 +112,10 @@ struct GroupCell {
         status = ST_OK;
         const bool fin = grp_bits(finite_d(y) && finite_d(f0)) == 0xFFFFu;
         t = 0.0;
-        h = P.fixed_steps > 0 ? P.dt / P.fixed_steps : fmin(P.h0 > 0.0 ? P.h0 : P.dt, P.dt);
+        const double hw = hcell ? hcell[c] : 0.0;
+        h = P.fixed_steps > 0 ? P.dt / P.fixed_steps
+                              : fmin(hw > 0.0 ? hw : (P.h0 > 0.0 ? P.h0 : P.dt), P.dt);
+        h_pre = fin ? h : 0.0;
         h_old = ih_acc = qerr_acc = inprev = 0.0;
         eta = 1.0;
         k = 0;
@@ -128,8 +132,9 @@ struct GroupCell {
     }
 
     __device__ __forceinline__ void store(double* __restrict__ states, int32_t* __restrict__ stats,
-                                          int64_t n, int64_t c) const {
+                                          int64_t n, int64_t c, double* __restrict__ hcell) const {
         if (act) states[(int64_t)q * n + c] = y;
+        if (hcell && q == 0) hcell[c] = h_pre;
         if (stats && q == 0) {
             stats[0 * n + c] = status;
             stats[1 * n + c] = nstep;
@@ -293,6 +298,7 @@ struct GroupCell {
     template <bool FIXED>
     __device__ __forceinline__ void start(const StepParams& P) {
         if (!FIXED) {
+            h_pre = h;
             if (nstep >= P.max_steps) { status = ST_MAXSTEPS; phase = PH_IDLE; return; }
             if (h < P.h_min) { status = ST_HSMALL; phase = PH_IDLE; return; }
             const bool last = t + 1.0001 * h >= P.dt;

@@ -264,6 +264,7 @@ struct SmallCell {
     double w[3][M];
     LT e1[M][M], e2r[M][M], e2i[M][M];
     double t, h, ih, h_old, ih_acc, qerr_acc, eta, inprev;
+    double h_pre; /* step size before the last-step shortening (warm start out) */
     unsigned p1, p2, flags;
     int phase, status, k, nsing, outcome;
     /* counters (paper Appendix A: f evaluations per node) */
@@ -275,7 +276,7 @@ struct SmallCell {
 
     __device__ __forceinline__ void load(const Model& md, const StepParams& P,
                                          const double* __restrict__ states, int64_t n,
-                                         int64_t c) {
+                                         int64_t c, const double* __restrict__ hcell) {
 #pragma unroll
         for (int r = 0; r < M; ++r) y[r] = states[(int64_t)r * n + c];
         nstep = naccept = nreject = njac = ndec = nsol = nnewt = 0;
@@ -286,7 +287,11 @@ struct SmallCell {
 #pragma unroll
         for (int r = 0; r < M; ++r) fin = fin && finite_d(y[r]) && finite_d(f0[r]);
         t = 0.0;
-        h = P.fixed_steps > 0 ? P.dt / P.fixed_steps : fmin(P.h0 > 0.0 ? P.h0 : P.dt, P.dt);
+        /* first trial step: the cell's warm-start value when one is given */
+        const double hw = hcell ? hcell[c] : 0.0;
+        h = P.fixed_steps > 0 ? P.dt / P.fixed_steps
+                              : fmin(hw > 0.0 ? hw : (P.h0 > 0.0 ? P.h0 : P.dt), P.dt);
+        h_pre = fin ? h : 0.0;
         h_old = ih_acc = qerr_acc = inprev = 0.0;
         eta = 1.0;
         k = 0;
@@ -297,9 +302,10 @@ struct SmallCell {
     }
 
     __device__ __forceinline__ void store(double* __restrict__ states, int32_t* __restrict__ stats,
-                                          int64_t n, int64_t c) const {
+                                          int64_t n, int64_t c, double* __restrict__ hcell) const {
 #pragma unroll
         for (int r = 0; r < M; ++r) states[(int64_t)r * n + c] = y[r];
+        if (hcell) hcell[c] = h_pre;
         if (stats) {
             stats[0 * n + c] = status;
             stats[1 * n + c] = nstep;
@@ -336,6 +342,7 @@ struct SmallCell {
     template <bool FIXED>
     __device__ __forceinline__ void start(const Model& md, const StepParams& P) {
         if (!FIXED) {
+            h_pre = h;
             if (nstep >= P.max_steps) { status = ST_MAXSTEPS; phase = PH_IDLE; return; }
             if (h < P.h_min) { status = ST_HSMALL; phase = PH_IDLE; return; }
             const bool last = t + 1.0001 * h >= P.dt;
@@ -351,7 +358,12 @@ struct SmallCell {
         for (int r = 0; r < M; ++r) isc[r] = rcp(P.atol + P.rtol * __builtin_fabs(y[r]));
         if (FIXED || has(F_JSTALE)) {
             double J[M][M];
-            md.jac(y, J);
+            if (fd_jac_of<Model>::value) {
+                fd_jacobian(md, y, f0, J);
+                nfev += M;
+            } else {
+                md.jac(y, J);
+            }
 #pragma unroll
             for (int i = 0; i < M; ++i)
 #pragma unroll

@@ -70,7 +70,8 @@ bool model_block(const rd_model* model, int32_t m, std::vector<double>& block);
 void make_step_params(double dt, double rtol, double atol, const rd_options& o,
                       StepParams* P);
 
+/* jac: RD_JAC_ANALYTIC / RD_JAC_FD, or -1 for the kind's own Jacobian. */
 const KernelEntry* find_kernel(int kind, int m, int precision, int schedule, int fixed,
-                               int variant);
+                               int variant, int jac);
 
 }  // namespace rd

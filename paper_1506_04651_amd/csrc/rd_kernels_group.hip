@@ -82,9 +82,9 @@ k_group_onelaunch(LaunchArgs a, int m) {
     if (c >= a.n) return;
     GroupCell<Model, LT> cell;
     init_cell(cell, tab, m);
-    cell.load(sP, a.states, a.n, c);
+    cell.load(sP, a.states, a.n, c, a.hcell);
     while (cell.phase != PH_IDLE) advance_group<Model, LT, FIXED, FSMIN>(cell, sP);
-    cell.store(a.states, a.stats, a.n, c);
+    cell.store(a.states, a.stats, a.n, c, a.hcell);
     if (cell.status != ST_OK && cell.q == 0) atomicAdd(a.nfail, 1ull);
 }
 
@@ -105,7 +105,7 @@ k_group_persistent(LaunchArgs a, int m) {
     for (;;) {
         const bool need = alive && cell.phase == PH_IDLE; /* group-uniform */
         if (need && c >= 0) {
-            cell.store(a.states, a.stats, a.n, c);
+            cell.store(a.states, a.stats, a.n, c, a.hcell);
             if (cell.status != ST_OK && cell.q == 0) atomicAdd(a.nfail, 1ull);
             c = -1;
         }
@@ -132,7 +132,7 @@ k_group_persistent(LaunchArgs a, int m) {
             if (need) {
                 if (pos < (unsigned long long)a.n) {
                     c = a.order ? (int64_t)a.order[pos] : (int64_t)pos;
-                    cell.load(sP, a.states, a.n, c);
+                    cell.load(sP, a.states, a.n, c, a.hcell);
                 } else {
                     alive = false;
                 }
@@ -161,11 +161,11 @@ hipError_t launch_group_pers(const LaunchArgs& a, int grid, hipStream_t s) {
 }
 
 #define RD_GONE(KIND, MODEL, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, NAME)                          \
-    {KIND, 16, PREC, 1, FIXED, VAR, BLOCK, BLOCK / kGroup, NAME,                                 \
+    {KIND, 0, 16, PREC, 1, FIXED, VAR, BLOCK, BLOCK / kGroup, NAME,                                 \
      &launch_group_one<MODEL, LT, FIXED, BLOCK, WPE, FS>,                                        \
      (const void*)&k_group_onelaunch<MODEL, LT, FIXED, BLOCK, WPE, FS>}
 #define RD_GPERS(KIND, MODEL, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, NAME)                         \
-    {KIND, 16, PREC, 0, FIXED, VAR, BLOCK, BLOCK / kGroup, NAME,                                 \
+    {KIND, 0, 16, PREC, 0, FIXED, VAR, BLOCK, BLOCK / kGroup, NAME,                                 \
      &launch_group_pers<MODEL, LT, FIXED, BLOCK, WPE, FS>,                                       \
      (const void*)&k_group_persistent<MODEL, LT, FIXED, BLOCK, WPE, FS>}
 

@@ -20,125 +20,9 @@
  */
 #include <hip/hip_runtime.h>
 
-#include "rd_cell_small.h"
-#include "rd_launch.h"
+#include "rd_small_kernels.h"
 
 namespace rd {
-
-/* One pass of the scheduling loop.  Lanes in PH_NEWTON take one Newton
- * iteration; a lane whose Newton loop ends moves to PH_END.  The step-end
- * block (error estimate, control) and the step-start block (Jacobian,
- * factorization, start values) together cost about three Newton iterations
- * and run with only the lanes that need them active, so they are batched:
- * they run once at least FSMIN lanes of the wave wait for them, or when no
- * lane is left iterating.  FSMIN = 1 runs them every pass.  Batching delays
- * individual lanes but never changes what a cell computes. */
-template <class Model, typename LT, bool FIXED, int BLOCK, int FSMIN>
-__device__ __forceinline__ void advance(SmallCell<Model, LT, BLOCK>& cell, const Model& md,
-                                        const StepParams& P) {
-    if (cell.phase == PH_NEWTON) {
-        const int o = cell.newton(md, P);
-        if (o != NW_CONTINUE) {
-            cell.outcome = o;
-            cell.phase = PH_END;
-        }
-    }
-    const bool waits = cell.phase == PH_END || cell.phase == PH_START;
-    if (FSMIN > 1) {
-        const unsigned long long wmask = __ballot(waits);
-        if (wmask == 0ull) return;
-        if ((unsigned)__popcll(wmask) < (unsigned)FSMIN && __ballot(cell.phase == PH_NEWTON) != 0ull)
-            return;
-    }
-    if (cell.phase == PH_END) cell.template finish<FIXED>(md, P, cell.outcome);
-    if (cell.phase == PH_START) cell.template start<FIXED>(md, P);
-}
-
-template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
-k_onelaunch(LaunchArgs a) {
-    using L = SmallLds<Model::M>;
-    __shared__ double sh[L::ROWS * BLOCK];
-    __shared__ StepParams sP;
-    stage_params(sP, a.P);
-    const int64_t c = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (c >= a.n) return;
-    const Model md(a.params);
-    SmallCell<Model, LT, BLOCK> cell;
-    cell.lds.base = sh + threadIdx.x;
-    cell.load(md, sP, a.states, a.n, c);
-    while (cell.phase != PH_IDLE) {
-        __asm__ volatile("" ::: "memory"); /* re-read sP from LDS each pass */
-        advance<Model, LT, FIXED, BLOCK, FSMIN>(cell, md, sP);
-    }
-    cell.store(a.states, a.stats, a.n, c);
-    if (cell.status != ST_OK) atomicAdd(a.nfail, 1ull);
-}
-
-/* Claim queue of one wave: a range [next, end) of positions in the claim
- * order already reserved from the global counter.  Idle lanes take positions
- * from it in lane order; only when it runs dry does one lane reserve a new
- * chunk (at least kClaimChunk positions) with a single atomic. */
-constexpr unsigned kClaimChunk = 16;
-
-template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
-k_persistent(LaunchArgs a) {
-    using L = SmallLds<Model::M>;
-    __shared__ double sh[L::ROWS * BLOCK];
-    __shared__ StepParams sP;
-    stage_params(sP, a.P);
-    const Model md(a.params);
-    SmallCell<Model, LT, BLOCK> cell;
-    cell.lds.base = sh + threadIdx.x;
-    cell.phase = PH_IDLE;
-    cell.status = ST_OK;
-    int64_t c = -1;
-    bool alive = true;
-    const unsigned lane = __lane_id();
-    const unsigned long long below = (1ull << lane) - 1ull;
-    unsigned long long qnext = 0, qend = 0; /* wave-uniform */
-    for (;;) {
-        const bool need = alive && cell.phase == PH_IDLE;
-        if (need && c >= 0) {
-            cell.store(a.states, a.stats, a.n, c);
-            if (cell.status != ST_OK) atomicAdd(a.nfail, 1ull);
-            c = -1;
-        }
-        const unsigned long long mask = __ballot(need);
-        if (mask) {
-            const unsigned cnt = (unsigned)__popcll(mask);
-            const unsigned rank = (unsigned)__popcll(mask & below);
-            const unsigned long long avail = qend - qnext;
-            unsigned long long pos;
-            if (avail >= cnt) {
-                pos = qnext + rank;
-                qnext += cnt;
-            } else {
-                const unsigned take = (cnt - (unsigned)avail) > kClaimChunk
-                                          ? cnt - (unsigned)avail : kClaimChunk;
-                const int leader = __ffsll((long long)mask) - 1;
-                unsigned long long base = 0;
-                if (lane == (unsigned)leader) base = atomicAdd(a.counter, (unsigned long long)take);
-                base = __shfl(base, leader);
-                pos = rank < avail ? qnext + rank : base + (rank - avail);
-                qnext = base + (cnt - avail);
-                qend = base + take;
-            }
-            if (need) {
-                if (pos < (unsigned long long)a.n) {
-                    c = a.order ? (int64_t)a.order[pos] : (int64_t)pos;
-                    cell.load(md, sP, a.states, a.n, c);
-                } else {
-                    alive = false;
-                }
-            }
-        }
-        if (__ballot(alive) == 0ull) break;
-        __asm__ volatile("" ::: "memory"); /* re-read sP from LDS each pass */
-        advance<Model, LT, FIXED, BLOCK, FSMIN>(cell, md, sP);
-    }
-}
 
 __global__ void k_reset(unsigned long long* p, int n) {
     const int i = threadIdx.x;
@@ -149,41 +33,6 @@ hipError_t launch_reset(unsigned long long* p, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, p, n);
     return hipGetLastError();
 }
-
-template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN>
-hipError_t launch_one(const LaunchArgs& a, int grid, hipStream_t s) {
-    if (grid <= 0) grid = (int)((a.n + BLOCK - 1) / BLOCK);
-    hipLaunchKernelGGL((k_onelaunch<Model, LT, FIXED, BLOCK, WPE, FSMIN>), dim3(grid), dim3(BLOCK), 0,
-                       s, a);
-    return hipGetLastError();
-}
-
-template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN>
-hipError_t launch_pers(const LaunchArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_persistent<Model, LT, FIXED, BLOCK, WPE, FSMIN>), dim3(grid), dim3(BLOCK), 0,
-                       s, a);
-    return hipGetLastError();
-}
-
-#define RD_ONE(KIND, MODEL, M, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, NAME)                       \
-    {KIND, M, PREC, 1, FIXED, VAR, BLOCK, BLOCK, NAME,                                          \
-     &launch_one<MODEL, LT, FIXED, BLOCK, WPE, FS>,                                             \
-     (const void*)&k_onelaunch<MODEL, LT, FIXED, BLOCK, WPE, FS>}
-#define RD_PERS(KIND, MODEL, M, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, NAME)                      \
-    {KIND, M, PREC, 0, FIXED, VAR, BLOCK, BLOCK, NAME,                                          \
-     &launch_pers<MODEL, LT, FIXED, BLOCK, WPE, FS>,                                            \
-     (const void*)&k_persistent<MODEL, LT, FIXED, BLOCK, WPE, FS>}
-
-/* model kinds (same numbering as the public header) */
-enum { K_OREG = 1, K_KIN = 2, K_NAG = 3, K_LIN = 4, K_ROB = 5 };
-
-#define RD_MODEL_SET(KIND, MODEL, M, TAG)                                                     \
-    RD_ONE(KIND, MODEL, M, 0, double, false, 1, 256, 1, 32, TAG ".fp64.onelaunch.b256.fs32"), \
-    RD_ONE(KIND, MODEL, M, 1, float, false, 1, 256, 1, 32, TAG ".mixed.onelaunch.b256.fs32"), \
-    RD_PERS(KIND, MODEL, M, 0, double, false, 1, 128, 1, 40, TAG ".fp64.persistent.b128.fs40"), \
-    RD_PERS(KIND, MODEL, M, 1, float, false, 1, 128, 1, 40, TAG ".mixed.persistent.b128.fs40"), \
-    RD_ONE(KIND, MODEL, M, 0, double, true, 1, 256, 1, 1, TAG ".fp64.onelaunch.fixed"),       \
-    RD_PERS(KIND, MODEL, M, 0, double, true, 1, 256, 1, 1, TAG ".fp64.persistent.fixed")
 
 #define RD_TUNE_SET(KIND, MODEL, M, PREC, LT, TAG)                                            \
     RD_PERS(KIND, MODEL, M, PREC, LT, false, 2, 128, 1, 1, TAG ".persistent.b128.fs1"),       \

@@ -38,6 +38,7 @@ struct LaunchArgs {
     int64_t n;
     unsigned long long* counter;    /* claim counter (persistent schedule)      */
     unsigned long long* nfail;      /* cells with nonzero status                */
+    double* hcell;                  /* [n] per-cell warm-start step, or null    */
     StepParams P;
 };
 
@@ -45,6 +46,7 @@ typedef hipError_t (*launch_fn)(const LaunchArgs&, int grid, hipStream_t);
 
 struct KernelEntry {
     int kind;           /* RD_* model kind                              */
+    int jac;            /* 0 analytic Jacobian, 1 forward differences   */
     int m;
     int precision;      /* 0 FP64, 1 mixed                              */
     int schedule;       /* 0 persistent, 1 one launch                   */

@@ -127,4 +127,98 @@ struct Kinetics {
     }
 };
 
+/* Forward-difference Jacobian at y, given fy = f(y): column j =
+ * (f(y + d_j e_j) - f(y)) / d_j with d_j = sqrt(u_r max(1e-5, |y_j|)), u_r the
+ * unit roundoff (M more f evaluations). */
+template <class Model>
+__device__ __forceinline__ void fd_jacobian(const Model& md, const double (&y)[Model::M],
+                                            const double (&fy)[Model::M],
+                                            double (&J)[Model::M][Model::M]) {
+    constexpr int M = Model::M;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        double yp[M], fp[M];
+#pragma unroll
+        for (int i = 0; i < M; ++i) yp[i] = y[i];
+        const double dj = __builtin_sqrt(2.220446049250313e-16 * fmax(1e-5, __builtin_fabs(y[j])));
+        yp[j] = y[j] + dj;
+        md.rhs(yp, fp);
+#pragma unroll
+        for (int i = 0; i < M; ++i) J[i][j] = (fp[i] - fy[i]) / dj;
+    }
+}
+
+/* An analytic model run with the finite-difference Jacobian instead. */
+template <class Base>
+struct FdJac : Base {
+    static constexpr bool FD_JAC = true;
+    using Base::Base;
+};
+
+/* Bytecode model: f given at run time as a register program (format in the
+ * public header).  Device block, prepared and validated by the host:
+ *   [0] L (instructions), [1] C (constants), [2 .. 2+C) constants, then L
+ *   words, each an instruction packed as op | d << 8 | a << 16 | b << 24 in
+ *   the low 32 bits of a 64-bit slot.
+ * The program is the same for every cell, so the interpreter's control flow
+ * and register indices are wave-uniform; the register file is a per-lane
+ * array indexed by those uniform indices. */
+constexpr int kBcRegs = 32;
+enum : int { BC_ADD = 1, BC_SUB, BC_MUL, BC_DIV, BC_NEG, BC_EXP, BC_LOG, BC_POW, BC_OUT };
+
+template <int M_>
+struct Bytecode {
+    static constexpr int M = M_;
+    static constexpr bool FD_JAC = true;
+    const double* __restrict__ p;
+    __device__ __forceinline__ explicit Bytecode(const double* __restrict__ q) : p(q) {}
+    __device__ __forceinline__ void rhs(const double (&y)[M], double (&o)[M]) const {
+        const long long* w = reinterpret_cast<const long long*>(p);
+        const int L = (int)w[0], C = (int)w[1];
+        double r[kBcRegs];
+#pragma unroll
+        for (int i = 0; i < M; ++i) r[i] = y[i];
+        for (int c = 0; c < C; ++c) r[M + c] = p[2 + c];
+        const long long* ins = w + 2 + C;
+        for (int k = 0; k < L; ++k) {
+            const unsigned x = (unsigned)ins[k];
+            const int op = (int)(x & 0xffu), d = (int)((x >> 8) & 0xffu);
+            const int a = (int)((x >> 16) & 0xffu), b = (int)(x >> 24);
+            const double va = r[a], vb = r[b];
+            double v;
+            switch (op) {
+            case BC_ADD: v = va + vb; break;
+            case BC_SUB: v = va - vb; break;
+            case BC_MUL: v = va * vb; break;
+            case BC_DIV: v = va / vb; break;
+            case BC_NEG: v = -va; break;
+            case BC_EXP: v = exp(va); break;
+            case BC_LOG: v = log(va); break;
+            case BC_POW: v = pow(va, vb); break;
+            default: v = va; break; /* BC_OUT */
+            }
+            if (op == BC_OUT) {
+#pragma unroll
+                for (int i = 0; i < M; ++i)
+                    if (d == i) o[i] = v;
+            } else {
+                r[d] = v;
+            }
+        }
+    }
+    /* no analytic Jacobian (FD_JAC is set) */
+    __device__ __forceinline__ void jac(const double (&)[M], double (&J)[M][M]) const {
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+#pragma unroll
+            for (int j = 0; j < M; ++j) J[i][j] = 0.0;
+    }
+};
+
+/* FD_JAC trait with a default of false for the analytic models */
+template <class Model, class = void>
+struct fd_jac_of { static constexpr bool value = false; };
+template <class Model>
+struct fd_jac_of<Model, decltype((void)Model::FD_JAC)> { static constexpr bool value = Model::FD_JAC; };
+
 }  // namespace rd

@@ -135,6 +135,14 @@ order_fn find_order_fn(int kind, int m) {
         case 16: return &launch_order<Kinetics<16>>;
         default: return nullptr;
         }
+    case 6:
+        switch (m) {
+        case 1: return &launch_order<Bytecode<1>>;
+        case 2: return &launch_order<Bytecode<2>>;
+        case 3: return &launch_order<Bytecode<3>>;
+        case 4: return &launch_order<Bytecode<4>>;
+        default: return nullptr;
+        }
     default: return nullptr;
     }
 }

@@ -242,6 +242,10 @@ size_t rd_request_bytes(int64_t n_cells, int32_t m, int32_t with_stats) {
 int32_t rd_session_create(rd_session** out, int32_t device, size_t hbm_budget_bytes,
                           const rd_options* defaults, int32_t n_streams) {
     if (!out || hbm_budget_bytes < 256) { set_error("bad session arguments"); return RD_EINVAL; }
+    if (defaults && defaults->h_cells) {
+        set_error("per-cell warm-start arrays are not accepted by sessions");
+        return RD_EINVAL;
+    }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
         set_error("bad device %d", device);

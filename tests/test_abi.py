@@ -38,6 +38,7 @@ def test_default_options(lib):
     assert (o.precision, o.schedule, o.tol_transform, o.max_steps, o.newton_max,
             o.fixed_steps, o.h0, o.h_min, o.variant, o.use_graph) == (0, 0, 1, 100000, 7, 0,
                                                                        0.0, 0.0, 0, 0)
+    assert (o.order, o.jacobian, o.h_cells) == (1, 0, None)
 
 
 def test_request_bytes(lib):
@@ -84,6 +85,44 @@ def test_validation_before_device_use(lib):
     o = _lib.default_options()
     o.newton_max = 0
     assert call(dummy, 10, 3, 0.1, 1e-5, 1e-5, ctypes.byref(good), ctypes.byref(o), None, None, 0) == -1
+
+
+def _bc_model(prog, m):
+    from paper_1506_04651_amd import _lib
+    arr = (ctypes.c_double * len(prog))(*prog)
+    return _lib.RdModel(6, m, ctypes.cast(arr, ctypes.POINTER(ctypes.c_double)), len(prog)), arr
+
+
+def test_bytecode_programs_validated_on_the_host(lib):
+    """Register programs are checked before any device work: valid programs
+    pass (n = 0 does nothing), malformed ones return RD_EINVAL."""
+    from paper_1506_04651_amd import _lib
+    from paper_1506_04651_amd import workloads as W
+    call = lib.rd_reaction_step_ex
+    for prog, m in [(W.oregonator_program(), 3), (W.robertson_program(), 3),
+                    (W.nagumo_program(2.0), 1)]:
+        md, keep = _bc_model(list(prog), m)
+        assert call(None, 0, m, 0.1, 1e-5, 1e-8, ctypes.byref(md), None, None, None, 0) == 0
+    bad = [([1, 0, 10, 0, 0, 0], 1), ([1, 0, 0, 0, 0, 0], 1), ([1, 0, 9, 1, 0, 0], 1),
+           ([2, 0, 9, 0, 0, 0, 9, 0, 0, 0], 1), ([1, 0, 1, 5, 0, 0], 1),
+           ([2, 0, 1, 1, 2, 0, 9, 0, 1, 0], 1), ([2, 1, 2.0, 1, 1, 0, 0, 9, 0, 1, 0], 1),
+           ([1, 0, 9, 0, 40, 0], 1), ([1, 0, 9, 0, 0.5, 0], 1), ([1, 0, 9, 0, 0], 1),
+           ([1, 0, 9, 0, 0, 0], 5)]
+    for prog, m in bad:
+        md, keep = _bc_model(prog, m)
+        assert call(None, 0, m, 0.1, 1e-5, 1e-8, ctypes.byref(md), None, None, None, 0) == -1, prog
+    # a jacobian mode other than analytic / finite differences is invalid;
+    # finite differences of the group-kernel models are not provided
+    p = (ctypes.c_double * 4)(1e-2, 1e-5, 1.6, 2e-3)
+    good = _lib.RdModel(1, 3, ctypes.cast(p, ctypes.POINTER(ctypes.c_double)), 4)
+    o = _lib.default_options()
+    o.jacobian = 2
+    assert call(None, 0, 3, 0.1, 1e-5, 1e-8, ctypes.byref(good), ctypes.byref(o), None, None, 0) == -1
+    o.jacobian = 1
+    assert call(None, 0, 3, 0.1, 1e-5, 1e-8, ctypes.byref(good), ctypes.byref(o), None, None, 0) == 0
+    K = (ctypes.c_double * 512)(*([0.0] * 512))
+    kin = _lib.RdModel(2, 16, ctypes.cast(K, ctypes.POINTER(ctypes.c_double)), 512)
+    assert call(None, 0, 16, 0.1, 1e-5, 1e-8, ctypes.byref(kin), ctypes.byref(o), None, None, 0) == -1
 
 
 def test_product_path_does_not_reference_the_oracle():
