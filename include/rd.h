@@ -160,6 +160,46 @@ int64_t rd_reaction_step_ex(double* states, int64_t n_cells, int32_t m,
                             int32_t* stats, void* hip_stream, int32_t async);
 
 /* ------------------------------------------------------------------------ */
+/* The steps around the reaction step: diffusion and the Strang step on a     */
+/* uniform grid (Descombes et al., §2.1: U_{n+1} = R_{dt/2} D_dt R_{dt/2} U_n).  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t dim;          /* 2 or 3                                               */
+    int32_t nx, ny, nz;   /* cells per direction (nz = 1 when dim = 2); cell
+                             c = x + nx (y + ny z) of the states array          */
+    double h;             /* grid spacing, the same in every direction           */
+    const double* diff;   /* HOST, m diffusion coefficients eps_i >= 0            */
+} rd_grid;
+
+/*
+ * Diffusion step D_dt: dU/dt = A_eps U on the cell-centred grid, A_eps = eps_i
+ * times the centred 5-point (2D) / 7-point (3D) Laplacian with homogeneous
+ * Neumann boundaries (paper §2 and §1), advanced over dt by one step of the
+ * explicit stabilised second-order Runge-Kutta-Chebyshev method RKC (damping
+ * 2/13; Sommeijer, Shampine & Verwer 1997).  The paper's ROCK4 is of the same
+ * family but needs tabulated coefficients; RKC's follow in closed form.
+ * stages: 0 chooses s = 1 + floor(sqrt(1 + 1.54 dt rho)) (at least 2) from the
+ * Gershgorin bound rho = 4 dim max(eps) / h^2; > 0 forces that count (>= 2).
+ * states: DEVICE [m][nx*ny*nz], updated in place.  The library keeps four
+ * state-sized work vectors per (device, stream).  Synchronous on hip_stream
+ * (null = null stream).  Returns the number of stages used, or RD_EINVAL /
+ * RD_ENOMEM / RD_EDEVICE.
+ */
+int64_t rd_diffusion_step(double* states, int32_t m, const rd_grid* grid, double dt,
+                          int32_t stages, void* hip_stream);
+
+/*
+ * Strang step: R_{dt/2} (rd_reaction_step_ex with opts), then D_dt, then
+ * R_{dt/2}, in place, synchronous on hip_stream.  stats nullable: DEVICE
+ * [2][RD_NSTATS][n] int32, the counters of the first and second reaction half.
+ * opts->h_cells must be null.  Returns the sum of the failed-cell counts of
+ * the two reaction halves, or a negative error.
+ */
+int64_t rd_strang_step(double* states, int32_t m, const rd_grid* grid, double dt, double rtol,
+                       double atol, const rd_model* model, const rd_options* opts,
+                       int32_t* stats, void* hip_stream);
+
+/* ------------------------------------------------------------------------ */
 /* Serving: a session admits reaction-step requests into an HBM arena of a    */
 /* fixed byte budget.  Admitted requests are copied into the arena, batched   */
 /* with whatever else was admitted at the same time, and run by persistent    */

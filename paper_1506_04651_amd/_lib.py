@@ -36,6 +36,12 @@ class RdOptions(ctypes.Structure):
                 ("h_cells", ctypes.c_void_p)]
 
 
+class RdGrid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("h", ctypes.c_double),
+                ("diff", ctypes.POINTER(ctypes.c_double))]
+
+
 class RdRequestInfo(ctypes.Structure):
     _fields_ = [("done", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("n_failed", ctypes.c_int64), ("n_cells", ctypes.c_int64),
@@ -72,6 +78,13 @@ SIGNATURES = {
     "rd_set_default_variant": (ctypes.c_int32, [ctypes.c_int32] * 5),
     "rd_persistent_grid": (ctypes.c_int32, [ctypes.c_int32] * 4 + [ctypes.c_int64]),
     "rd_last_kernel_ms": (ctypes.c_double, []),
+    "rd_diffusion_step": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_int32,
+                                           ctypes.POINTER(RdGrid), ctypes.c_double,
+                                           ctypes.c_int32, ctypes.c_void_p]),
+    "rd_strang_step": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(RdGrid),
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        ctypes.POINTER(RdModel), ctypes.POINTER(RdOptions),
+                                        ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 _lib = None

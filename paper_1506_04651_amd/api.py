@@ -94,6 +94,61 @@ def reaction_step(states, dt, rtol, atol, kind, params, *, stats=None, stream=No
     return _check(ret)
 
 
+def _grid(shape, h, diff):
+    """rd_grid for a uniform grid of `shape` = (nx, ny) or (nx, ny, nz)."""
+    d = np.ascontiguousarray(diff, dtype=np.float64)
+    dims = tuple(int(v) for v in shape)
+    if len(dims) not in (2, 3):
+        raise ValueError("shape must be (nx, ny) or (nx, ny, nz)")
+    nz = dims[2] if len(dims) == 3 else 1
+    g = _lib.RdGrid(len(dims), dims[0], dims[1], nz, float(h),
+                    d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return g, d
+
+
+def diffusion_step(states, shape, h, diff, dt, *, stages=0, stream=None) -> int:
+    """D_dt on the uniform grid (cell c = x + nx (y + ny z)) in place: RKC
+    stabilised explicit steps for dU/dt = eps_i Lap_h U with zero-flux
+    boundaries.  Returns the stage count used."""
+    lib = _lib.load()
+    _check_states(states)
+    m, n = int(states.shape[0]), int(states.shape[1])
+    if int(np.prod(shape)) != n or len(diff) != m:
+        raise ValueError("grid shape / diff do not match states")
+    g, keep = _grid(shape, h, diff)
+    r = lib.rd_diffusion_step(ctypes.c_void_p(states.data_ptr()), m, ctypes.byref(g), float(dt),
+                              int(stages), _stream_handle(stream))
+    del keep
+    return _check(r)
+
+
+def strang_step(states, shape, h, diff, dt, rtol, atol, kind, params, *, stats=None,
+                stream=None, **opts) -> int:
+    """U <- R_{dt/2} D_dt R_{dt/2} U in place (paper §2.1).  stats: optional int32
+    CUDA tensor [2, 9, n] (counters of the two reaction halves).  Returns the
+    summed failed-cell counts of the two halves."""
+    import torch
+    lib = _lib.load()
+    _check_states(states)
+    m, n = int(states.shape[0]), int(states.shape[1])
+    if int(np.prod(shape)) != n or len(diff) != m:
+        raise ValueError("grid shape / diff do not match states")
+    sp = None
+    if stats is not None:
+        if not isinstance(stats, torch.Tensor) or stats.dtype != torch.int32 or not stats.is_cuda \
+                or tuple(stats.shape) != (2, _lib.NSTATS, n) or not stats.is_contiguous():
+            raise ValueError(f"stats must be a contiguous int32 CUDA tensor of shape [2, 9, {n}]")
+        sp = stats.data_ptr()
+    g, keep = _grid(shape, h, diff)
+    mdl, keep2 = _model(kind, m, params)
+    o = make_options(**opts)
+    r = lib.rd_strang_step(ctypes.c_void_p(states.data_ptr()), m, ctypes.byref(g), float(dt),
+                           float(rtol), float(atol), ctypes.byref(mdl), ctypes.byref(o),
+                           ctypes.c_void_p(sp) if sp else None, _stream_handle(stream))
+    del keep, keep2
+    return _check(r)
+
+
 def last_kernel_ms() -> float:
     """Duration of this thread's last reaction-step kernel (HIP events on its
     launch stream), in ms; negative if unavailable."""

@@ -1,0 +1,185 @@
+/*
+ * rd_strang.cpp -- C ABI of the diffusion step and of the Strang splitting
+ * step U_{n+1} = R_{dt/2} D_dt R_{dt/2} U_n (Descombes et al., §2.1) on a
+ * uniform grid: argument checks, the RKC stage coefficients, workspace, and
+ * the sequence of launches on the caller's stream.
+ */
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "rd_diffusion.h"
+#include "rd_internal.h"
+
+namespace rd {
+
+/* RKC2 with damping 2/13 (Sommeijer, Shampine & Verwer 1997): w0 = 1 +
+ * eps/s^2, w1 = T_s'(w0) / T_s''(w0), b_j = T_j''(w0) / T_j'(w0)^2 for j >= 2,
+ * b_0 = b_1 = b_2, a_j = 1 - b_j T_j(w0); stage j >= 2 weights mu_j = 2 b_j w0 /
+ * b_{j-1}, nu_j = -b_j / b_{j-2}, mut_j = 2 b_j w1 / b_{j-1}, gamt_j = -a_{j-1}
+ * mut_j, and mut_1 = b_1 w1.  T_j and its derivatives at w0 come from the
+ * three-term recurrence T_{j+1} = 2 x T_j - T_{j-1}. */
+static void rkc_weights(int s, double tau, double& mut1tau, std::vector<RkcStage>& st) {
+    const double damp = 2.0 / 13.0;
+    const double w0 = 1.0 + damp / ((double)s * s);
+    std::vector<double> T(s + 1), dT(s + 1), d2T(s + 1);
+    T[0] = 1.0; dT[0] = 0.0; d2T[0] = 0.0;
+    T[1] = w0;  dT[1] = 1.0; d2T[1] = 0.0;
+    for (int j = 1; j < s; ++j) {
+        T[j + 1] = 2.0 * w0 * T[j] - T[j - 1];
+        dT[j + 1] = 2.0 * T[j] + 2.0 * w0 * dT[j] - dT[j - 1];
+        d2T[j + 1] = 4.0 * dT[j] + 2.0 * w0 * d2T[j] - d2T[j - 1];
+    }
+    const double w1 = dT[s] / d2T[s];
+    std::vector<double> b(s + 1), a(s + 1);
+    for (int j = 2; j <= s; ++j) b[j] = d2T[j] / (dT[j] * dT[j]);
+    b[0] = b[1] = b[2];
+    for (int j = 0; j <= s; ++j) a[j] = 1.0 - b[j] * T[j];
+    mut1tau = b[1] * w1 * tau;
+    st.assign(s + 1, RkcStage{0, 0, 0, 0, 0});
+    for (int j = 2; j <= s; ++j) {
+        const double mu = 2.0 * b[j] * w0 / b[j - 1];
+        const double nu = -b[j] / b[j - 2];
+        const double mut = 2.0 * b[j] * w1 / b[j - 1];
+        st[j] = RkcStage{1.0 - mu - nu, mu, nu, mut * tau, -a[j - 1] * mut * tau};
+    }
+}
+
+/* smallest recommended stage count: 1 + floor(sqrt(1 + 1.54 tau rho)), >= 2 */
+static int rkc_stage_count(double tau_rho) {
+    const int s = 1 + (int)std::sqrt(1.0 + 1.54 * tau_rho);
+    return s < 2 ? 2 : s;
+}
+
+/* workspace per (device, stream): 4 state-sized vectors and the eps array;
+ * calls on one stream run in order, so they can share it */
+struct DiffWork {
+    double* buf = nullptr;
+    size_t cap = 0; /* doubles */
+    std::vector<double*> retired;
+};
+static std::mutex g_dw_mu;
+static std::map<std::pair<int, hipStream_t>, DiffWork> g_dw;
+
+static int diff_workspace(int device, hipStream_t s, size_t doubles, double** out) {
+    std::lock_guard<std::mutex> lk(g_dw_mu);
+    DiffWork& w = g_dw[{device, s}];
+    if (w.cap < doubles) {
+        double* p = nullptr;
+        const size_t cap = doubles + doubles / 4;
+        if (hipMalloc((void**)&p, cap * sizeof(double)) != hipSuccess) {
+            set_error("hipMalloc(diffusion workspace of %zu doubles) failed", cap);
+            return RD_ENOMEM;
+        }
+        /* an older buffer may still be in use by queued work on some stream */
+        if (w.buf) w.retired.push_back(w.buf);
+        w.buf = p;
+        w.cap = cap;
+    }
+    *out = w.buf;
+    return 0;
+}
+
+static bool grid_valid(const rd_grid* g, int32_t m) {
+    if (!g || (g->dim != 2 && g->dim != 3) || g->nx < 1 || g->ny < 1 || g->nz < 1) return false;
+    if (g->dim == 2 && g->nz != 1) return false;
+    if (!(g->h > 0.0) || !std::isfinite(g->h) || !g->diff) return false;
+    for (int i = 0; i < m; ++i)
+        if (!(g->diff[i] >= 0.0) || !std::isfinite(g->diff[i])) return false;
+    return true;
+}
+
+static int64_t diffusion_enqueue(double* states, int32_t m, const rd_grid* grid, double dt,
+                                 int32_t stages, hipStream_t s) {
+    if (m < 1 || m > RD_MAX_M || !grid_valid(grid, m)) {
+        set_error("invalid grid or species count");
+        return RD_EINVAL;
+    }
+    if (!std::isfinite(dt) || !(dt > 0.0) || stages < 0 || stages > 100000) {
+        set_error("dt must be finite and > 0, stages in [0, 100000]");
+        return RD_EINVAL;
+    }
+    const int64_t n = (int64_t)grid->nx * grid->ny * grid->nz;
+    if (!states) { set_error("states is null"); return RD_EINVAL; }
+    double emax = 0.0;
+    for (int i = 0; i < m; ++i) emax = std::fmax(emax, grid->diff[i]);
+    const double rho = 4.0 * grid->dim * emax / (grid->h * grid->h); /* Gershgorin */
+    const int sc = stages > 0 ? (stages < 2 ? 2 : stages) : rkc_stage_count(dt * rho);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        set_error("no current device");
+        return RD_EDEVICE;
+    }
+    const size_t vec = (size_t)m * (size_t)n;
+    double* w = nullptr;
+    if (int r = diff_workspace(dev, s, 4 * vec + 256, &w)) return r;
+    double* f0 = w;
+    double* b0 = w + vec;
+    double* b1 = w + 2 * vec;
+    double* b2 = w + 3 * vec;
+    double* eps = w + 4 * vec;
+    if (hipMemcpyAsync(eps, grid->diff, sizeof(double) * m, hipMemcpyHostToDevice, s) != hipSuccess) {
+        set_error("hipMemcpyAsync(eps) failed");
+        return RD_EDEVICE;
+    }
+    double mut1tau = 0.0;
+    std::vector<RkcStage> st;
+    rkc_weights(sc, dt, mut1tau, st);
+    DiffGrid g{grid->nx, grid->ny, grid->nz, n, 1.0 / (grid->h * grid->h)};
+    hipError_t e = launch_rkc(grid->dim, states, states, f0, b0, b1, b2, m, g, eps, mut1tau,
+                              st.data(), sc, s);
+    if (e != hipSuccess) {
+        set_error("diffusion launch: %s", hipGetErrorString(e));
+        return RD_EDEVICE;
+    }
+    return sc;
+}
+
+}  // namespace rd
+
+using namespace rd;
+
+extern "C" {
+
+int64_t rd_diffusion_step(double* states, int32_t m, const rd_grid* grid, double dt,
+                          int32_t stages, void* hip_stream) {
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int64_t r = diffusion_enqueue(states, m, grid, dt, stages, s);
+    if (r < 0) return r;
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        set_error("hipStreamSynchronize failed");
+        return RD_EDEVICE;
+    }
+    return r;
+}
+
+int64_t rd_strang_step(double* states, int32_t m, const rd_grid* grid, double dt, double rtol,
+                       double atol, const rd_model* model, const rd_options* opts,
+                       int32_t* stats, void* hip_stream) {
+    if (m < 1 || m > RD_MAX_M || !grid_valid(grid, m)) {
+        set_error("invalid grid or species count");
+        return RD_EINVAL;
+    }
+    if (!std::isfinite(dt) || !(dt > 0.0)) { set_error("dt must be finite and > 0"); return RD_EINVAL; }
+    const int64_t n = (int64_t)grid->nx * grid->ny * grid->nz;
+    if (opts && opts->h_cells) {
+        set_error("per-cell warm start is not supported by the Strang driver");
+        return RD_EINVAL;
+    }
+    const int64_t r1 = rd_reaction_step_ex(states, n, m, 0.5 * dt, rtol, atol, model, opts, stats,
+                                           hip_stream, 0);
+    if (r1 < 0) return r1;
+    const int64_t sd = diffusion_enqueue(states, m, grid, dt, 0, (hipStream_t)hip_stream);
+    if (sd < 0) return sd;
+    const int64_t r2 = rd_reaction_step_ex(states, n, m, 0.5 * dt, rtol, atol, model, opts,
+                                           stats ? stats + (size_t)RD_NSTATS * n : nullptr,
+                                           hip_stream, 0);
+    if (r2 < 0) return r2;
+    return r1 + r2;
+}
+
+}  // extern "C"

@@ -125,6 +125,34 @@ def test_bytecode_programs_validated_on_the_host(lib):
     assert call(None, 0, 16, 0.1, 1e-5, 1e-8, ctypes.byref(kin), ctypes.byref(o), None, None, 0) == -1
 
 
+def test_diffusion_and_strang_validation(lib):
+    """Malformed grids and steps are rejected before any device work."""
+    from paper_1506_04651_amd import _lib
+    eps = (ctypes.c_double * 3)(2.5e-3, 2.5e-3, 1.5e-3)
+    epsp = ctypes.cast(eps, ctypes.POINTER(ctypes.c_double))
+    dummy = ctypes.c_void_p(1)
+    bad_grids = [_lib.RdGrid(1, 8, 8, 1, 0.1, epsp), _lib.RdGrid(2, 8, 8, 2, 0.1, epsp),
+                 _lib.RdGrid(3, 0, 8, 8, 0.1, epsp), _lib.RdGrid(2, 8, 8, 1, 0.0, epsp),
+                 _lib.RdGrid(2, 8, 8, 1, float("nan"), epsp), _lib.RdGrid(2, 8, 8, 1, 0.1, None)]
+    for g in bad_grids:
+        assert lib.rd_diffusion_step(dummy, 3, ctypes.byref(g), 1e-3, 0, None) == -1
+    g = _lib.RdGrid(2, 8, 8, 1, 0.1, epsp)
+    assert lib.rd_diffusion_step(dummy, 3, ctypes.byref(g), 0.0, 0, None) == -1
+    assert lib.rd_diffusion_step(dummy, 3, ctypes.byref(g), 1e-3, -1, None) == -1
+    assert lib.rd_diffusion_step(None, 3, ctypes.byref(g), 1e-3, 0, None) == -1
+    neg = (ctypes.c_double * 3)(2.5e-3, -1.0, 1.5e-3)
+    g2 = _lib.RdGrid(2, 8, 8, 1, 0.1, ctypes.cast(neg, ctypes.POINTER(ctypes.c_double)))
+    assert lib.rd_diffusion_step(dummy, 3, ctypes.byref(g2), 1e-3, 0, None) == -1
+    p = (ctypes.c_double * 4)(1e-2, 1e-5, 1.6, 2e-3)
+    md = _lib.RdModel(1, 3, ctypes.cast(p, ctypes.POINTER(ctypes.c_double)), 4)
+    assert lib.rd_strang_step(dummy, 3, ctypes.byref(bad_grids[0]), 1e-3, 1e-5, 1e-8,
+                              ctypes.byref(md), None, None, None) == -1
+    o = _lib.default_options()
+    o.h_cells = 1
+    assert lib.rd_strang_step(dummy, 3, ctypes.byref(g), 1e-3, 1e-5, 1e-8,
+                              ctypes.byref(md), ctypes.byref(o), None, None) == -1
+
+
 def test_product_path_does_not_reference_the_oracle():
     pkg = os.path.join(ROOT, "paper_1506_04651_amd")
     for dp, _, files in os.walk(pkg):
