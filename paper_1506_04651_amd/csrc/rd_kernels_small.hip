@@ -42,6 +42,10 @@ hipError_t launch_reset(unsigned long long* p, int n, hipStream_t s) {
     RD_PERS(KIND, MODEL, M, PREC, LT, false, 6, 128, 1, 56, TAG ".persistent.b128.fs56"),     \
     RD_PERS(KIND, MODEL, M, PREC, LT, false, 7, 256, 1, 40, TAG ".persistent.b256.fs40"),     \
     RD_PERS(KIND, MODEL, M, PREC, LT, false, 8, 64, 1, 40, TAG ".persistent.b64.fs40"),       \
+    RD_PERS(KIND, MODEL, M, PREC, LT, false, 9, 128, 3, 40, TAG ".persistent.b128.w3.fs40"),  \
+    RD_PERS_K(KIND, MODEL, M, PREC, LT, 10, 128, 1, 40, TAG ".persistent.b128.fs40.kp"),      \
+    RD_PERS_K(KIND, MODEL, M, PREC, LT, 11, 64, 1, 40, TAG ".persistent.b64.fs40.kp"),        \
+    RD_PERS_K(KIND, MODEL, M, PREC, LT, 12, 256, 1, 48, TAG ".persistent.b256.fs48.kp"),      \
     RD_ONE(KIND, MODEL, M, PREC, LT, false, 2, 256, 1, 16, TAG ".onelaunch.b256.fs16"),       \
     RD_ONE(KIND, MODEL, M, PREC, LT, false, 3, 256, 1, 1, TAG ".onelaunch.b256.fs1")
 

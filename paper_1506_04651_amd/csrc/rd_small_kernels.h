@@ -68,13 +68,17 @@ k_onelaunch(LaunchArgs a) {
  * chunk (at least kClaimChunk positions) with a single atomic. */
 constexpr unsigned kClaimChunk = 16;
 
-template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN>
+/* PLDS: the step parameters are staged in LDS and re-read each pass (true),
+ * or read from the kernel arguments, where the compiler keeps them in scalar
+ * registers across the loop (false).  Same arithmetic either way. */
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool PLDS = true>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_persistent(LaunchArgs a) {
     using L = SmallLds<Model::M>;
     __shared__ double sh[L::ROWS * BLOCK];
-    __shared__ StepParams sP;
-    stage_params(sP, a.P);
+    __shared__ StepParams sPl;
+    if (PLDS) stage_params(sPl, a.P);
+    const StepParams& sP = PLDS ? sPl : a.P;
     const Model md(a.params);
     SmallCell<Model, LT, BLOCK> cell;
     cell.lds.base = sh + threadIdx.x;
@@ -122,7 +126,7 @@ k_persistent(LaunchArgs a) {
             }
         }
         if (__ballot(alive) == 0ull) break;
-        __asm__ volatile("" ::: "memory"); /* re-read sP from LDS each pass */
+        if (PLDS) __asm__ volatile("" ::: "memory"); /* re-read sP from LDS each pass */
         advance<Model, LT, FIXED, BLOCK, FSMIN>(cell, md, sP);
     }
 }
@@ -135,10 +139,10 @@ hipError_t launch_one(const LaunchArgs& a, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN>
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool PLDS = true>
 hipError_t launch_pers(const LaunchArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_persistent<Model, LT, FIXED, BLOCK, WPE, FSMIN>), dim3(grid), dim3(BLOCK), 0,
-                       s, a);
+    hipLaunchKernelGGL((k_persistent<Model, LT, FIXED, BLOCK, WPE, FSMIN, PLDS>), dim3(grid),
+                       dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
@@ -146,6 +150,10 @@ hipError_t launch_pers(const LaunchArgs& a, int grid, hipStream_t s) {
     {KIND, fd_jac_of<MODEL>::value ? 1 : 0, M, PREC, 1, FIXED, VAR, BLOCK, BLOCK, NAME,                                          \
      &launch_one<MODEL, LT, FIXED, BLOCK, WPE, FS>,                                             \
      (const void*)&k_onelaunch<MODEL, LT, FIXED, BLOCK, WPE, FS>}
+#define RD_PERS_K(KIND, MODEL, M, PREC, LT, VAR, BLOCK, WPE, FS, NAME)                          \
+    {KIND, fd_jac_of<MODEL>::value ? 1 : 0, M, PREC, 0, false, VAR, BLOCK, BLOCK, NAME,           \
+     &launch_pers<MODEL, LT, false, BLOCK, WPE, FS, false>,                                     \
+     (const void*)&k_persistent<MODEL, LT, false, BLOCK, WPE, FS, false>}
 #define RD_PERS(KIND, MODEL, M, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, NAME)                      \
     {KIND, fd_jac_of<MODEL>::value ? 1 : 0, M, PREC, 0, FIXED, VAR, BLOCK, BLOCK, NAME,                                          \
      &launch_pers<MODEL, LT, FIXED, BLOCK, WPE, FS>,                                            \
