@@ -46,6 +46,12 @@ hipError_t launch_reset(unsigned long long* p, int n, hipStream_t s) {
     RD_PERS_K(KIND, MODEL, M, PREC, LT, 10, 128, 1, 40, TAG ".persistent.b128.fs40.kp"),      \
     RD_PERS_K(KIND, MODEL, M, PREC, LT, 11, 64, 1, 40, TAG ".persistent.b64.fs40.kp"),        \
     RD_PERS_K(KIND, MODEL, M, PREC, LT, 12, 256, 1, 48, TAG ".persistent.b256.fs48.kp"),      \
+    RD_PERS(KIND, MODEL, M, PREC, LT, false, 13, 128, 3, 32, TAG ".persistent.b128.w3.fs32"),  \
+    RD_PERS(KIND, MODEL, M, PREC, LT, false, 14, 128, 3, 48, TAG ".persistent.b128.w3.fs48"),  \
+    RD_PERS(KIND, MODEL, M, PREC, LT, false, 15, 64, 3, 40, TAG ".persistent.b64.w3.fs40"),    \
+    RD_PERS(KIND, MODEL, M, PREC, LT, false, 16, 192, 3, 40, TAG ".persistent.b192.w3.fs40"),  \
+    RD_PERS(KIND, MODEL, M, PREC, LT, false, 17, 128, 4, 40, TAG ".persistent.b128.w4.fs40"),  \
+    RD_PERS_K(KIND, MODEL, M, PREC, LT, 18, 128, 3, 40, TAG ".persistent.b128.w3.fs40.kp"),   \
     RD_ONE(KIND, MODEL, M, PREC, LT, false, 2, 256, 1, 16, TAG ".onelaunch.b256.fs16"),       \
     RD_ONE(KIND, MODEL, M, PREC, LT, false, 3, 256, 1, 1, TAG ".onelaunch.b256.fs1")
 
