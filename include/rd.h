@@ -200,6 +200,53 @@ int64_t rd_strang_step(double* states, int32_t m, const rd_grid* grid, double dt
                        int32_t* stats, void* hip_stream);
 
 /* ------------------------------------------------------------------------ */
+/* Multiresolution leaf sets (Descombes et al., §2.2 after Cohen et al. 2003;  */
+/* node keys §3.1) on the dyadic tree of [0,1]^d, d = 2, 3.                     */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t dim;          /* 2 or 3                                               */
+    int32_t levels;       /* J >= 1, the finest level: 2^J cells per direction;
+                             dim * J <= 30                                        */
+    double eps;           /* threshold eps >= 0; level thresholds
+                             eps_j = 2^((dim/2)(j - J)) eps                        */
+    const double* scale;  /* HOST, m per-species detail scales s_i > 0, or null
+                             (all 1)                                              */
+} rd_mra_params;
+
+/*
+ * Leaf set of the graded tree built from a field on the finest level: node
+ * values by projection (average of the 2^dim children); details d = u -
+ * prediction, the prediction being the third-order centred interpolation
+ * (l = 1) applied as a tensor product one direction at a time, with even
+ * reflection at the domain edge; a node gets children when one of them has
+ * (1/m) sum_i (d_i / s_i)^2 >= eps_j^2; grading: a node with children makes
+ * the parents of its 3^dim neighbours get children (finest to coarsest).
+ * fine: DEVICE [m][2^(dim J)] float64, x fastest (cell x + N (y + N z)).
+ * Output in Morton order of the leaves: keys DEVICE [n_leaves] uint64 (the
+ * level-j Morton index, bits of x, y[, z] interleaved with x most significant,
+ * left-aligned in bits 63..16; the level in bits 15..12; bits 11..0 zero) and
+ * values DEVICE [m][n_leaves] (cell averages, packed with stride n_leaves),
+ * written only when n_leaves <= capacity (values must hold m * capacity
+ * doubles).  level_counts: HOST [J + 1] or null, leaves per level (when
+ * written).  Synchronous.  Returns n_leaves, or RD_EINVAL / RD_ENOMEM /
+ * RD_EDEVICE.  Workspace (the whole pyramid) is kept per (device, stream).
+ */
+int64_t rd_mra_leaves(const double* fine, int32_t m, const rd_mra_params* params,
+                      uint64_t* keys, double* values, int64_t capacity,
+                      int64_t* level_counts, void* hip_stream);
+
+/*
+ * Inverse: the finest-level field from a leaf set (keys, values as written by
+ * rd_mra_leaves): tree nodes valued by projection of the leaves, every node
+ * outside the tree predicted level by level from the coarser one.  fine:
+ * DEVICE [m][2^(dim J)] output, x fastest.  Keys that do not name a node of
+ * the tree are ignored.  Synchronous.  Returns 0 or a negative error.
+ */
+int64_t rd_mra_reconstruct(const uint64_t* keys, const double* values, int64_t n_leaves,
+                           int32_t m, const rd_mra_params* params, double* fine,
+                           void* hip_stream);
+
+/* ------------------------------------------------------------------------ */
 /* Serving: a session admits reaction-step requests into an HBM arena of a    */
 /* fixed byte budget.  Admitted requests are copied into the arena, batched   */
 /* with whatever else was admitted at the same time, and run by persistent    */

@@ -42,6 +42,11 @@ class RdGrid(ctypes.Structure):
                 ("diff", ctypes.POINTER(ctypes.c_double))]
 
 
+class RdMraParams(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("levels", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("scale", ctypes.POINTER(ctypes.c_double))]
+
+
 class RdRequestInfo(ctypes.Structure):
     _fields_ = [("done", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("n_failed", ctypes.c_int64), ("n_cells", ctypes.c_int64),
@@ -81,6 +86,12 @@ SIGNATURES = {
     "rd_diffusion_step": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_int32,
                                            ctypes.POINTER(RdGrid), ctypes.c_double,
                                            ctypes.c_int32, ctypes.c_void_p]),
+    "rd_mra_leaves": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(RdMraParams),
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
+    "rd_mra_reconstruct": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                            ctypes.c_int32, ctypes.POINTER(RdMraParams),
+                                            ctypes.c_void_p, ctypes.c_void_p]),
     "rd_strang_step": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(RdGrid),
                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                         ctypes.POINTER(RdModel), ctypes.POINTER(RdOptions),

@@ -149,6 +149,59 @@ def strang_step(states, shape, h, diff, dt, rtol, atol, kind, params, *, stats=N
     return _check(r)
 
 
+def _mra_params(dim, levels, eps, scale, m):
+    sc = None if scale is None else np.ascontiguousarray(scale, dtype=np.float64)
+    if sc is not None and sc.size != m:
+        raise ValueError("scale needs one value per species")
+    p = _lib.RdMraParams(int(dim), int(levels), float(eps),
+                         None if sc is None else sc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return p, sc
+
+
+def mra_leaves(fine, dim, levels, eps, *, scale=None, stream=None):
+    """Leaf set of the graded multiresolution tree of `fine` ([m, 2^(dim levels)]
+    float64 CUDA tensor, x fastest).  Returns (keys int64 CUDA tensor holding
+    the uint64 node keys in Morton order, values [m, n_leaves] CUDA tensor,
+    per-level leaf counts as a list)."""
+    import torch
+    lib = _lib.load()
+    _check_states(fine)
+    m = int(fine.shape[0])
+    if int(fine.shape[1]) != 1 << (dim * levels):
+        raise ValueError("fine must hold 2^(dim*levels) cells per species")
+    p, keep = _mra_params(dim, levels, eps, scale, m)
+    sh = _stream_handle(stream)
+    n = _check(lib.rd_mra_leaves(ctypes.c_void_p(fine.data_ptr()), m, ctypes.byref(p), None, None, 0,
+                                 None, sh))
+    keys = torch.empty(n, dtype=torch.int64, device=fine.device)
+    vals = torch.empty((m, n), dtype=torch.float64, device=fine.device)
+    counts = (ctypes.c_int64 * (levels + 1))()
+    n2 = _check(lib.rd_mra_leaves(ctypes.c_void_p(fine.data_ptr()), m, ctypes.byref(p),
+                                  ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(vals.data_ptr()),
+                                  n, counts, sh))
+    del keep
+    if n2 != n:
+        raise RuntimeError("leaf count changed between calls")
+    return keys, vals, list(counts)
+
+
+def mra_reconstruct(keys, values, dim, levels, *, scale=None, stream=None):
+    """Finest-level field ([m, 2^(dim levels)], x fastest) from a leaf set."""
+    import torch
+    lib = _lib.load()
+    _check_states(values)
+    m, n = int(values.shape[0]), int(values.shape[1])
+    if keys.dtype != torch.int64 or not keys.is_cuda or tuple(keys.shape) != (n,):
+        raise ValueError("keys must be an int64 CUDA tensor of n_leaves entries")
+    p, keep = _mra_params(dim, levels, 0.0, scale, m)
+    out = torch.empty((m, 1 << (dim * levels)), dtype=torch.float64, device=values.device)
+    _check(lib.rd_mra_reconstruct(ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(values.data_ptr()),
+                                  n, m, ctypes.byref(p), ctypes.c_void_p(out.data_ptr()),
+                                  _stream_handle(stream)))
+    del keep
+    return out
+
+
 def last_kernel_ms() -> float:
     """Duration of this thread's last reaction-step kernel (HIP events on its
     launch stream), in ms; negative if unavailable."""

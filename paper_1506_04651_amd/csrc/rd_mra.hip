@@ -1,0 +1,529 @@
+/*
+ * rd_mra.hip -- multiresolution leaf sets on the GPU (Descombes et al., §2.2
+ * after Cohen et al. 2003; node keys of §3.1): from a field on the finest
+ * uniform level J of the dyadic tree of [0,1]^d (d = 2, 3), build the graded
+ * tree whose leaves are the adapted grid, and go back (reconstruction).
+ *
+ * GPU layout: every level j of the tree is a dense array of 2^(d j) nodes per
+ * species, in Morton order (index = bits of x, y[, z] interleaved, x most
+ * significant in each group), so the 2^d children of node p are the
+ * consecutive indices 2^d p .. 2^d p + 2^d - 1 and projection reads
+ * contiguous memory.  Per level a byte array R_j marks the nodes that have
+ * children.  One kernel per level and operation:
+ *   projection      node = average of its 2^d children;
+ *   details + flags one thread per parent: predicts its 2^d children from the
+ *                   3^d parent-level stencil (third order, tensor product of
+ *                   the 1D operator, one direction at a time, even reflection
+ *                   at the domain edge), details d = u - prediction, and
+ *                   R_{j-1}[p] = some child with (1/m) sum_i (d_i/s_i)^2 >= eps_j^2,
+ *                   eps_j^2 = 2^(d (j-J)) eps^2;
+ *   grading         finest to coarsest: a node with children makes the
+ *                   parents of its 3^d neighbours get children;
+ *   leaves          one thread per finest cell finds the leaf covering it;
+ *                   the first cell of each leaf emits the leaf, compacted in
+ *                   Morton order by a block count, a scan and a write pass.
+ * Keys: the level-j Morton index left-aligned in bits 63..16 (48-bit
+ * abscissa), the level in bits 15..12, bits 11..0 free.
+ *
+ * The detail decision compares floating-point numbers against a threshold;
+ * this file is compiled without contraction and evaluates every formula in
+ * a fixed order, so the decisions are reproducible operation by operation.
+ */
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "rd_internal.h"
+
+namespace rd {
+
+/* ---------------------------------------------------------------- Morton */
+__host__ __device__ __forceinline__ int64_t morton_encode(const int* c, int d, int bits) {
+    int64_t out = 0;
+    for (int b = 0; b < bits; ++b)
+        for (int a = 0; a < d; ++a)
+            out |= (int64_t)((c[a] >> b) & 1) << (d * b + (d - 1 - a));
+    return out;
+}
+__host__ __device__ __forceinline__ void morton_decode(int64_t idx, int d, int bits, int* c) {
+    for (int a = 0; a < d; ++a) c[a] = 0;
+    for (int b = 0; b < bits; ++b)
+        for (int a = 0; a < d; ++a) c[a] |= (int)((idx >> (d * b + (d - 1 - a))) & 1) << b;
+}
+
+struct Pyr {
+    int d, J, m;
+    int64_t total;          /* nodes over all levels, per species */
+    int64_t off[25];        /* start of level j within a species plane */
+    double* U;              /* [m][total] */
+    unsigned char* R;       /* [total] refine flags (finest level unused) */
+    unsigned char* T;       /* [total] tree membership (reconstruction) */
+};
+
+__device__ __forceinline__ double* lvl(const Pyr& P, int i, int j) {
+    return P.U + (int64_t)i * P.total + P.off[j];
+}
+
+/* even reflection at the domain edge */
+__device__ __forceinline__ int clampc(int c, int N) { return c < 0 ? 0 : (c >= N ? N - 1 : c); }
+
+/* Prediction of the child with per-axis bits cb of the level-jc node with
+ * coordinates pc, from level-jc values uc, one direction at a time. */
+template <int D>
+__device__ __forceinline__ double predict(const double* uc, int jc, const int* pc, const int* cb) {
+    const int N = 1 << jc;
+    double sg[3];
+    for (int a = 0; a < D; ++a) sg[a] = cb[a] == 0 ? 0.125 : -0.125;
+    if (D == 2) {
+        double rows[3];
+        for (int oy = -1; oy <= 1; ++oy) {
+            int c0[2] = {clampc(pc[0] - 1, N), clampc(pc[1] + oy, N)};
+            int c1[2] = {clampc(pc[0], N), clampc(pc[1] + oy, N)};
+            int c2[2] = {clampc(pc[0] + 1, N), clampc(pc[1] + oy, N)};
+            const double vm = uc[morton_encode(c0, 2, jc)];
+            const double v0 = uc[morton_encode(c1, 2, jc)];
+            const double vp = uc[morton_encode(c2, 2, jc)];
+            const double dif = vm - vp;
+            const double t = sg[0] * dif;
+            rows[oy + 1] = v0 + t;
+        }
+        const double dif = rows[0] - rows[2];
+        const double t = sg[1] * dif;
+        return rows[1] + t;
+    } else {
+        double planes[3];
+        for (int oz = -1; oz <= 1; ++oz) {
+            double rows[3];
+            for (int oy = -1; oy <= 1; ++oy) {
+                int c0[3] = {clampc(pc[0] - 1, N), clampc(pc[1] + oy, N), clampc(pc[2] + oz, N)};
+                int c1[3] = {clampc(pc[0], N), clampc(pc[1] + oy, N), clampc(pc[2] + oz, N)};
+                int c2[3] = {clampc(pc[0] + 1, N), clampc(pc[1] + oy, N), clampc(pc[2] + oz, N)};
+                const double vm = uc[morton_encode(c0, 3, jc)];
+                const double v0 = uc[morton_encode(c1, 3, jc)];
+                const double vp = uc[morton_encode(c2, 3, jc)];
+                const double dif = vm - vp;
+                const double t = sg[0] * dif;
+                rows[oy + 1] = v0 + t;
+            }
+            const double dif = rows[0] - rows[2];
+            const double t = sg[1] * dif;
+            planes[oz + 1] = rows[1] + t;
+        }
+        const double dif = planes[0] - planes[2];
+        const double t = sg[2] * dif;
+        return planes[1] + t;
+    }
+}
+
+/* ---------------------------------------------------------------- kernels */
+template <int D>
+__global__ void k_to_morton(const double* __restrict__ fine, Pyr P) {
+    const int64_t n = P.off[P.J + 1] - P.off[P.J];
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int N = 1 << P.J;
+    int c[3];
+    int64_t t = r;
+    for (int a = 0; a < D; ++a) { c[a] = (int)(t % N); t /= N; }
+    const int64_t k = morton_encode(c, D, P.J);
+    for (int i = 0; i < P.m; ++i) lvl(P, i, P.J)[k] = fine[(int64_t)i * n + r];
+}
+
+template <int D>
+__global__ void k_from_morton(double* __restrict__ fine, Pyr P) {
+    const int64_t n = P.off[P.J + 1] - P.off[P.J];
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int N = 1 << P.J;
+    int c[3];
+    int64_t t = r;
+    for (int a = 0; a < D; ++a) { c[a] = (int)(t % N); t /= N; }
+    const int64_t k = morton_encode(c, D, P.J);
+    for (int i = 0; i < P.m; ++i) fine[(int64_t)i * n + r] = lvl(P, i, P.J)[k];
+}
+
+/* level j -> j-1: node = average of its 2^D children (summed in child order) */
+template <int D>
+__global__ void k_project(Pyr P, int j) {
+    const int64_t np = (int64_t)1 << (D * (j - 1));
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    constexpr int NC = 1 << D;
+    for (int i = 0; i < P.m; ++i) {
+        const double* u = lvl(P, i, j) + p * NC;
+        double s = u[0];
+        for (int c = 1; c < NC; ++c) s = s + u[c];
+        lvl(P, i, j - 1)[p] = s * (1.0 / NC);
+    }
+}
+
+/* details of the children of level-(j-1) node p and its refine flag */
+template <int D>
+__global__ void k_detail_flags(Pyr P, int j, double eps_j2, const double* __restrict__ scale) {
+    const int jc = j - 1;
+    const int64_t np = (int64_t)1 << (D * jc);
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    constexpr int NC = 1 << D;
+    int pc[3];
+    morton_decode(p, D, jc, pc);
+    bool sig = false;
+    const double invm = 1.0 / P.m;
+    for (int c = 0; c < NC; ++c) {
+        int cb[3];
+        for (int a = 0; a < D; ++a) cb[a] = (c >> (D - 1 - a)) & 1;
+        double acc = 0.0;
+        for (int i = 0; i < P.m; ++i) {
+            const double pred = predict<D>(lvl(P, i, jc), jc, pc, cb);
+            const double dd = lvl(P, i, j)[p * NC + c] - pred;
+            const double q = dd / scale[i];
+            acc = (i == 0) ? q * q : acc + q * q;
+        }
+        sig = sig || (acc * invm >= eps_j2);
+    }
+    if (sig) P.R[P.off[jc] + p] = 1;
+}
+
+/* grading: a node of level j with children makes the parents of its 3^D
+ * neighbours (inside the domain) get children */
+template <int D>
+__global__ void k_grade(Pyr P, int j) {
+    const int64_t nj = (int64_t)1 << (D * j);
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nj || !P.R[P.off[j] + k]) return;
+    const int N = 1 << j;
+    int c[3];
+    morton_decode(k, D, j, c);
+    const int lo2 = D == 3 ? -1 : 0, hi2 = D == 3 ? 1 : 0;
+    for (int oz = lo2; oz <= hi2; ++oz)
+        for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox) {
+                int nb[3] = {c[0] + ox, c[1] + oy, D == 3 ? c[2] + oz : 0};
+                bool in = true;
+                for (int a = 0; a < D; ++a) in = in && nb[a] >= 0 && nb[a] < N;
+                if (!in) continue;
+                const int64_t q = morton_encode(nb, D, j);
+                P.R[P.off[j - 1] + (q >> D)] = 1;
+            }
+}
+
+/* level of the leaf covering finest cell f (Morton), and whether f is the
+ * first finest cell of that leaf */
+__device__ __forceinline__ int leaf_of(const Pyr& P, int64_t f, int d, bool& first) {
+    for (int j = 0; j <= P.J; ++j) {
+        const int64_t k = f >> (d * (P.J - j));
+        const bool exists = (j == 0) || P.R[P.off[j - 1] + (k >> d)];
+        const bool refined = (j < P.J) && P.R[P.off[j] + k];
+        if (exists && !refined) {
+            first = (f & (((int64_t)1 << (d * (P.J - j))) - 1)) == 0;
+            return j;
+        }
+    }
+    first = false;
+    return -1;
+}
+
+constexpr int kLeafBlock = 256;
+
+__global__ void k_leaf_count(Pyr P, int d, unsigned* __restrict__ block_count) {
+    const int64_t n = P.off[P.J + 1] - P.off[P.J];
+    const int64_t f = (int64_t)blockIdx.x * kLeafBlock + threadIdx.x;
+    bool first = false;
+    if (f < n) (void)leaf_of(P, f, d, first);
+    const unsigned cnt = (unsigned)__popcll(__ballot(first));
+    __shared__ unsigned wsum[kLeafBlock / 64];
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned s = 0;
+        for (int w = 0; w < kLeafBlock / 64; ++w) s += wsum[w];
+        block_count[blockIdx.x] = s;
+    }
+}
+
+/* exclusive scan of nb block counts in one block of 1024 threads; the total
+ * goes to out[nb] */
+__global__ void k_scan_blocks(const unsigned* __restrict__ in, unsigned long long* __restrict__ out,
+                              int64_t nb) {
+    __shared__ unsigned long long part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t b0 = t * per, b1 = (b0 + per < nb) ? b0 + per : nb;
+    unsigned long long s = 0;
+    for (int64_t b = b0; b < b1; ++b) s += in[b];
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        unsigned long long run = 0;
+        for (int i = 0; i < 1024; ++i) {
+            const unsigned long long v = part[i];
+            part[i] = run;
+            run += v;
+        }
+        out[nb] = run;
+    }
+    __syncthreads();
+    unsigned long long run = part[t];
+    for (int64_t b = b0; b < b1; ++b) {
+        out[b] = run;
+        run += in[b];
+    }
+}
+
+__global__ void k_leaf_write(Pyr P, int d, const unsigned long long* __restrict__ block_off,
+                             uint64_t* __restrict__ keys, double* __restrict__ values,
+                             int64_t n_leaves) {
+    const int64_t n = P.off[P.J + 1] - P.off[P.J];
+    const int64_t f = (int64_t)blockIdx.x * kLeafBlock + threadIdx.x;
+    bool first = false;
+    int j = -1;
+    if (f < n) j = leaf_of(P, f, d, first);
+    const unsigned long long mask = __ballot(first);
+    __shared__ unsigned wsum[kLeafBlock / 64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) wsum[w] = (unsigned)__popcll(mask);
+    __syncthreads();
+    if (!first) return;
+    unsigned before = 0;
+    for (int i = 0; i < w; ++i) before += wsum[i];
+    before += (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
+    const int64_t pos = (int64_t)block_off[blockIdx.x] + before;
+    if (pos >= n_leaves) return;
+    const int64_t k = f >> (d * (P.J - j));
+    keys[pos] = (j == 0 ? 0ull : ((uint64_t)k << (64 - d * j))) | ((uint64_t)j << 12);
+    for (int i = 0; i < P.m; ++i) values[(int64_t)i * n_leaves + pos] = lvl(P, i, j)[k];
+}
+
+/* reconstruction: leaves into their levels, tree membership */
+__global__ void k_scatter_leaves(Pyr P, int d, const uint64_t* __restrict__ keys,
+                                 const double* __restrict__ values, int64_t n_leaves) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_leaves) return;
+    const uint64_t key = keys[t];
+    const int j = (int)((key >> 12) & 15u);
+    if (j > P.J) return;
+    const int64_t k = j == 0 ? 0 : (int64_t)(key >> (64 - d * j));
+    if (k >= ((int64_t)1 << (d * j))) return;
+    P.T[P.off[j] + k] = 1;
+    for (int i = 0; i < P.m; ++i) lvl(P, i, j)[k] = values[(int64_t)i * n_leaves + t];
+}
+
+/* parents of tree nodes are tree nodes valued by the average of children */
+template <int D>
+__global__ void k_tree_up(Pyr P, int j) {
+    const int64_t np = (int64_t)1 << (D * (j - 1));
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    constexpr int NC = 1 << D;
+    bool any = false;
+    for (int c = 0; c < NC; ++c) any = any || P.T[P.off[j] + p * NC + c];
+    if (!any) return;
+    P.T[P.off[j - 1] + p] = 1;
+    for (int i = 0; i < P.m; ++i) {
+        const double* u = lvl(P, i, j) + p * NC;
+        double s = u[0];
+        for (int c = 1; c < NC; ++c) s = s + u[c];
+        lvl(P, i, j - 1)[p] = s * (1.0 / NC);
+    }
+}
+
+/* nodes outside the tree are predicted from the (complete) coarser level */
+template <int D>
+__global__ void k_fill_down(Pyr P, int j) {
+    const int64_t nj = (int64_t)1 << (D * j);
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nj || P.T[P.off[j] + k]) return;
+    int pc[3], cb[3];
+    morton_decode(k >> D, D, j - 1, pc);
+    for (int a = 0; a < D; ++a) cb[a] = (int)((k >> (D - 1 - a)) & 1);
+    for (int i = 0; i < P.m; ++i) lvl(P, i, j)[k] = predict<D>(lvl(P, i, j - 1), j - 1, pc, cb);
+}
+
+/* ---------------------------------------------------------------- host */
+struct MraWork {
+    void* buf = nullptr;
+    size_t cap = 0;
+    std::vector<void*> retired;
+};
+static std::mutex g_mra_mu;
+static std::map<std::pair<int, hipStream_t>, MraWork> g_mra;
+
+static void* mra_workspace(hipStream_t s, size_t bytes, int* err) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) { *err = RD_EDEVICE; return nullptr; }
+    std::lock_guard<std::mutex> lk(g_mra_mu);
+    MraWork& w = g_mra[{dev, s}];
+    if (w.cap < bytes) {
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            set_error("hipMalloc(MRA workspace of %zu bytes) failed", bytes);
+            *err = RD_ENOMEM;
+            return nullptr;
+        }
+        if (w.buf) w.retired.push_back(w.buf);
+        w.buf = p;
+        w.cap = bytes;
+    }
+    return w.buf;
+}
+
+static bool mra_params_valid(const rd_mra_params* p, int32_t m) {
+    if (!p || (p->dim != 2 && p->dim != 3) || m < 1 || m > RD_MAX_M) return false;
+    if (p->levels < 1 || p->dim * p->levels > 30) return false; /* <= 2^30 finest cells */
+    if (!std::isfinite(p->eps) || p->eps < 0.0) return false;
+    if (p->scale)
+        for (int i = 0; i < m; ++i)
+            if (!(p->scale[i] > 0.0) || !std::isfinite(p->scale[i])) return false;
+    return true;
+}
+
+/* pyramid + flags + scratch, laid out in one workspace */
+static int setup_pyr(const rd_mra_params* p, int32_t m, hipStream_t s, Pyr& P, double** scale_dev,
+                     unsigned** bcount, unsigned long long** boff, int64_t* nblocks) {
+    P.d = p->dim;
+    P.J = p->levels;
+    P.m = m;
+    int64_t off = 0;
+    for (int j = 0; j <= P.J; ++j) {
+        P.off[j] = off;
+        off += (int64_t)1 << (P.d * j);
+    }
+    P.off[P.J + 1] = off;
+    P.total = off;
+    const int64_t nfine = (int64_t)1 << (P.d * P.J);
+    *nblocks = (nfine + kLeafBlock - 1) / kLeafBlock;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t bU = al(sizeof(double) * (size_t)m * P.total);
+    const size_t bR = al((size_t)P.total);
+    const size_t bS = al(sizeof(double) * m);
+    const size_t bC = al(sizeof(unsigned) * (size_t)*nblocks);
+    const size_t bO = al(sizeof(unsigned long long) * ((size_t)*nblocks + 1));
+    int err = 0;
+    char* w = (char*)mra_workspace(s, bU + 2 * bR + bS + bC + bO, &err);
+    if (!w) return err ? err : RD_ENOMEM;
+    P.U = (double*)w;
+    P.R = (unsigned char*)(w + bU);
+    P.T = (unsigned char*)(w + bU + bR);
+    *scale_dev = (double*)(w + bU + 2 * bR);
+    *bcount = (unsigned*)(w + bU + 2 * bR + bS);
+    *boff = (unsigned long long*)(w + bU + 2 * bR + bS + bC);
+    return 0;
+}
+
+static unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace rd
+
+using namespace rd;
+
+extern "C" {
+
+int64_t rd_mra_leaves(const double* fine, int32_t m, const rd_mra_params* p, uint64_t* keys,
+                      double* values, int64_t capacity, int64_t* level_counts, void* hip_stream) {
+    if (!mra_params_valid(p, m) || !fine || capacity < 0) {
+        set_error("invalid MRA arguments");
+        return RD_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    Pyr P{};
+    double* sc = nullptr;
+    unsigned* bcount = nullptr;
+    unsigned long long* boff = nullptr;
+    int64_t nb = 0;
+    if (int r = setup_pyr(p, m, s, P, &sc, &bcount, &boff, &nb)) return r;
+    std::vector<double> hs(m, 1.0);
+    if (p->scale) hs.assign(p->scale, p->scale + m);
+    const int d = P.d, J = P.J;
+    const int64_t nfine = (int64_t)1 << (d * J);
+#define MRA_TRY(e)                                                                              \
+    do {                                                                                        \
+        hipError_t e_ = (e);                                                                    \
+        if (e_ != hipSuccess) { set_error("%s: %s", #e, hipGetErrorString(e_)); return RD_EDEVICE; } \
+    } while (0)
+    MRA_TRY(hipMemcpyAsync(sc, hs.data(), sizeof(double) * m, hipMemcpyHostToDevice, s));
+    MRA_TRY(hipMemsetAsync(P.R, 0, (size_t)P.total, s));
+    const int B = 256;
+    if (d == 2) hipLaunchKernelGGL(k_to_morton<2>, dim3(blocks_for(nfine, B)), dim3(B), 0, s, fine, P);
+    else hipLaunchKernelGGL(k_to_morton<3>, dim3(blocks_for(nfine, B)), dim3(B), 0, s, fine, P);
+    for (int j = J; j >= 1; --j) {
+        const int64_t np = (int64_t)1 << (d * (j - 1));
+        if (d == 2) hipLaunchKernelGGL(k_project<2>, dim3(blocks_for(np, B)), dim3(B), 0, s, P, j);
+        else hipLaunchKernelGGL(k_project<3>, dim3(blocks_for(np, B)), dim3(B), 0, s, P, j);
+    }
+    for (int j = 1; j <= J; ++j) {
+        const int64_t np = (int64_t)1 << (d * (j - 1));
+        const double e2 = (p->eps * p->eps) * std::ldexp(1.0, d * (j - J));
+        if (d == 2) hipLaunchKernelGGL(k_detail_flags<2>, dim3(blocks_for(np, B)), dim3(B), 0, s, P, j, e2, (const double*)sc);
+        else hipLaunchKernelGGL(k_detail_flags<3>, dim3(blocks_for(np, B)), dim3(B), 0, s, P, j, e2, (const double*)sc);
+    }
+    for (int j = J - 1; j >= 1; --j) {
+        const int64_t nj = (int64_t)1 << (d * j);
+        if (d == 2) hipLaunchKernelGGL(k_grade<2>, dim3(blocks_for(nj, B)), dim3(B), 0, s, P, j);
+        else hipLaunchKernelGGL(k_grade<3>, dim3(blocks_for(nj, B)), dim3(B), 0, s, P, j);
+    }
+    hipLaunchKernelGGL(k_leaf_count, dim3((unsigned)nb), dim3(kLeafBlock), 0, s, P, d, bcount);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, (const unsigned*)bcount, boff, nb);
+    MRA_TRY(hipGetLastError());
+    unsigned long long total = 0;
+    MRA_TRY(hipMemcpyAsync(&total, boff + nb, sizeof(total), hipMemcpyDeviceToHost, s));
+    MRA_TRY(hipStreamSynchronize(s));
+    const int64_t nl = (int64_t)total;
+    if (nl <= capacity && nl > 0) {
+        if (!keys || !values) { set_error("keys / values are null"); return RD_EINVAL; }
+        hipLaunchKernelGGL(k_leaf_write, dim3((unsigned)nb), dim3(kLeafBlock), 0, s, P, d,
+                           (const unsigned long long*)boff, keys, values, nl);
+        MRA_TRY(hipGetLastError());
+        if (level_counts) {
+            std::vector<uint64_t> hk((size_t)nl);
+            MRA_TRY(hipMemcpyAsync(hk.data(), keys, sizeof(uint64_t) * nl, hipMemcpyDeviceToHost, s));
+            MRA_TRY(hipStreamSynchronize(s));
+            for (int j = 0; j <= J; ++j) level_counts[j] = 0;
+            for (uint64_t k : hk) level_counts[(k >> 12) & 15u]++;
+        }
+        MRA_TRY(hipStreamSynchronize(s));
+    }
+    return nl;
+}
+
+int64_t rd_mra_reconstruct(const uint64_t* keys, const double* values, int64_t n_leaves,
+                           int32_t m, const rd_mra_params* p, double* fine, void* hip_stream) {
+    if (!mra_params_valid(p, m) || !fine || n_leaves < 1 || !keys || !values) {
+        set_error("invalid MRA arguments");
+        return RD_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    Pyr P{};
+    double* sc = nullptr;
+    unsigned* bcount = nullptr;
+    unsigned long long* boff = nullptr;
+    int64_t nb = 0;
+    if (int r = setup_pyr(p, m, s, P, &sc, &bcount, &boff, &nb)) return r;
+    const int d = P.d, J = P.J;
+    const int64_t nfine = (int64_t)1 << (d * J);
+    const int B = 256;
+    MRA_TRY(hipMemsetAsync(P.T, 0, (size_t)P.total, s));
+    hipLaunchKernelGGL(k_scatter_leaves, dim3(blocks_for(n_leaves, B)), dim3(B), 0, s, P, d, keys,
+                       values, n_leaves);
+    for (int j = J; j >= 1; --j) {
+        const int64_t np = (int64_t)1 << (d * (j - 1));
+        if (d == 2) hipLaunchKernelGGL(k_tree_up<2>, dim3(blocks_for(np, B)), dim3(B), 0, s, P, j);
+        else hipLaunchKernelGGL(k_tree_up<3>, dim3(blocks_for(np, B)), dim3(B), 0, s, P, j);
+    }
+    for (int j = 1; j <= J; ++j) {
+        const int64_t nj = (int64_t)1 << (d * j);
+        if (d == 2) hipLaunchKernelGGL(k_fill_down<2>, dim3(blocks_for(nj, B)), dim3(B), 0, s, P, j);
+        else hipLaunchKernelGGL(k_fill_down<3>, dim3(blocks_for(nj, B)), dim3(B), 0, s, P, j);
+    }
+    if (d == 2) hipLaunchKernelGGL(k_from_morton<2>, dim3(blocks_for(nfine, B)), dim3(B), 0, s, fine, P);
+    else hipLaunchKernelGGL(k_from_morton<3>, dim3(blocks_for(nfine, B)), dim3(B), 0, s, fine, P);
+    MRA_TRY(hipGetLastError());
+    MRA_TRY(hipStreamSynchronize(s));
+    return 0;
+}
+
+}  // extern "C"
