@@ -42,7 +42,7 @@ hipError_t launch_reset(unsigned long long* p, int n, hipStream_t s) {
     RD_PERS(KIND, MODEL, M, PREC, LT, false, 6, 128, 1, 56, TAG ".persistent.b128.fs56"),     \
     RD_PERS(KIND, MODEL, M, PREC, LT, false, 7, 256, 1, 40, TAG ".persistent.b256.fs40"),     \
     RD_PERS(KIND, MODEL, M, PREC, LT, false, 8, 64, 1, 40, TAG ".persistent.b64.fs40"),       \
-    RD_PERS(KIND, MODEL, M, PREC, LT, false, 9, 128, 3, 40, TAG ".persistent.b128.w3.fs40"),  \
+    RD_PERS(KIND, MODEL, M, PREC, LT, false, 9, 128, 1, 40, TAG ".persistent.b128.fs40"),     \
     RD_PERS_K(KIND, MODEL, M, PREC, LT, 10, 128, 1, 40, TAG ".persistent.b128.fs40.kp"),      \
     RD_PERS_K(KIND, MODEL, M, PREC, LT, 11, 64, 1, 40, TAG ".persistent.b64.fs40.kp"),        \
     RD_PERS_K(KIND, MODEL, M, PREC, LT, 12, 256, 1, 48, TAG ".persistent.b256.fs48.kp"),      \
@@ -63,12 +63,12 @@ static const KernelEntry g_small_table[] = {
     RD_MODEL_SET(K_NAG, Nagumo, 1, "nagumo"),
     RD_MODEL_SET(K_LIN, Linear<1>, 1, "linear1"),
     RD_MODEL_SET(K_LIN, Linear<2>, 2, "linear2"),
-    RD_MODEL_SET(K_LIN, Linear<3>, 3, "linear3"),
-    RD_MODEL_SET(K_LIN, Linear<4>, 4, "linear4"),
+    RD_MODEL_SET_W(K_LIN, Linear<3>, 3, "linear3", 1),
+    RD_MODEL_SET_W(K_LIN, Linear<4>, 4, "linear4", 1),
     RD_MODEL_SET(K_KIN, Kinetics<1>, 1, "kinetics1"),
     RD_MODEL_SET(K_KIN, Kinetics<2>, 2, "kinetics2"),
-    RD_MODEL_SET(K_KIN, Kinetics<3>, 3, "kinetics3"),
-    RD_MODEL_SET(K_KIN, Kinetics<4>, 4, "kinetics4"),
+    RD_MODEL_SET_W(K_KIN, Kinetics<3>, 3, "kinetics3", 1),
+    RD_MODEL_SET_W(K_KIN, Kinetics<4>, 4, "kinetics4", 1),
 };
 
 const KernelEntry* small_kernel_table(int* count) {

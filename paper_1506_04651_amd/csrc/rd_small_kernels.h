@@ -162,12 +162,19 @@ hipError_t launch_pers(const LaunchArgs& a, int grid, hipStream_t s) {
 /* model kinds (same numbering as the public header) */
 enum { K_OREG = 1, K_KIN = 2, K_NAG = 3, K_LIN = 4, K_ROB = 5, K_BC = 6 };
 
-#define RD_MODEL_SET(KIND, MODEL, M, TAG)                                                     \
-    RD_ONE(KIND, MODEL, M, 0, double, false, 1, 256, 1, 32, TAG ".fp64.onelaunch.b256.fs32"), \
-    RD_ONE(KIND, MODEL, M, 1, float, false, 1, 256, 1, 32, TAG ".mixed.onelaunch.b256.fs32"), \
-    RD_PERS(KIND, MODEL, M, 0, double, false, 1, 128, 1, 40, TAG ".fp64.persistent.b128.fs40"), \
-    RD_PERS(KIND, MODEL, M, 1, float, false, 1, 128, 1, 40, TAG ".mixed.persistent.b128.fs40"), \
-    RD_ONE(KIND, MODEL, M, 0, double, true, 1, 256, 1, 1, TAG ".fp64.onelaunch.fixed"),       \
+#define RD_STR_(X) #X
+#define RD_STR(X) RD_STR_(X)
+/* the base kernels of a model; WPE: waves-per-SIMD target of the persistent
+ * kernels (3 where the engine fits 168 registers with few spills, else 1) */
+#define RD_MODEL_SET_W(KIND, MODEL, M, TAG, WPE)                                                      \
+    RD_ONE(KIND, MODEL, M, 0, double, false, 1, 256, 1, 32, TAG ".fp64.onelaunch.b256.fs32"),        \
+    RD_ONE(KIND, MODEL, M, 1, float, false, 1, 256, 1, 32, TAG ".mixed.onelaunch.b256.fs32"),         \
+    RD_PERS(KIND, MODEL, M, 0, double, false, 1, 128, WPE, 40,                                      \
+            TAG ".fp64.persistent.b128.w" RD_STR(WPE) ".fs40"),                                     \
+    RD_PERS(KIND, MODEL, M, 1, float, false, 1, 128, WPE, 40,                                       \
+            TAG ".mixed.persistent.b128.w" RD_STR(WPE) ".fs40"),                                    \
+    RD_ONE(KIND, MODEL, M, 0, double, true, 1, 256, 1, 1, TAG ".fp64.onelaunch.fixed"),             \
     RD_PERS(KIND, MODEL, M, 0, double, true, 1, 256, 1, 1, TAG ".fp64.persistent.fixed")
+#define RD_MODEL_SET(KIND, MODEL, M, TAG) RD_MODEL_SET_W(KIND, MODEL, M, TAG, 3)
 
 }  // namespace rd
