@@ -159,8 +159,10 @@ void* stream_workspace(DevCtx& c, hipStream_t s, size_t bytes, int* err) {
  * more than the tail it removes). */
 constexpr int64_t kOrderMinCells = 8192;
 
-int enqueue_order(DevCtx& c, Prepared& pr, hipStream_t s) {
+int enqueue_order(DevCtx& c, Prepared& pr, hipStream_t s, unsigned long long* counters,
+                  bool* cleared) {
     pr.args.order = nullptr;
+    if (cleared) *cleared = false;
     if (pr.entry->schedule != RD_PERSISTENT || !pr.order || pr.args.n < kOrderMinCells ||
         pr.args.n > INT32_MAX)
         return 0;
@@ -172,8 +174,9 @@ int enqueue_order(DevCtx& c, Prepared& pr, hipStream_t s) {
     char* ws = (char*)stream_workspace(c, s, ordb + wsb, &err);
     if (!ws) return err ? err : RD_ENOMEM;
     int32_t* order = (int32_t*)ws;
-    HIP_TRY(fn(pr.args, ws + ordb, order, s));
+    HIP_TRY(fn(pr.args, ws + ordb, order, counters, s));
     pr.args.order = order;
+    if (cleared) *cleared = counters != nullptr;
     return 0;
 }
 
@@ -471,14 +474,15 @@ static int launch_prepared(Prepared& pr, hipStream_t s, bool use_graph, unsigned
                 if (!stream_workspace(*c, s, need, &err)) return err;
             }
             HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            if (int r = enqueue_order(*c, pr, s)) {
+            bool cleared = false;
+            if (int r = enqueue_order(*c, pr, s, v.counters, &cleared)) {
                 hipGraph_t dummy = nullptr;
                 hipStreamEndCapture(s, &dummy);
                 if (dummy) hipGraphDestroy(dummy);
                 return r;
             }
             a.order = pr.args.order;
-            hipError_t e1 = launch_reset(v.counters, 2, s);
+            hipError_t e1 = cleared ? hipSuccess : launch_reset(v.counters, 2, s);
             hipError_t e2 = pr.entry->launch(a, pr.grid, s);
             hipError_t e3 = hipStreamEndCapture(s, &g);
             if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
@@ -501,8 +505,9 @@ static int launch_prepared(Prepared& pr, hipStream_t s, bool use_graph, unsigned
     unsigned long long* cnt = c->slots + 2 * slot;
     pr.args.counter = cnt;
     pr.args.nfail = cnt + 1;
-    if (int r = enqueue_order(*c, pr, s)) return r;
-    HIP_TRY(launch_reset(cnt, 2, s));
+    bool cleared = false;
+    if (int r = enqueue_order(*c, pr, s, cnt, &cleared)) return r;
+    if (!cleared) HIP_TRY(launch_reset(cnt, 2, s));
     HIP_TRY(hipEventRecord(g_tt.a, s));
     HIP_TRY(pr.entry->launch(pr.args, pr.grid, s));
     HIP_TRY(hipEventRecord(g_tt.b, s));

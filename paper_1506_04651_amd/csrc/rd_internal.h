@@ -55,8 +55,11 @@ int prepare(double* states, int64_t n, int32_t m, double dt, double rtol, double
 void* stream_workspace(DevCtx& c, hipStream_t s, size_t bytes, int* err);
 
 /* Enqueue the claim-order kernels for a prepared persistent launch (when the
- * options ask for it and an order kernel exists); sets pr.args.order. */
-int enqueue_order(DevCtx& c, Prepared& pr, hipStream_t s);
+ * options ask for it and an order kernel exists); sets pr.args.order.  The
+ * order kernels then also clear `counters` (two entries, nullable) and
+ * *cleared is set; otherwise the caller clears them. */
+int enqueue_order(DevCtx& c, Prepared& pr, hipStream_t s, unsigned long long* counters,
+                  bool* cleared);
 
 /* Grid for a persistent kernel: resident workgroups on the device, capped by
  * the number of workgroups the cells would fill. */

@@ -59,10 +59,13 @@ struct KernelEntry {
     const void* func;   /* for occupancy queries                        */
 };
 
-/* Longest-first claim order: launches the cost-bucket, scan and scatter
- * kernels that write order[n] (cell indices, most expensive estimate first).
- * ws must hold order_workspace_bytes(n) bytes. */
-typedef hipError_t (*order_fn)(const LaunchArgs&, void* ws, int32_t* order, hipStream_t);
+/* Longest-first claim order: launches the kernels that write order[n] (cell
+ * indices, most expensive estimate first).  ws must hold
+ * order_workspace_bytes(n) bytes.  counters (nullable): two 64-bit counters
+ * the first of these kernels also clears (the persistent kernel's claim
+ * counter and failure count). */
+typedef hipError_t (*order_fn)(const LaunchArgs&, void* ws, int32_t* order,
+                               unsigned long long* counters, hipStream_t);
 size_t order_workspace_bytes(int64_t n);
 order_fn find_order_fn(int kind, int m);
 

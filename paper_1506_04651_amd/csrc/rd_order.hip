@@ -23,7 +23,7 @@ namespace rd {
 
 constexpr int kBuckets = 64;
 constexpr int kLog2Min = -24; /* bucket 0 holds key < 2^-24 (and non-finite keys) */
-constexpr int kOrderBlock = 256;
+constexpr int kOrderBlock = 1024;
 
 static size_t align_up(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -31,8 +31,35 @@ size_t order_workspace_bytes(int64_t n) {
     return align_up((size_t)n) + 2 * kBuckets * sizeof(unsigned);
 }
 
-__global__ void k_order_zero(unsigned* hist) {
+/* hist[0, kBuckets): cell counts per bucket; hist[kBuckets, 2 kBuckets):
+ * cursors of the scatter; counters: the persistent kernel's claim counter
+ * and failure count, cleared in the same launch. */
+__global__ void k_order_init(unsigned* hist, unsigned long long* counters) {
     if (threadIdx.x < 2 * kBuckets) hist[threadIdx.x] = 0u;
+    if (counters && threadIdx.x < 2) counters[threadIdx.x] = 0ull;
+}
+
+/* Adds one to lh[b] for every active lane of the wave with one LDS atomic
+ * per distinct bucket, and returns the lane's slot in its bucket (the count
+ * before the add plus the lane's rank among the active lanes of that bucket).
+ * Called by every lane of the wave. */
+__device__ __forceinline__ unsigned wave_bucket_add(unsigned* lh, int b, bool active) {
+    const unsigned lane = __lane_id();
+    const unsigned long long below = (1ull << lane) - 1ull;
+    unsigned long long rest = __ballot(active);
+    unsigned slot = 0u;
+    while (rest) {
+        const int leader = __ffsll((long long)rest) - 1;
+        const int lb = __shfl(b, leader);
+        const bool mine = active && b == lb;
+        const unsigned long long same = __ballot(mine);
+        unsigned base = 0u;
+        if ((int)lane == leader) base = atomicAdd(&lh[lb], (unsigned)__popcll(same));
+        base = __shfl(base, leader);
+        if (mine) slot = base + (unsigned)__popcll(same & below);
+        rest &= ~same;
+    }
+    return slot;
 }
 
 template <class Model>
@@ -43,7 +70,9 @@ __global__ void __launch_bounds__(kOrderBlock) k_order_cost(LaunchArgs a, unsign
     if (threadIdx.x < kBuckets) lh[threadIdx.x] = 0u;
     __syncthreads();
     const int64_t c = (int64_t)blockIdx.x * kOrderBlock + threadIdx.x;
-    if (c < a.n) {
+    const bool act = c < a.n;
+    int b = 0;
+    if (act) {
         const Model md(a.params);
         double y[M], f[M];
 #pragma unroll
@@ -53,7 +82,6 @@ __global__ void __launch_bounds__(kOrderBlock) k_order_cost(LaunchArgs a, unsign
 #pragma unroll
         for (int r = 0; r < M; ++r)
             key = fmax(key, __builtin_fabs(f[r]) * a.P.dt / (a.P.atol + a.P.rtol * __builtin_fabs(y[r])));
-        int b = 0;
         if (key > 0.0 && __builtin_isfinite(key)) {
             /* floor(log2(key)) from the exponent field (subnormals clamp low) */
             const int e = (int)((__double_as_longlong(key) >> 52) & 0x7ff) - 1023;
@@ -61,52 +89,53 @@ __global__ void __launch_bounds__(kOrderBlock) k_order_cost(LaunchArgs a, unsign
             b = b < 0 ? 0 : (b >= kBuckets ? kBuckets - 1 : b);
         }
         bucket[c] = (unsigned char)b;
-        atomicAdd(&lh[b], 1u);
     }
+    wave_bucket_add(lh, b, act);
     __syncthreads();
     if (threadIdx.x < kBuckets && lh[threadIdx.x]) atomicAdd(&hist[threadIdx.x], lh[threadIdx.x]);
 }
 
-/* cursor[b] = number of cells in buckets above b (descending order) */
-__global__ void k_order_scan(unsigned* hist) {
-    if (threadIdx.x == 0) {
-        unsigned acc = 0;
-        for (int b = kBuckets - 1; b >= 0; --b) {
-            const unsigned h = hist[b];
-            hist[kBuckets + b] = acc;
-            acc += h;
-        }
-    }
-}
-
+/* Each block finds where the buckets start (most expensive bucket first:
+ * start[b] = number of cells in buckets above b) from the global counts,
+ * ranks its cells inside their buckets, reserves one range per bucket from
+ * the bucket's cursor and writes the cell indices there. */
 __global__ void __launch_bounds__(kOrderBlock) k_order_scatter(const unsigned char* bucket,
                                                                unsigned* hist, int32_t* order,
                                                                int64_t n) {
+    static_assert(kBuckets == 64, "the bucket scan runs on one wave of 64 lanes");
     __shared__ unsigned lcount[kBuckets], lbase[kBuckets];
-    if (threadIdx.x < kBuckets) lcount[threadIdx.x] = 0u;
-    __syncthreads();
-    const int64_t c = (int64_t)blockIdx.x * kOrderBlock + threadIdx.x;
-    int b = 0;
-    unsigned local = 0;
-    if (c < n) {
-        b = bucket[c];
-        local = atomicAdd(&lcount[b], 1u);
+    if (threadIdx.x < kBuckets) {
+        /* suffix sum over the 64 bucket counts, one bucket per lane */
+        const unsigned h = hist[threadIdx.x];
+        unsigned s = h;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const unsigned t = __shfl_down(s, off);
+            if (threadIdx.x + off < 64) s += t;
+        }
+        lbase[threadIdx.x] = s - h;
+        lcount[threadIdx.x] = 0u;
     }
     __syncthreads();
-    if (threadIdx.x < kBuckets && lcount[threadIdx.x])
-        lbase[threadIdx.x] = atomicAdd(&hist[kBuckets + threadIdx.x], lcount[threadIdx.x]);
+    const int64_t c = (int64_t)blockIdx.x * kOrderBlock + threadIdx.x;
+    const bool act = c < n;
+    const int b = act ? (int)bucket[c] : 0;
+    const unsigned local = wave_bucket_add(lcount, b, act);
     __syncthreads();
-    if (c < n) order[lbase[b] + local] = (int32_t)c;
+    if (threadIdx.x < kBuckets && lcount[threadIdx.x])
+        lbase[threadIdx.x] += atomicAdd(&hist[kBuckets + threadIdx.x], lcount[threadIdx.x]);
+    __syncthreads();
+    if (act) order[lbase[b] + local] = (int32_t)c;
 }
 
 template <class Model>
-hipError_t launch_order(const LaunchArgs& a, void* ws, int32_t* order, hipStream_t s) {
+hipError_t launch_order(const LaunchArgs& a, void* ws, int32_t* order,
+                        unsigned long long* counters, hipStream_t s) {
     unsigned char* bucket = (unsigned char*)ws;
     unsigned* hist = (unsigned*)((char*)ws + align_up((size_t)a.n));
     const int grid = (int)((a.n + kOrderBlock - 1) / kOrderBlock);
-    hipLaunchKernelGGL(k_order_zero, dim3(1), dim3(2 * kBuckets), 0, s, hist);
+    hipLaunchKernelGGL(k_order_init, dim3(1), dim3(2 * kBuckets), 0, s, hist, counters);
     hipLaunchKernelGGL(k_order_cost<Model>, dim3(grid), dim3(kOrderBlock), 0, s, a, bucket, hist);
-    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, s, hist);
     hipLaunchKernelGGL(k_order_scatter, dim3(grid), dim3(kOrderBlock), 0, s,
                        (const unsigned char*)bucket, hist, order, a.n);
     return hipGetLastError();

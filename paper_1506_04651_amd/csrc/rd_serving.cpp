@@ -139,9 +139,10 @@ static bool launch_request(rd_session* s, Request* r) {
     pr.args.nfail = pr.args.counter + 1;
     if (hipMemcpyAsync(a_states, r->user_states, sbytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return false;
     DevCtx* ctx = current_ctx();
-    if (!ctx || enqueue_order(*ctx, pr, st) != 0) return false;
+    bool cleared = false;
+    if (!ctx || enqueue_order(*ctx, pr, st, pr.args.counter, &cleared) != 0) return false;
     const LaunchArgs& a = pr.args;
-    if (launch_reset(a.counter, 2, st) != hipSuccess) return false;
+    if (!cleared && launch_reset(a.counter, 2, st) != hipSuccess) return false;
     if (pr.entry->launch(a, pr.grid, st) != hipSuccess) return false;
     if (hipMemcpyAsync(r->user_states, a_states, sbytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return false;
     if (a_stats &&
