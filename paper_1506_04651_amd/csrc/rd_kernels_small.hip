@@ -52,6 +52,15 @@ hipError_t launch_reset(unsigned long long* p, int n, hipStream_t s) {
     RD_PERS(KIND, MODEL, M, PREC, LT, false, 16, 192, 3, 40, TAG ".persistent.b192.w3.fs40"),  \
     RD_PERS(KIND, MODEL, M, PREC, LT, false, 17, 128, 4, 40, TAG ".persistent.b128.w4.fs40"),  \
     RD_PERS_K(KIND, MODEL, M, PREC, LT, 18, 128, 3, 40, TAG ".persistent.b128.w3.fs40.kp"),   \
+    RD_PERS_P(KIND, MODEL, M, PREC, LT, 19, 128, 3, 40, 3, TAG ".persistent.b128.w3.fs40.p3"), \
+    RD_PERS_P(KIND, MODEL, M, PREC, LT, 20, 128, 3, 40, 6, TAG ".persistent.b128.w3.fs40.p6"), \
+    RD_PERS_P(KIND, MODEL, M, PREC, LT, 21, 128, 3, 40, 12, TAG ".persistent.b128.w3.fs40.p12"), \
+    RD_PERS_P(KIND, MODEL, M, PREC, LT, 22, 128, 3, 24, 6, TAG ".persistent.b128.w3.fs24.p6"), \
+    RD_PERS_P(KIND, MODEL, M, PREC, LT, 23, 128, 3, 32, 3, TAG ".persistent.b128.w3.fs32.p3"), \
+    RD_PERS_P(KIND, MODEL, M, PREC, LT, 24, 128, 3, 32, 2, TAG ".persistent.b128.w3.fs32.p2"), \
+    RD_PERS_P(KIND, MODEL, M, PREC, LT, 25, 128, 3, 32, 4, TAG ".persistent.b128.w3.fs32.p4"), \
+    RD_PERS_P(KIND, MODEL, M, PREC, LT, 26, 128, 3, 28, 3, TAG ".persistent.b128.w3.fs28.p3"), \
+    RD_PERS(KIND, MODEL, M, PREC, LT, false, 27, 128, 3, 40, TAG ".persistent.b128.w3.fs40"),  \
     RD_ONE(KIND, MODEL, M, PREC, LT, false, 2, 256, 1, 16, TAG ".onelaunch.b256.fs16"),       \
     RD_ONE(KIND, MODEL, M, PREC, LT, false, 3, 256, 1, 1, TAG ".onelaunch.b256.fs1")
 

@@ -10,9 +10,12 @@
  * cells for the end.  The cost estimate is the scaled initial rate
  *   key = max_i |f_i(u0)| dt / (atol' + rtol' |u0_i|),
  * i.e. how many tolerance units the state would move over the substep at its
- * initial speed; cells are bucketed by floor(log2(key)) and listed bucket by
- * bucket, most expensive first (a counting sort; order inside a bucket is
- * arbitrary and does not affect any cell's result).
+ * initial speed; cells are bucketed by log2(key) in quarter octaves (the
+ * exponent and the two leading mantissa bits) and listed bucket by bucket,
+ * most expensive first (a counting sort; order inside a bucket is arbitrary
+ * and does not affect any cell's result).  On the BZ fields the most
+ * expensive octave spans nearly a factor of two in cost, so whole octaves
+ * would scatter the costliest cells over many more waves.
  */
 #include <hip/hip_runtime.h>
 
@@ -21,8 +24,9 @@
 
 namespace rd {
 
-constexpr int kBuckets = 64;
-constexpr int kLog2Min = -24; /* bucket 0 holds key < 2^-24 (and non-finite keys) */
+constexpr int kSub = 4;                 /* buckets per octave */
+constexpr int kBuckets = 64 * kSub;     /* 64 octaves */
+constexpr int kLog2Min = -24;           /* bucket 0 holds key < 2^-24 (and non-finite keys) */
 constexpr int kOrderBlock = 1024;
 
 static size_t align_up(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -83,9 +87,12 @@ __global__ void __launch_bounds__(kOrderBlock) k_order_cost(LaunchArgs a, unsign
         for (int r = 0; r < M; ++r)
             key = fmax(key, __builtin_fabs(f[r]) * a.P.dt / (a.P.atol + a.P.rtol * __builtin_fabs(y[r])));
         if (key > 0.0 && __builtin_isfinite(key)) {
-            /* floor(log2(key)) from the exponent field (subnormals clamp low) */
-            const int e = (int)((__double_as_longlong(key) >> 52) & 0x7ff) - 1023;
-            b = e - kLog2Min;
+            /* floor(kSub log2(key)), approximately: the exponent field and
+             * the leading mantissa bits (subnormals clamp low) */
+            const long long bits = __double_as_longlong(key);
+            const int e = (int)((bits >> 52) & 0x7ff) - 1023;
+            const int q = (int)((bits >> 50) & (kSub - 1));
+            b = (e - kLog2Min) * kSub + q;
             b = b < 0 ? 0 : (b >= kBuckets ? kBuckets - 1 : b);
         }
         bucket[c] = (unsigned char)b;
@@ -102,19 +109,30 @@ __global__ void __launch_bounds__(kOrderBlock) k_order_cost(LaunchArgs a, unsign
 __global__ void __launch_bounds__(kOrderBlock) k_order_scatter(const unsigned char* bucket,
                                                                unsigned* hist, int32_t* order,
                                                                int64_t n) {
-    static_assert(kBuckets == 64, "the bucket scan runs on one wave of 64 lanes");
+    static_assert(kBuckets == 64 * kSub, "the bucket scan runs on one wave, kSub buckets per lane");
     __shared__ unsigned lcount[kBuckets], lbase[kBuckets];
-    if (threadIdx.x < kBuckets) {
-        /* suffix sum over the 64 bucket counts, one bucket per lane */
-        const unsigned h = hist[threadIdx.x];
-        unsigned s = h;
+    if (threadIdx.x < 64) {
+        /* lane l holds buckets kSub l .. kSub l + kSub - 1: suffix sums of
+         * the lane totals across the wave, then inside the lane downwards */
+        unsigned h[kSub], tot = 0u;
+#pragma unroll
+        for (int k = 0; k < kSub; ++k) {
+            h[k] = hist[kSub * threadIdx.x + k];
+            tot += h[k];
+        }
+        unsigned s = tot;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
             const unsigned t = __shfl_down(s, off);
             if (threadIdx.x + off < 64) s += t;
         }
-        lbase[threadIdx.x] = s - h;
-        lcount[threadIdx.x] = 0u;
+        unsigned above = s - tot; /* cells in the buckets of higher lanes */
+#pragma unroll
+        for (int k = kSub - 1; k >= 0; --k) {
+            lbase[kSub * threadIdx.x + k] = above;
+            lcount[kSub * threadIdx.x + k] = 0u;
+            above += h[k];
+        }
     }
     __syncthreads();
     const int64_t c = (int64_t)blockIdx.x * kOrderBlock + threadIdx.x;

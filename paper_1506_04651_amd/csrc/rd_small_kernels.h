@@ -68,10 +68,29 @@ k_onelaunch(LaunchArgs a) {
  * chunk (at least kClaimChunk positions) with a single atomic. */
 constexpr unsigned kClaimChunk = 16;
 
+/* Issue priority of a wave from the claim positions of the cells it holds.
+ * Under the longest-first order a small position means an expensive cell,
+ * and the launch cannot end before its most expensive cells do; waves holding
+ * such cells get the SIMD first, and the waves with cheap cells fill the
+ * cycles in which the former stall.  span = lanes of the grid / PDIV:
+ * priority 3 for a wave holding a position below span, 2 below 2 span, 1
+ * below 3 span, else 0.  Priorities only arbitrate instruction issue between
+ * ready waves; they change no result. */
+template <int PDIV>
+__device__ __forceinline__ void claim_priority(unsigned long long held, unsigned long long lanes) {
+    const unsigned long long span = (lanes + PDIV - 1) / PDIV;
+    if (__ballot(held < span)) __builtin_amdgcn_s_setprio(3);
+    else if (__ballot(held < 2 * span)) __builtin_amdgcn_s_setprio(2);
+    else if (__ballot(held < 3 * span)) __builtin_amdgcn_s_setprio(1);
+    else __builtin_amdgcn_s_setprio(0);
+}
+
 /* PLDS: the step parameters are staged in LDS and re-read each pass (true),
  * or read from the kernel arguments, where the compiler keeps them in scalar
- * registers across the loop (false).  Same arithmetic either way. */
-template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool PLDS = true>
+ * registers across the loop (false).  Same arithmetic either way.  PDIV > 0:
+ * wave issue priorities from claim positions (claim_priority). */
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool PLDS = true,
+          int PDIV = 0>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_persistent(LaunchArgs a) {
     using L = SmallLds<Model::M>;
@@ -89,12 +108,14 @@ k_persistent(LaunchArgs a) {
     const unsigned lane = __lane_id();
     const unsigned long long below = (1ull << lane) - 1ull;
     unsigned long long qnext = 0, qend = 0; /* wave-uniform */
+    unsigned long long held = ~0ull;         /* claim position of the cell held */
     for (;;) {
         const bool need = alive && cell.phase == PH_IDLE;
         if (need && c >= 0) {
             cell.store(a.states, a.stats, a.n, c, a.hcell);
             if (cell.status != ST_OK) atomicAdd(a.nfail, 1ull);
             c = -1;
+            held = ~0ull;
         }
         const unsigned long long mask = __ballot(need);
         if (mask) {
@@ -119,11 +140,13 @@ k_persistent(LaunchArgs a) {
             if (need) {
                 if (pos < (unsigned long long)a.n) {
                     c = a.order ? (int64_t)a.order[pos] : (int64_t)pos;
+                    held = pos;
                     cell.load(md, sP, a.states, a.n, c, a.hcell);
                 } else {
                     alive = false;
                 }
             }
+            if (PDIV > 0) claim_priority<PDIV>(held, (unsigned long long)gridDim.x * BLOCK);
         }
         if (__ballot(alive) == 0ull) break;
         if (PLDS) __asm__ volatile("" ::: "memory"); /* re-read sP from LDS each pass */
@@ -139,9 +162,10 @@ hipError_t launch_one(const LaunchArgs& a, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool PLDS = true>
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool PLDS = true,
+          int PDIV = 0>
 hipError_t launch_pers(const LaunchArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_persistent<Model, LT, FIXED, BLOCK, WPE, FSMIN, PLDS>), dim3(grid),
+    hipLaunchKernelGGL((k_persistent<Model, LT, FIXED, BLOCK, WPE, FSMIN, PLDS, PDIV>), dim3(grid),
                        dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
@@ -154,6 +178,10 @@ hipError_t launch_pers(const LaunchArgs& a, int grid, hipStream_t s) {
     {KIND, fd_jac_of<MODEL>::value ? 1 : 0, M, PREC, 0, false, VAR, BLOCK, BLOCK, NAME,           \
      &launch_pers<MODEL, LT, false, BLOCK, WPE, FS, false>,                                     \
      (const void*)&k_persistent<MODEL, LT, false, BLOCK, WPE, FS, false>}
+#define RD_PERS_P(KIND, MODEL, M, PREC, LT, VAR, BLOCK, WPE, FS, PDIV, NAME)                     \
+    {KIND, fd_jac_of<MODEL>::value ? 1 : 0, M, PREC, 0, false, VAR, BLOCK, BLOCK, NAME,           \
+     &launch_pers<MODEL, LT, false, BLOCK, WPE, FS, true, PDIV>,                                \
+     (const void*)&k_persistent<MODEL, LT, false, BLOCK, WPE, FS, true, PDIV>}
 #define RD_PERS(KIND, MODEL, M, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, NAME)                      \
     {KIND, fd_jac_of<MODEL>::value ? 1 : 0, M, PREC, 0, FIXED, VAR, BLOCK, BLOCK, NAME,                                          \
      &launch_pers<MODEL, LT, FIXED, BLOCK, WPE, FS>,                                            \
@@ -165,14 +193,17 @@ enum { K_OREG = 1, K_KIN = 2, K_NAG = 3, K_LIN = 4, K_ROB = 5, K_BC = 6 };
 #define RD_STR_(X) #X
 #define RD_STR(X) RD_STR_(X)
 /* the base kernels of a model; WPE: waves-per-SIMD target of the persistent
- * kernels (3 where the engine fits 168 registers with few spills, else 1) */
+ * kernels (3 where the engine fits 168 registers with few spills, else 1);
+ * the persistent kernels give waves that hold early claim positions (the
+ * costliest cells under the longest-first order) a higher issue priority
+ * (claim_priority with PDIV = 2) */
 #define RD_MODEL_SET_W(KIND, MODEL, M, TAG, WPE)                                                      \
     RD_ONE(KIND, MODEL, M, 0, double, false, 1, 256, 1, 32, TAG ".fp64.onelaunch.b256.fs32"),        \
     RD_ONE(KIND, MODEL, M, 1, float, false, 1, 256, 1, 32, TAG ".mixed.onelaunch.b256.fs32"),         \
-    RD_PERS(KIND, MODEL, M, 0, double, false, 1, 128, WPE, 40,                                      \
-            TAG ".fp64.persistent.b128.w" RD_STR(WPE) ".fs40"),                                     \
-    RD_PERS(KIND, MODEL, M, 1, float, false, 1, 128, WPE, 40,                                       \
-            TAG ".mixed.persistent.b128.w" RD_STR(WPE) ".fs40"),                                    \
+    RD_PERS_P(KIND, MODEL, M, 0, double, 1, 128, WPE, 40, 2,                                        \
+              TAG ".fp64.persistent.b128.w" RD_STR(WPE) ".fs40.p2"),                                \
+    RD_PERS_P(KIND, MODEL, M, 1, float, 1, 128, WPE, 40, 2,                                         \
+              TAG ".mixed.persistent.b128.w" RD_STR(WPE) ".fs40.p2"),                               \
     RD_ONE(KIND, MODEL, M, 0, double, true, 1, 256, 1, 1, TAG ".fp64.onelaunch.fixed"),             \
     RD_PERS(KIND, MODEL, M, 0, double, true, 1, 256, 1, 1, TAG ".fp64.persistent.fixed")
 #define RD_MODEL_SET(KIND, MODEL, M, TAG) RD_MODEL_SET_W(KIND, MODEL, M, TAG, 3)

@@ -61,6 +61,21 @@ def test_persistent_equals_one_launch_bitwise(rd):
     assert np.array_equal(sa, sb)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_every_small_variant_bitwise(rd, precision):
+    """Every compiled kernel variant of the m = 3 engine (block size, waves per
+    SIMD, step-end batching, parameter staging, wave priorities, one launch)
+    gives bit-identical states and counters: the scheduling never changes
+    what a cell computes."""
+    w = W.oregonator_2d().subset(W.sample_indices(262144, 40000, 3))
+    a, sa, _ = run_gpu(rd, w, precision=precision)
+    for sched in (0, 1):
+        for v in range(1, rd.variant_count(rd.OREGONATOR, 3, precision, sched) + 1):
+            say("variant", rd.variant_name(rd.OREGONATOR, 3, precision, sched, v))
+            b, sb, _ = run_gpu(rd, w, precision=precision, schedule=sched, variant=v)
+            assert np.array_equal(a, b) and np.array_equal(sa, sb), (sched, v)
+
+
 def test_oregonator_2d_full_field(rd, orc):
     w = W.oregonator_2d()
     say("oregonator_2d fp64 persistent, n", w.n)
