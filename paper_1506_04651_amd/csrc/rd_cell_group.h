@@ -37,6 +37,7 @@
 
 #include "rd_constants.h"
 #include "rd_group.h"
+#include "rd_group_fused.h"
 #include "rd_launch.h"
 #include "rd_cell_small.h" /* status / phase / flag enums, UROUND, finite_d */
 
@@ -64,10 +65,13 @@ struct GroupLinear {
     static constexpr bool HAS_G = false;
 };
 
-template <class Model, typename LT>
+/* FUSE: broadcasts fused into the multiply-adds (rd_group_fused.h); same
+ * operations in the same order as the plain loops. */
+template <class Model, typename LT, bool FUSE = false>
 struct GroupCell {
     static constexpr int M = kGroup; /* loops run over the 16 lanes; rows >= m are zero */
     static constexpr bool HAS_G = Model::HAS_G;
+    static constexpr bool kFused = FUSE;
     int m;           /* species (run time, 1..16) */
     double inv3m, invm;
 
@@ -92,11 +96,25 @@ struct GroupCell {
     /* f_q(u) and (G u)_q; every lane of the group must be active */
     __device__ __forceinline__ double rhs(double u, double& gu) const {
         double lin = 0.0, loss = 0.0;
+        if constexpr (kFused) {
+            if constexpr (HAS_G) {
+                fused_row4<0>(u, kg, kg + M, lin, loss);
+                fused_row4<4>(u, kg, kg + M, lin, loss);
+                fused_row4<8>(u, kg, kg + M, lin, loss);
+                fused_row4<12>(u, kg, kg + M, lin, loss);
+            } else {
+                fused_row4<0>(u, kg, lin);
+                fused_row4<4>(u, kg, lin);
+                fused_row4<8>(u, kg, lin);
+                fused_row4<12>(u, kg, lin);
+            }
+        } else {
 #pragma unroll
-        for (int j = 0; j < M; ++j) {
-            const double uj = bcast_dyn(u, j);
-            lin += kg[j] * uj;
-            if (HAS_G) loss += kg[M + j] * uj;
+            for (int j = 0; j < M; ++j) {
+                const double uj = bcast_dyn(u, j);
+                lin += kg[j] * uj;
+                if (HAS_G) loss += kg[M + j] * uj;
+            }
         }
         gu = loss;
         return HAS_G ? lin - u * loss : lin;
@@ -192,9 +210,13 @@ struct GroupCell {
                 const LT inv = rcp(akk);
                 const bool piv = q == kk;
                 const LT f = piv ? LT(0) : a[kk] * inv;
+                if constexpr (kFused) {
+                    fused_gj_real(a, f, kk);
+                } else {
 #pragma unroll
-                for (int j = 0; j < M; ++j)
-                    if (j != kk) a[j] = fmaf_t(-f, bcast_dyn(a[j], kk), a[j]);
+                    for (int j = 0; j < M; ++j)
+                        if (j != kk) a[j] = fmaf_t(-f, bcast_dyn(a[j], kk), a[j]);
+                }
                 a[kk] = piv ? LT(1) : -f;
                 d = piv ? inv : d;
             }
@@ -235,12 +257,16 @@ struct GroupCell {
                 const LT xr = ar[kk], xi = ai[kk];
                 const LT fr = piv ? LT(0) : xr * ir - xi * ii;
                 const LT fi = piv ? LT(0) : xr * ii + xi * ir;
+                if constexpr (kFused) {
+                    fused_gj_cplx(ar, ai, fr, fi, kk);
+                } else {
 #pragma unroll
-                for (int j = 0; j < M; ++j) {
-                    if (j != kk) {
-                        const LT ur = bcast_dyn(ar[j], kk), ui = bcast_dyn(ai[j], kk);
-                        ar[j] = fmaf_t(-fr, ur, fmaf_t(fi, ui, ar[j]));
-                        ai[j] = fmaf_t(-fr, ui, fmaf_t(-fi, ur, ai[j]));
+                    for (int j = 0; j < M; ++j) {
+                        if (j != kk) {
+                            const LT ur = bcast_dyn(ar[j], kk), ui = bcast_dyn(ai[j], kk);
+                            ar[j] = fmaf_t(-fr, ur, fmaf_t(fi, ui, ar[j]));
+                            ai[j] = fmaf_t(-fr, ui, fmaf_t(-fi, ur, ai[j]));
+                        }
                     }
                 }
                 ar[kk] = piv ? LT(1) : -fr;
@@ -255,6 +281,9 @@ struct GroupCell {
     /* x = E1^{-1} b = diag(d) R (P b); lane q holds b_q on entry, x_q on return */
     __device__ __forceinline__ LT solve_real(LT b) const {
         if (__ballot(org1 != q) != 0ull) b = grp_shfl(b, org1);
+        if constexpr (kFused) {
+            if (m == M) return fused_mv16(e1, b) * d1;
+        }
         LT acc = LT(0);
 #pragma unroll
         for (int j = 0; j < M; ++j)
@@ -268,12 +297,21 @@ struct GroupCell {
             bi = grp_shfl(bi, org2);
         }
         LT sr = LT(0), si = LT(0);
+        bool done = false;
+        if constexpr (kFused) {
+            if (m == M) {
+                fused_cmv16(e2r, e2i, br, bi, sr, si);
+                done = true;
+            }
+        }
+        if (!done) {
 #pragma unroll
-        for (int j = 0; j < M; ++j) {
-            if (j < m) {
-                const LT ur = bcast_dyn(br, j), ui = bcast_dyn(bi, j);
-                sr = fmaf_t(e2r[j], ur, fmaf_t(-e2i[j], ui, sr));
-                si = fmaf_t(e2r[j], ui, fmaf_t(e2i[j], ur, si));
+            for (int j = 0; j < M; ++j) {
+                if (j < m) {
+                    const LT ur = bcast_dyn(br, j), ui = bcast_dyn(bi, j);
+                    sr = fmaf_t(e2r[j], ur, fmaf_t(-e2i[j], ui, sr));
+                    si = fmaf_t(e2r[j], ui, fmaf_t(e2i[j], ur, si));
+                }
             }
         }
         br = sr * d2r - si * d2i;

@@ -34,8 +34,8 @@ __device__ __forceinline__ void load_table(double* tab, const double* __restrict
     __syncthreads();
 }
 
-template <class Model, typename LT>
-__device__ __forceinline__ void init_cell(GroupCell<Model, LT>& cell, const double* tab, int m) {
+template <class Cell>
+__device__ __forceinline__ void init_cell(Cell& cell, const double* tab, int m) {
     cell.q = (int)grp_lane();
     cell.m = m;
     cell.act = cell.q < m;
@@ -47,8 +47,8 @@ __device__ __forceinline__ void init_cell(GroupCell<Model, LT>& cell, const doub
     cell.uJ = cell.gJ = 0.0;
 }
 
-template <class Model, typename LT, bool FIXED, int FSMIN>
-__device__ __forceinline__ void advance_group(GroupCell<Model, LT>& cell, const StepParams& P) {
+template <bool FIXED, int FSMIN, class Cell>
+__device__ __forceinline__ void advance_group(Cell& cell, const StepParams& P) {
     /* keep the LDS table reads inside the loop (no hoisting into registers) */
     /* keep the LDS model rows out of registers: they are re-read, not hoisted */
     __asm__ volatile("" ::: "memory");
@@ -71,7 +71,7 @@ __device__ __forceinline__ void advance_group(GroupCell<Model, LT>& cell, const 
     if (cell.phase == PH_START) cell.template start<FIXED>(P);
 }
 
-template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN>
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool FUSE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_group_onelaunch(LaunchArgs a, int m) {
     __shared__ double tab[GroupTable::DOUBLES];
@@ -80,22 +80,22 @@ k_group_onelaunch(LaunchArgs a, int m) {
     load_table<Model>(tab, a.params, m, BLOCK);
     const int64_t c = (int64_t)blockIdx.x * (BLOCK / kGroup) + threadIdx.x / kGroup;
     if (c >= a.n) return;
-    GroupCell<Model, LT> cell;
+    GroupCell<Model, LT, FUSE> cell;
     init_cell(cell, tab, m);
     cell.load(sP, a.states, a.n, c, a.hcell);
-    while (cell.phase != PH_IDLE) advance_group<Model, LT, FIXED, FSMIN>(cell, sP);
+    while (cell.phase != PH_IDLE) advance_group<FIXED, FSMIN>(cell, sP);
     cell.store(a.states, a.stats, a.n, c, a.hcell);
     if (cell.status != ST_OK && cell.q == 0) atomicAdd(a.nfail, 1ull);
 }
 
-template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN>
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool FUSE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_group_persistent(LaunchArgs a, int m) {
     __shared__ double tab[GroupTable::DOUBLES];
     __shared__ StepParams sP;
     stage_params(sP, a.P);
     load_table<Model>(tab, a.params, m, BLOCK);
-    GroupCell<Model, LT> cell;
+    GroupCell<Model, LT, FUSE> cell;
     init_cell(cell, tab, m);
     int64_t c = -1;
     bool alive = true;
@@ -139,35 +139,39 @@ k_group_persistent(LaunchArgs a, int m) {
             }
         }
         if (__ballot(alive) == 0ull) break;
-        advance_group<Model, LT, FIXED, FSMIN>(cell, sP);
+        advance_group<FIXED, FSMIN>(cell, sP);
     }
 }
 
 /* the species count travels in StepParams::m */
-template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN>
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool FUSE>
 hipError_t launch_group_one(const LaunchArgs& a, int grid, hipStream_t s) {
     constexpr int cells = BLOCK / kGroup;
     if (grid <= 0) grid = (int)((a.n + cells - 1) / cells);
-    hipLaunchKernelGGL((k_group_onelaunch<Model, LT, FIXED, BLOCK, WPE, FSMIN>), dim3(grid),
+    hipLaunchKernelGGL((k_group_onelaunch<Model, LT, FIXED, BLOCK, WPE, FSMIN, FUSE>), dim3(grid),
                        dim3(BLOCK), 0, s, a, (int)a.P.m);
     return hipGetLastError();
 }
 
-template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN>
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool FUSE>
 hipError_t launch_group_pers(const LaunchArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_group_persistent<Model, LT, FIXED, BLOCK, WPE, FSMIN>), dim3(grid),
+    hipLaunchKernelGGL((k_group_persistent<Model, LT, FIXED, BLOCK, WPE, FSMIN, FUSE>), dim3(grid),
                        dim3(BLOCK), 0, s, a, (int)a.P.m);
     return hipGetLastError();
 }
 
+/* FUSE: broadcasts fused into the multiply-adds (rd_group_fused.h), in FP64
+ * and, for the mixed kernels' factors and solves, in FP32. */
 #define RD_GONE(KIND, MODEL, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, NAME)                          \
     {KIND, 0, 16, PREC, 1, FIXED, VAR, BLOCK, BLOCK / kGroup, NAME,                                 \
-     &launch_group_one<MODEL, LT, FIXED, BLOCK, WPE, FS>,                                        \
-     (const void*)&k_group_onelaunch<MODEL, LT, FIXED, BLOCK, WPE, FS>}
-#define RD_GPERS(KIND, MODEL, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, NAME)                         \
+     &launch_group_one<MODEL, LT, FIXED, BLOCK, WPE, FS, true>,                                  \
+     (const void*)&k_group_onelaunch<MODEL, LT, FIXED, BLOCK, WPE, FS, true>}
+#define RD_GPERS_X(KIND, MODEL, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, FUSE, NAME)                 \
     {KIND, 0, 16, PREC, 0, FIXED, VAR, BLOCK, BLOCK / kGroup, NAME,                                 \
-     &launch_group_pers<MODEL, LT, FIXED, BLOCK, WPE, FS>,                                       \
-     (const void*)&k_group_persistent<MODEL, LT, FIXED, BLOCK, WPE, FS>}
+     &launch_group_pers<MODEL, LT, FIXED, BLOCK, WPE, FS, FUSE>,                                 \
+     (const void*)&k_group_persistent<MODEL, LT, FIXED, BLOCK, WPE, FS, FUSE>}
+#define RD_GPERS(KIND, MODEL, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, NAME)                         \
+    RD_GPERS_X(KIND, MODEL, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, true, NAME)
 
 /* m is marked 16 in the table: these kernels serve every 5 <= m <= 16 */
 static const KernelEntry g_group_table[] = {
@@ -183,12 +187,17 @@ static const KernelEntry g_group_table[] = {
     RD_GPERS(2, GroupKinetics, 1, float, false, 4, 256, 2, 2, "kinetics.g16.mixed.persistent.b256.w2.fs2"),
     RD_GPERS(2, GroupKinetics, 0, double, false, 5, 256, 3, 2, "kinetics.g16.fp64.persistent.b256.w3.fs2"),
     RD_GPERS(2, GroupKinetics, 1, float, false, 5, 256, 3, 2, "kinetics.g16.mixed.persistent.b256.w3.fs2"),
+    /* the same kernel as variant 1 with separate DPP moves and FMAs */
+    RD_GPERS_X(2, GroupKinetics, 0, double, false, 6, 256, 2, 3, false,
+               "kinetics.g16.fp64.persistent.b256.w2.fs3.unfused"),
     RD_GONE(2, GroupKinetics, 0, double, true, 1, 256, 1, 1, "kinetics.g16.fp64.onelaunch.fixed"),
     RD_GPERS(2, GroupKinetics, 0, double, true, 1, 256, 1, 1, "kinetics.g16.fp64.persistent.fixed"),
     RD_GONE(4, GroupLinear, 0, double, false, 1, 256, 1, 1, "linear.g16.fp64.onelaunch.b256"),
     RD_GONE(4, GroupLinear, 1, float, false, 1, 256, 1, 1, "linear.g16.mixed.onelaunch.b256"),
     RD_GPERS(4, GroupLinear, 0, double, false, 1, 256, 2, 3, "linear.g16.fp64.persistent.b256.w2.fs3"),
     RD_GPERS(4, GroupLinear, 1, float, false, 1, 256, 2, 3, "linear.g16.mixed.persistent.b256.w2.fs3"),
+    RD_GPERS_X(4, GroupLinear, 0, double, false, 2, 256, 2, 3, false,
+               "linear.g16.fp64.persistent.b256.w2.fs3.unfused"),
     RD_GONE(4, GroupLinear, 0, double, true, 1, 256, 1, 1, "linear.g16.fp64.onelaunch.fixed"),
     RD_GPERS(4, GroupLinear, 0, double, true, 1, 256, 1, 1, "linear.g16.fp64.persistent.fixed"),
 };
