@@ -177,8 +177,8 @@ hipError_t launch_group_pers(const LaunchArgs& a, int grid, hipStream_t s) {
 static const KernelEntry g_group_table[] = {
     RD_GONE(2, GroupKinetics, 0, double, false, 1, 256, 1, 1, "kinetics.g16.fp64.onelaunch.b256"),
     RD_GONE(2, GroupKinetics, 1, float, false, 1, 256, 1, 1, "kinetics.g16.mixed.onelaunch.b256"),
-    RD_GPERS(2, GroupKinetics, 0, double, false, 1, 256, 2, 3, "kinetics.g16.fp64.persistent.b256.w2.fs3"),
-    RD_GPERS(2, GroupKinetics, 1, float, false, 1, 256, 2, 3, "kinetics.g16.mixed.persistent.b256.w2.fs3"),
+    RD_GPERS(2, GroupKinetics, 0, double, false, 1, 256, 2, 4, "kinetics.g16.fp64.persistent.b256.w2.fs4"),
+    RD_GPERS(2, GroupKinetics, 1, float, false, 1, 256, 3, 4, "kinetics.g16.mixed.persistent.b256.w3.fs4"),
     RD_GPERS(2, GroupKinetics, 0, double, false, 2, 256, 1, 2, "kinetics.g16.fp64.persistent.b256.fs2"),
     RD_GPERS(2, GroupKinetics, 1, float, false, 2, 256, 1, 2, "kinetics.g16.mixed.persistent.b256.fs2"),
     RD_GPERS(2, GroupKinetics, 0, double, false, 3, 256, 2, 1, "kinetics.g16.fp64.persistent.b256.w2.fs1"),
@@ -188,16 +188,20 @@ static const KernelEntry g_group_table[] = {
     RD_GPERS(2, GroupKinetics, 0, double, false, 5, 256, 3, 2, "kinetics.g16.fp64.persistent.b256.w3.fs2"),
     RD_GPERS(2, GroupKinetics, 1, float, false, 5, 256, 3, 2, "kinetics.g16.mixed.persistent.b256.w3.fs2"),
     /* the same kernel as variant 1 with separate DPP moves and FMAs */
-    RD_GPERS_X(2, GroupKinetics, 0, double, false, 6, 256, 2, 3, false,
-               "kinetics.g16.fp64.persistent.b256.w2.fs3.unfused"),
+    RD_GPERS_X(2, GroupKinetics, 0, double, false, 6, 256, 2, 4, false,
+               "kinetics.g16.fp64.persistent.b256.w2.fs4.unfused"),
+    RD_GPERS(2, GroupKinetics, 1, float, false, 6, 256, 3, 3, "kinetics.g16.mixed.persistent.b256.w3.fs3"),
+    RD_GPERS(2, GroupKinetics, 0, double, false, 7, 256, 2, 3, "kinetics.g16.fp64.persistent.b256.w2.fs3"),
+    RD_GPERS(2, GroupKinetics, 1, float, false, 7, 256, 2, 3, "kinetics.g16.mixed.persistent.b256.w2.fs3"),
+    RD_GPERS(2, GroupKinetics, 1, float, false, 8, 128, 3, 4, "kinetics.g16.mixed.persistent.b128.w3.fs4"),
     RD_GONE(2, GroupKinetics, 0, double, true, 1, 256, 1, 1, "kinetics.g16.fp64.onelaunch.fixed"),
     RD_GPERS(2, GroupKinetics, 0, double, true, 1, 256, 1, 1, "kinetics.g16.fp64.persistent.fixed"),
     RD_GONE(4, GroupLinear, 0, double, false, 1, 256, 1, 1, "linear.g16.fp64.onelaunch.b256"),
     RD_GONE(4, GroupLinear, 1, float, false, 1, 256, 1, 1, "linear.g16.mixed.onelaunch.b256"),
-    RD_GPERS(4, GroupLinear, 0, double, false, 1, 256, 2, 3, "linear.g16.fp64.persistent.b256.w2.fs3"),
-    RD_GPERS(4, GroupLinear, 1, float, false, 1, 256, 2, 3, "linear.g16.mixed.persistent.b256.w2.fs3"),
-    RD_GPERS_X(4, GroupLinear, 0, double, false, 2, 256, 2, 3, false,
-               "linear.g16.fp64.persistent.b256.w2.fs3.unfused"),
+    RD_GPERS(4, GroupLinear, 0, double, false, 1, 256, 2, 4, "linear.g16.fp64.persistent.b256.w2.fs4"),
+    RD_GPERS(4, GroupLinear, 1, float, false, 1, 256, 3, 4, "linear.g16.mixed.persistent.b256.w3.fs4"),
+    RD_GPERS_X(4, GroupLinear, 0, double, false, 2, 256, 2, 4, false,
+               "linear.g16.fp64.persistent.b256.w2.fs4.unfused"),
     RD_GONE(4, GroupLinear, 0, double, true, 1, 256, 1, 1, "linear.g16.fp64.onelaunch.fixed"),
     RD_GPERS(4, GroupLinear, 0, double, true, 1, 256, 1, 1, "linear.g16.fp64.persistent.fixed"),
 };
