@@ -194,6 +194,8 @@ static const KernelEntry g_group_table[] = {
     RD_GPERS(2, GroupKinetics, 0, double, false, 7, 256, 2, 3, "kinetics.g16.fp64.persistent.b256.w2.fs3"),
     RD_GPERS(2, GroupKinetics, 1, float, false, 7, 256, 2, 3, "kinetics.g16.mixed.persistent.b256.w2.fs3"),
     RD_GPERS(2, GroupKinetics, 1, float, false, 8, 128, 3, 4, "kinetics.g16.mixed.persistent.b128.w3.fs4"),
+    RD_GPERS_X(2, GroupKinetics, 1, float, false, 9, 256, 3, 4, false,
+               "kinetics.g16.mixed.persistent.b256.w3.fs4.unfused"),
     RD_GONE(2, GroupKinetics, 0, double, true, 1, 256, 1, 1, "kinetics.g16.fp64.onelaunch.fixed"),
     RD_GPERS(2, GroupKinetics, 0, double, true, 1, 256, 1, 1, "kinetics.g16.fp64.persistent.fixed"),
     RD_GONE(4, GroupLinear, 0, double, false, 1, 256, 1, 1, "linear.g16.fp64.onelaunch.b256"),

@@ -140,6 +140,23 @@ def test_group_schedules_and_order_bitwise(rd):
         assert np.array_equal(a, d), v
 
 
+@pytest.mark.parametrize("m", [16, 7])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_group_variants_fused_and_unfused_identical(rd, m, precision):
+    """Every persistent variant of the 16-lane engine, including the ones
+    whose row broadcasts are separate DPP moves instead of fused DPP
+    multiply-adds, gives the same states and counters (m = 16 takes the fused
+    matrix-vector solves, m = 7 the loops)."""
+    w = W.kinetics16(n=6000, m=m, seed=21 + m)
+    a, sa, _ = run_gpu(rd, w, precision=precision)
+    names = []
+    for v in range(1, rd.variant_count(rd.KINETICS, 16, precision, 0) + 1):
+        names.append(rd.variant_name(rd.KINETICS, 16, precision, 0, v))
+        d, sd, _ = run_gpu(rd, w, precision=precision, variant=v)
+        assert np.array_equal(a, d) and np.array_equal(sa, sd), names[-1]
+    assert any(n.endswith(".unfused") for n in names)
+
+
 def test_kinetics16_mixed_precision_error_report(rd, orc):
     """FP32 factors and solves inside the FP64 Newton iteration: per-cell
     error against the FP64 oracle is reported; every cell must stay within the
