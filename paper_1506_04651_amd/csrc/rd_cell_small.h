@@ -238,19 +238,26 @@ __device__ __forceinline__ void lu_solve_cplx(const T (&ar)[M][M], const T (&ai)
 }
 
 /* Per-lane LDS slots: a [ROWS][BLOCK] array, lane column `tid`. */
-template <int BLOCK>
+template <int BLOCK, typename V = double>
 struct LdsCol {
-    double* base; /* &arr[0][tid] */
-    __device__ __forceinline__ double& operator[](int row) const { return base[row * BLOCK]; }
+    V* base; /* &arr[0][tid] */
+    __device__ __forceinline__ V& operator[](int row) const { return base[row * BLOCK]; }
 };
 
-/* Rows of the per-lane LDS column: Jacobian (M*M), then Z of the last
- * accepted step (3*M). */
+/* Rows of the per-lane LDS column: Jacobian (M*M), Z of the last accepted
+ * step (3*M), then the step-control scalars read once per step (previous
+ * step size, 1/h and err^(1/4) of the last accepted step, the warm-start
+ * step size); and the integer rows of the counters that change once per
+ * step or less.  Keeping this cold state out of registers lets the engine
+ * run three waves per SIMD with fewer spills. */
 template <int M>
 struct SmallLds {
     static constexpr int J0 = 0;
     static constexpr int Z0 = M * M;
-    static constexpr int ROWS = M * M + 3 * M;
+    static constexpr int HOLD = M * M + 3 * M, IHACC = HOLD + 1, QACC = HOLD + 2, HPRE = HOLD + 3;
+    static constexpr int ROWS = HPRE + 1;
+    static constexpr int NSTEP = 0, NACCEPT = 1, NREJECT = 2, NJAC = 3, NDEC = 4;
+    static constexpr int IROWS = 5;
 };
 
 /* ---------------- the per-cell engine ----------------------------------- */
@@ -263,13 +270,14 @@ struct SmallCell {
     double y[M], f0[M], isc[M];
     double w[3][M];
     LT e1[M][M], e2r[M][M], e2i[M][M];
-    double t, h, ih, h_old, ih_acc, qerr_acc, eta, inprev;
-    double h_pre; /* step size before the last-step shortening (warm start out) */
+    double t, h, ih, eta, inprev;
     unsigned p1, p2, flags;
     int phase, status, k, nsing, outcome;
-    /* counters (paper Appendix A: f evaluations per node) */
-    int nstep, naccept, nreject, nfev, njac, ndec, nsol, nnewt;
+    /* counters (paper Appendix A: f evaluations per node); the ones that
+     * change once per step or less live in LDS (SmallLds) */
+    int nfev, nsol, nnewt;
     LdsCol<BLOCK> lds;
+    LdsCol<BLOCK, int> ilds;
 
     __device__ __forceinline__ bool has(unsigned f) const { return (flags & f) != 0u; }
     __device__ __forceinline__ void set(unsigned f, bool v) { flags = v ? (flags | f) : (flags & ~f); }
@@ -279,7 +287,9 @@ struct SmallCell {
                                          int64_t c, const double* __restrict__ hcell) {
 #pragma unroll
         for (int r = 0; r < M; ++r) y[r] = states[(int64_t)r * n + c];
-        nstep = naccept = nreject = njac = ndec = nsol = nnewt = 0;
+        ilds[L::NSTEP] = ilds[L::NACCEPT] = ilds[L::NREJECT] = 0;
+        ilds[L::NJAC] = ilds[L::NDEC] = 0;
+        nsol = nnewt = 0;
         nfev = 1;
         md.rhs(y, f0);
         status = ST_OK;
@@ -291,8 +301,8 @@ struct SmallCell {
         const double hw = hcell ? hcell[c] : 0.0;
         h = P.fixed_steps > 0 ? P.dt / P.fixed_steps
                               : fmin(hw > 0.0 ? hw : (P.h0 > 0.0 ? P.h0 : P.dt), P.dt);
-        h_pre = fin ? h : 0.0;
-        h_old = ih_acc = qerr_acc = inprev = 0.0;
+        lds[L::HPRE] = fin ? h : 0.0;
+        lds[L::HOLD] = lds[L::IHACC] = lds[L::QACC] = inprev = 0.0;
         eta = 1.0;
         k = 0;
         nsing = 0;
@@ -305,15 +315,15 @@ struct SmallCell {
                                           int64_t n, int64_t c, double* __restrict__ hcell) const {
 #pragma unroll
         for (int r = 0; r < M; ++r) states[(int64_t)r * n + c] = y[r];
-        if (hcell) hcell[c] = h_pre;
+        if (hcell) hcell[c] = lds[L::HPRE];
         if (stats) {
             stats[0 * n + c] = status;
-            stats[1 * n + c] = nstep;
-            stats[2 * n + c] = naccept;
-            stats[3 * n + c] = nreject;
+            stats[1 * n + c] = ilds[L::NSTEP];
+            stats[2 * n + c] = ilds[L::NACCEPT];
+            stats[3 * n + c] = ilds[L::NREJECT];
             stats[4 * n + c] = nfev;
-            stats[5 * n + c] = njac;
-            stats[6 * n + c] = ndec;
+            stats[5 * n + c] = ilds[L::NJAC];
+            stats[6 * n + c] = ilds[L::NDEC];
             stats[7 * n + c] = nsol;
             stats[8 * n + c] = nnewt;
         }
@@ -342,8 +352,8 @@ struct SmallCell {
     template <bool FIXED>
     __device__ __forceinline__ void start(const Model& md, const StepParams& P) {
         if (!FIXED) {
-            h_pre = h;
-            if (nstep >= P.max_steps) { status = ST_MAXSTEPS; phase = PH_IDLE; return; }
+            lds[L::HPRE] = h;
+            if (ilds[L::NSTEP] >= P.max_steps) { status = ST_MAXSTEPS; phase = PH_IDLE; return; }
             if (h < P.h_min) { status = ST_HSMALL; phase = PH_IDLE; return; }
             const bool last = t + 1.0001 * h >= P.dt;
             if (last) {
@@ -368,11 +378,11 @@ struct SmallCell {
             for (int i = 0; i < M; ++i)
 #pragma unroll
                 for (int j = 0; j < M; ++j) lds[L::J0 + i * M + j] = J[i][j];
-            ++njac;
+            ++ilds[L::NJAC];
             flags = (flags & ~(F_JSTALE | F_LUOK)) | F_JATY0;
         }
         if (FIXED || !has(F_LUOK)) {
-            ++ndec;
+            ++ilds[L::NDEC];
             if (!factor()) {
                 if (FIXED || ++nsing >= 5) { status = ST_SINGULAR; phase = PH_IDLE; return; }
                 h *= 0.5;
@@ -386,7 +396,7 @@ struct SmallCell {
          * step continued to the new stage points (nodes s = -1, c1-1, c2-1, 0
          * in units of h_old; values -z3, z1 - z3, z2 - z3, 0), then W = T^-1 Z. */
         if (has(F_OLD)) {
-            const double r = h * rcp(h_old);
+            const double r = h * rcp(lds[L::HOLD]);
             const double s1 = -1.0, s2 = radau::C1 - 1.0, s3 = radau::C2 - 1.0;
             const double cs[3] = {radau::C1 * r, radau::C2 * r, r};
             double Lw[3][3];
@@ -531,21 +541,21 @@ struct SmallCell {
     __device__ __forceinline__ void finish(const Model& md, const StepParams& P, int outcome) {
         if (FIXED) {
             if (outcome == NW_FAILED) { status = ST_NEWTON; phase = PH_IDLE; return; }
-            ++nstep;
-            ++naccept;
+            ++ilds[L::NSTEP];
+            ++ilds[L::NACCEPT];
             accept_state(md);
             bool fin = true;
 #pragma unroll
             for (int q = 0; q < M; ++q) fin = fin && finite_d(y[q]);
             if (!fin) { status = ST_NONFINITE; phase = PH_IDLE; return; }
-            h_old = h;
+            lds[L::HOLD] = h;
             eta = pow08(fmax(eta, UROUND));
-            phase = (naccept >= P.fixed_steps) ? PH_IDLE : PH_START;
+            phase = (ilds[L::NACCEPT] >= P.fixed_steps) ? PH_IDLE : PH_START;
             return;
         }
         if (outcome == NW_FAILED) {
-            ++nstep;
-            ++nreject;
+            ++ilds[L::NSTEP];
+            ++ilds[L::NREJECT];
             h *= 0.5;
             flags = (flags | F_REJECT) & ~F_LUOK;
             if (!has(F_JATY0)) flags |= F_JSTALE;
@@ -563,7 +573,7 @@ struct SmallCell {
             err = estimate(fe, e);
         }
         if (!finite_d(err)) { status = ST_NONFINITE; phase = PH_IDLE; return; }
-        ++nstep;
+        ++ilds[L::NSTEP];
         const double fac = k <= kMaxFacTable
                                ? P.fac[k]
                                : 0.9 * (2.0 * P.kmax + 1.0) / (2.0 * P.kmax + (double)k);
@@ -576,7 +586,7 @@ struct SmallCell {
                 /* predictive: fac (h / h_acc) err_acc^(1/4) / err^(1/2) */
                 const double r2 = (err == 0.0)
                     ? 8.0
-                    : fmin(8.0, fmax(0.2, fac * (h * ih_acc) * qerr_acc * (s * s)));
+                    : fmin(8.0, fmax(0.2, fac * (h * lds[L::IHACC]) * lds[L::QACC] * (s * s)));
                 h_new = fmin(h_new, h * r2);
             }
             double zs[3][M];
@@ -594,9 +604,9 @@ struct SmallCell {
 #pragma unroll
             for (int q = 0; q < M; ++q) fin = fin && finite_d(y1[q]) && finite_d(f1[q]);
             if (!fin) { status = ST_NONFINITE; phase = PH_IDLE; return; }
-            ih_acc = ih;
+            lds[L::IHACC] = ih;
             /* max(err, 1e-2)^(1/4); (1e-2)^(1/4) = sqrt(0.1) */
-            qerr_acc = err >= 1e-2 ? rcp_nr(s) : 0.31622776601683794;
+            lds[L::QACC] = err >= 1e-2 ? rcp_nr(s) : 0.31622776601683794;
 #pragma unroll
             for (int q = 0; q < M; ++q) {
                 y[q] = y1[q];
@@ -606,9 +616,9 @@ struct SmallCell {
                 lds[L::Z0 + 2 * M + q] = zs[2][q];
             }
             t = has(F_LAST) ? P.dt : t + h;
-            h_old = h;
+            lds[L::HOLD] = h;
             eta = pow08(fmax(eta, UROUND));
-            ++naccept;
+            ++ilds[L::NACCEPT];
             if (has(F_REJECT)) h_new = fmin(h_new, h);
             const bool keep_j = has(F_KEEPJ);
             flags = (flags & ~(F_FIRST | F_REJECT | F_JATY0 | F_JSTALE)) | F_OLD | F_ACC |
@@ -622,7 +632,7 @@ struct SmallCell {
             h = hn;
             phase = (t < P.dt) ? PH_START : PH_IDLE;
         } else {
-            ++nreject;
+            ++ilds[L::NREJECT];
             const double hn = has(F_FIRST) ? 0.1 * h : h_new;
             if (hn != h) flags &= ~F_LUOK;
             h = hn;

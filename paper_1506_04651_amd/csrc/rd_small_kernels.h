@@ -46,6 +46,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE,
 k_onelaunch(LaunchArgs a) {
     using L = SmallLds<Model::M>;
     __shared__ double sh[L::ROWS * BLOCK];
+    __shared__ int shi[L::IROWS * BLOCK];
     __shared__ StepParams sP;
     stage_params(sP, a.P);
     const int64_t c = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
@@ -53,6 +54,7 @@ k_onelaunch(LaunchArgs a) {
     const Model md(a.params);
     SmallCell<Model, LT, BLOCK> cell;
     cell.lds.base = sh + threadIdx.x;
+    cell.ilds.base = shi + threadIdx.x;
     cell.load(md, sP, a.states, a.n, c, a.hcell);
     while (cell.phase != PH_IDLE) {
         __asm__ volatile("" ::: "memory"); /* re-read sP from LDS each pass */
@@ -95,12 +97,14 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE,
 k_persistent(LaunchArgs a) {
     using L = SmallLds<Model::M>;
     __shared__ double sh[L::ROWS * BLOCK];
+    __shared__ int shi[L::IROWS * BLOCK];
     __shared__ StepParams sPl;
     if (PLDS) stage_params(sPl, a.P);
     const StepParams& sP = PLDS ? sPl : a.P;
     const Model md(a.params);
     SmallCell<Model, LT, BLOCK> cell;
     cell.lds.base = sh + threadIdx.x;
+    cell.ilds.base = shi + threadIdx.x;
     cell.phase = PH_IDLE;
     cell.status = ST_OK;
     int64_t c = -1;
