@@ -166,7 +166,9 @@ int enqueue_order(DevCtx& c, Prepared& pr, hipStream_t s, unsigned long long* co
     if (pr.entry->schedule != RD_PERSISTENT || !pr.order || pr.args.n < kOrderMinCells ||
         pr.args.n > INT32_MAX)
         return 0;
-    order_fn fn = find_order_fn(pr.entry->kind, pr.entry->m);
+    /* the 16-lane kernels are registered under m = 16 but serve 5..16:
+     * the cost keys use the request's species count */
+    order_fn fn = find_order_fn(pr.entry->kind, (int)pr.args.P.m);
     if (!fn) return 0;
     const size_t wsb = order_workspace_bytes(pr.args.n);
     const size_t ordb = ((size_t)pr.args.n * sizeof(int32_t) + 255) & ~(size_t)255;

@@ -67,7 +67,7 @@ struct KernelEntry {
 typedef hipError_t (*order_fn)(const LaunchArgs&, void* ws, int32_t* order,
                                unsigned long long* counters, hipStream_t);
 size_t order_workspace_bytes(int64_t n);
-order_fn find_order_fn(int kind, int m);
+order_fn find_order_fn(int kind, int m); /* m: the request's species count */
 
 /* All kernels compiled into the library. */
 const KernelEntry* kernel_table(int* count);

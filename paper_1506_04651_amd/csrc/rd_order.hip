@@ -28,6 +28,7 @@ constexpr int kSub = 4;                 /* buckets per octave */
 constexpr int kBuckets = 64 * kSub;     /* 64 octaves */
 constexpr int kLog2Min = -24;           /* bucket 0 holds key < 2^-24 (and non-finite keys) */
 constexpr int kOrderBlock = 1024;
+constexpr int kMaxGroupM = 16; /* species of the 16-lane kernels: 5..16 */
 
 static size_t align_up(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -66,17 +67,12 @@ __device__ __forceinline__ unsigned wave_bucket_add(unsigned* lh, int b, bool ac
     return slot;
 }
 
+/* max_i |f_i(u0)| dt / (atol' + rtol' |u0_i|) of cell c, for a model with a
+ * compile-time species count */
 template <class Model>
-__global__ void __launch_bounds__(kOrderBlock) k_order_cost(LaunchArgs a, unsigned char* bucket,
-                                                            unsigned* hist) {
-    constexpr int M = Model::M;
-    __shared__ unsigned lh[kBuckets];
-    if (threadIdx.x < kBuckets) lh[threadIdx.x] = 0u;
-    __syncthreads();
-    const int64_t c = (int64_t)blockIdx.x * kOrderBlock + threadIdx.x;
-    const bool act = c < a.n;
-    int b = 0;
-    if (act) {
+struct ModelKey {
+    static __device__ __forceinline__ double key(const LaunchArgs& a, int64_t c) {
+        constexpr int M = Model::M;
         const Model md(a.params);
         double y[M], f[M];
 #pragma unroll
@@ -86,6 +82,53 @@ __global__ void __launch_bounds__(kOrderBlock) k_order_cost(LaunchArgs a, unsign
 #pragma unroll
         for (int r = 0; r < M; ++r)
             key = fmax(key, __builtin_fabs(f[r]) * a.P.dt / (a.P.atol + a.P.rtol * __builtin_fabs(y[r])));
+        return key;
+    }
+};
+
+/* The same key for the kinetics (HAS_G) and linear models of the 16-lane
+ * kernels, whose species count 5..16 is known at run time (StepParams::m):
+ * states [m][n], parameter blocks K then G, each m x m row-major. */
+template <bool HAS_G>
+struct GroupKey {
+    static __device__ __forceinline__ double key(const LaunchArgs& a, int64_t c) {
+        const int m = a.P.m;
+        double y[kMaxGroupM];
+#pragma unroll
+        for (int r = 0; r < kMaxGroupM; ++r) y[r] = r < m ? a.states[(int64_t)r * a.n + c] : 0.0;
+        const double* K = a.params;
+        const double* G = a.params + m * m;
+        double key = 0.0;
+        for (int i = 0; i < m; ++i) {
+            double lin = 0.0, loss = 0.0;
+#pragma unroll
+            for (int j = 0; j < kMaxGroupM; ++j) {
+                if (j < m) {
+                    lin += K[i * m + j] * y[j];
+                    if (HAS_G) loss += G[i * m + j] * y[j];
+                }
+            }
+            double yi = 0.0;
+#pragma unroll
+            for (int r = 0; r < kMaxGroupM; ++r) yi = r == i ? y[r] : yi;
+            const double f = HAS_G ? lin - yi * loss : lin;
+            key = fmax(key, __builtin_fabs(f) * a.P.dt / (a.P.atol + a.P.rtol * __builtin_fabs(yi)));
+        }
+        return key;
+    }
+};
+
+template <class Key>
+__global__ void __launch_bounds__(kOrderBlock) k_order_cost(LaunchArgs a, unsigned char* bucket,
+                                                            unsigned* hist) {
+    __shared__ unsigned lh[kBuckets];
+    if (threadIdx.x < kBuckets) lh[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t c = (int64_t)blockIdx.x * kOrderBlock + threadIdx.x;
+    const bool act = c < a.n;
+    int b = 0;
+    if (act) {
+        const double key = Key::key(a, c);
         if (key > 0.0 && __builtin_isfinite(key)) {
             /* floor(kSub log2(key)), approximately: the exponent field and
              * the leading mantissa bits (subnormals clamp low) */
@@ -146,48 +189,48 @@ __global__ void __launch_bounds__(kOrderBlock) k_order_scatter(const unsigned ch
     if (act) order[lbase[b] + local] = (int32_t)c;
 }
 
-template <class Model>
+template <class Key>
 hipError_t launch_order(const LaunchArgs& a, void* ws, int32_t* order,
                         unsigned long long* counters, hipStream_t s) {
     unsigned char* bucket = (unsigned char*)ws;
     unsigned* hist = (unsigned*)((char*)ws + align_up((size_t)a.n));
     const int grid = (int)((a.n + kOrderBlock - 1) / kOrderBlock);
     hipLaunchKernelGGL(k_order_init, dim3(1), dim3(2 * kBuckets), 0, s, hist, counters);
-    hipLaunchKernelGGL(k_order_cost<Model>, dim3(grid), dim3(kOrderBlock), 0, s, a, bucket, hist);
+    hipLaunchKernelGGL(k_order_cost<Key>, dim3(grid), dim3(kOrderBlock), 0, s, a, bucket, hist);
     hipLaunchKernelGGL(k_order_scatter, dim3(grid), dim3(kOrderBlock), 0, s,
                        (const unsigned char*)bucket, hist, order, a.n);
     return hipGetLastError();
 }
 
 order_fn find_order_fn(int kind, int m) {
+    if ((kind == 2 || kind == 4) && m > 4 && m <= kMaxGroupM)
+        return kind == 2 ? &launch_order<GroupKey<true>> : &launch_order<GroupKey<false>>;
     switch (kind) {
-    case 1: return m == 3 ? &launch_order<Oregonator> : nullptr;
-    case 5: return m == 3 ? &launch_order<Robertson> : nullptr;
-    case 3: return m == 1 ? &launch_order<Nagumo> : nullptr;
+    case 1: return m == 3 ? &launch_order<ModelKey<Oregonator>> : nullptr;
+    case 5: return m == 3 ? &launch_order<ModelKey<Robertson>> : nullptr;
+    case 3: return m == 1 ? &launch_order<ModelKey<Nagumo>> : nullptr;
     case 4:
         switch (m) {
-        case 1: return &launch_order<Linear<1>>;
-        case 2: return &launch_order<Linear<2>>;
-        case 3: return &launch_order<Linear<3>>;
-        case 4: return &launch_order<Linear<4>>;
-        case 16: return &launch_order<Linear<16>>;
+        case 1: return &launch_order<ModelKey<Linear<1>>>;
+        case 2: return &launch_order<ModelKey<Linear<2>>>;
+        case 3: return &launch_order<ModelKey<Linear<3>>>;
+        case 4: return &launch_order<ModelKey<Linear<4>>>;
         default: return nullptr;
         }
     case 2:
         switch (m) {
-        case 1: return &launch_order<Kinetics<1>>;
-        case 2: return &launch_order<Kinetics<2>>;
-        case 3: return &launch_order<Kinetics<3>>;
-        case 4: return &launch_order<Kinetics<4>>;
-        case 16: return &launch_order<Kinetics<16>>;
+        case 1: return &launch_order<ModelKey<Kinetics<1>>>;
+        case 2: return &launch_order<ModelKey<Kinetics<2>>>;
+        case 3: return &launch_order<ModelKey<Kinetics<3>>>;
+        case 4: return &launch_order<ModelKey<Kinetics<4>>>;
         default: return nullptr;
         }
     case 6:
         switch (m) {
-        case 1: return &launch_order<Bytecode<1>>;
-        case 2: return &launch_order<Bytecode<2>>;
-        case 3: return &launch_order<Bytecode<3>>;
-        case 4: return &launch_order<Bytecode<4>>;
+        case 1: return &launch_order<ModelKey<Bytecode<1>>>;
+        case 2: return &launch_order<ModelKey<Bytecode<2>>>;
+        case 3: return &launch_order<ModelKey<Bytecode<3>>>;
+        case 4: return &launch_order<ModelKey<Bytecode<4>>>;
         default: return nullptr;
         }
     default: return nullptr;
