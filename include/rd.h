@@ -306,7 +306,10 @@ int32_t rd_session_destroy(rd_session* s);
 const char* rd_last_error(void);
 
 /* Number of kernel variants for (model kind, m, precision, schedule), and the
- * name of variant v (1-based); NULL when out of range. */
+ * name of variant v (1-based); NULL when out of range.  Kinetics and linear
+ * models share one variant set for m = 5..8 (8-column kernels) and one for
+ * m = 9..16 (16-column kernels); a default set for one m of a set applies to
+ * the whole set. */
 int32_t rd_variant_count(int32_t kind, int32_t m, int32_t precision,
                          int32_t schedule);
 const char* rd_variant_name(int32_t kind, int32_t m, int32_t precision,

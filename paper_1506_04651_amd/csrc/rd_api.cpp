@@ -78,11 +78,18 @@ static int default_variant(int kind, int m, int precision, int schedule) {
 /* The kind's own Jacobian: analytic, except for the bytecode model. */
 static int native_jac(int kind) { return kind == RD_BYTECODE ? RD_JAC_FD : RD_JAC_ANALYTIC; }
 
+/* Species count under which a request's kernels are registered: kinetics and
+ * linear models with 5..8 species run on the 8-column group kernels (m = 8),
+ * with 9..16 on the 16-column ones (m = 16); everything else under its own m.
+ * Variant ids and tuned defaults refer to this registry entry. */
+static int registry_m(int kind, int m) {
+    if ((kind == RD_KINETICS || kind == RD_LINEAR) && m > 4 && m <= RD_MAX_M) return m <= 8 ? 8 : 16;
+    return m;
+}
+
 const KernelEntry* find_kernel(int kind, int m, int precision, int schedule, int fixed,
                                int variant, int jac) {
-    /* kinetics and linear models with 5..16 species run on the 16-lane group
-     * kernels, registered under m = 16 */
-    if ((kind == RD_KINETICS || kind == RD_LINEAR) && m > 4 && m <= RD_MAX_M) m = 16;
+    m = registry_m(kind, m);
     if (jac < 0) jac = native_jac(kind);
     /* tuned defaults and variant ids refer to the kind's own Jacobian; the
      * finite-difference kernels of analytic models come in one variant */
@@ -575,6 +582,7 @@ double rd_last_kernel_ms(void) {
 }
 
 int32_t rd_variant_count(int32_t kind, int32_t m, int32_t precision, int32_t schedule) {
+    m = registry_m(kind, m);
     int best = 0;
     for (const KernelEntry& e : all_kernels())
         if (e.kind == kind && e.jac == native_jac(kind) && e.m == m && e.precision == precision &&
@@ -598,7 +606,7 @@ int32_t rd_set_default_variant(int32_t kind, int32_t m, int32_t precision, int32
         return RD_EINVAL;
     }
     std::lock_guard<std::mutex> lk(g_variant_mu);
-    g_default_variant[{kind, m, precision, schedule}] = variant;
+    g_default_variant[{kind, registry_m(kind, m), precision, schedule}] = variant;
     return 0;
 }
 

@@ -66,10 +66,14 @@ struct GroupLinear {
 };
 
 /* FUSE: broadcasts fused into the multiply-adds (rd_group_fused.h); same
- * operations in the same order as the plain loops. */
-template <class Model, typename LT, bool FUSE = false>
+ * operations in the same order as the plain loops.  NC: matrix columns held
+ * per lane, 16, or 8 for m <= 8 (lanes 8..15 of the group then hold zero
+ * rows, as lanes m..15 do in either form; halving the columns halves the
+ * matrices' registers and the elimination work). */
+template <class Model, typename LT, bool FUSE = false, int NC = kGroup>
 struct GroupCell {
-    static constexpr int M = kGroup; /* loops run over the 16 lanes; rows >= m are zero */
+    static_assert(NC == 8 || NC == kGroup, "8 or 16 columns");
+    static constexpr int M = NC; /* loops run over NC columns; rows and columns >= m are zero */
     static constexpr bool HAS_G = Model::HAS_G;
     static constexpr bool kFused = FUSE;
     int m;           /* species (run time, 1..16) */
@@ -80,7 +84,7 @@ struct GroupCell {
     LT e1[M], e2r[M], e2i[M]; /* rows of the Gauss-Jordan inverses (see gj_real) */
     LT d1, d2r, d2i;          /* reciprocal pivots */
     int org1, org2;
-    const double* kg; /* LDS row q: K then G */
+    const double* kg; /* LDS row q: K at kg[0..16), G at kg[16..32) */
     int q;
     bool act;         /* q < m */
     /* per-cell scalars, replicated across the group */
@@ -98,22 +102,26 @@ struct GroupCell {
         double lin = 0.0, loss = 0.0;
         if constexpr (kFused) {
             if constexpr (HAS_G) {
-                fused_row4<0>(u, kg, kg + M, lin, loss);
-                fused_row4<4>(u, kg, kg + M, lin, loss);
-                fused_row4<8>(u, kg, kg + M, lin, loss);
-                fused_row4<12>(u, kg, kg + M, lin, loss);
+                fused_row4<0>(u, kg, kg + kGroup, lin, loss);
+                fused_row4<4>(u, kg, kg + kGroup, lin, loss);
+                if constexpr (NC == 16) {
+                    fused_row4<8>(u, kg, kg + kGroup, lin, loss);
+                    fused_row4<12>(u, kg, kg + kGroup, lin, loss);
+                }
             } else {
                 fused_row4<0>(u, kg, lin);
                 fused_row4<4>(u, kg, lin);
-                fused_row4<8>(u, kg, lin);
-                fused_row4<12>(u, kg, lin);
+                if constexpr (NC == 16) {
+                    fused_row4<8>(u, kg, lin);
+                    fused_row4<12>(u, kg, lin);
+                }
             }
         } else {
 #pragma unroll
             for (int j = 0; j < M; ++j) {
                 const double uj = bcast_dyn(u, j);
                 lin += kg[j] * uj;
-                if (HAS_G) loss += kg[M + j] * uj;
+                if (HAS_G) loss += kg[kGroup + j] * uj;
             }
         }
         gu = loss;
@@ -170,7 +178,7 @@ struct GroupCell {
     __device__ __forceinline__ double jac(int j) const {
         double v = kg[j];
         if (HAS_G) {
-            v -= uJ * kg[M + j];
+            v -= uJ * kg[kGroup + j];
             if (j == q) v -= gJ;
         }
         return act ? v : 0.0;
@@ -211,7 +219,7 @@ struct GroupCell {
                 const bool piv = q == kk;
                 const LT f = piv ? LT(0) : a[kk] * inv;
                 if constexpr (kFused) {
-                    fused_gj_real(a, f, kk);
+                    fused_gj_real<NC>(a, f, kk);
                 } else {
 #pragma unroll
                     for (int j = 0; j < M; ++j)
@@ -258,7 +266,7 @@ struct GroupCell {
                 const LT fr = piv ? LT(0) : xr * ir - xi * ii;
                 const LT fi = piv ? LT(0) : xr * ii + xi * ir;
                 if constexpr (kFused) {
-                    fused_gj_cplx(ar, ai, fr, fi, kk);
+                    fused_gj_cplx<NC>(ar, ai, fr, fi, kk);
                 } else {
 #pragma unroll
                     for (int j = 0; j < M; ++j) {
@@ -282,7 +290,10 @@ struct GroupCell {
     __device__ __forceinline__ LT solve_real(LT b) const {
         if (__ballot(org1 != q) != 0ull) b = grp_shfl(b, org1);
         if constexpr (kFused) {
-            if (m == M) return fused_mv16(e1, b) * d1;
+            if (m == M) {
+                if constexpr (NC == 16) return fused_mv16(e1, b) * d1;
+                else return fused_mv8(e1, b) * d1;
+            }
         }
         LT acc = LT(0);
 #pragma unroll
@@ -300,7 +311,8 @@ struct GroupCell {
         bool done = false;
         if constexpr (kFused) {
             if (m == M) {
-                fused_cmv16(e2r, e2i, br, bi, sr, si);
+                if constexpr (NC == 16) fused_cmv16(e2r, e2i, br, bi, sr, si);
+                else fused_cmv8(e2r, e2i, br, bi, sr, si);
                 done = true;
             }
         }

@@ -59,6 +59,22 @@ __device__ __forceinline__ T fused_mv16(const T (&e)[16], T b) {
     return acc;
 }
 #undef RD_MV_BODY
+#define RD_MV8_BODY(OP)                                                                           \
+    "s_nop 1\n\t"                                                                                 \
+    RD_FM(OP, 0, 1, 2, 0) RD_FM(OP, 0, 1, 3, 1) RD_FM(OP, 0, 1, 4, 2) RD_FM(OP, 0, 1, 5, 3)       \
+    RD_FM(OP, 0, 1, 6, 4) RD_FM(OP, 0, 1, 7, 5) RD_FM(OP, 0, 1, 8, 6) RD_FM(OP, 0, 1, 9, 7)       \
+    "s_nop 1"
+/* the same product for the 8-column engine (m == 8) */
+template <typename T>
+__device__ __forceinline__ T fused_mv8(const T (&e)[8], T b) {
+    T acc = T(0);
+    RD_ASM2(T, RD_MV8_BODY,
+            : "+v"(acc)
+            : "v"(b), "v"(e[0]), "v"(e[1]), "v"(e[2]), "v"(e[3]), "v"(e[4]), "v"(e[5]), "v"(e[6]),
+              "v"(e[7]));
+    return acc;
+}
+#undef RD_MV8_BODY
 
 /* Complex product, per column j in order:
  *   sr += bi_j * (-ei[j]);  sr += br_j * er[j];
@@ -88,6 +104,25 @@ __device__ __forceinline__ void fused_cmv16(const T (&er)[16], const T (&ei)[16]
     si_out = si;
 }
 #undef RD_CMV_BODY
+#define RD_CMV8_BODY(OP)                                                                          \
+    "s_nop 1\n\t"                                                                                 \
+    RD_CMV(OP, 0, 4, 12) RD_CMV(OP, 1, 5, 13) RD_CMV(OP, 2, 6, 14) RD_CMV(OP, 3, 7, 15)           \
+    RD_CMV(OP, 4, 8, 16) RD_CMV(OP, 5, 9, 17) RD_CMV(OP, 6, 10, 18) RD_CMV(OP, 7, 11, 19)         \
+    "s_nop 1"
+/* the same product for the 8-column engine (m == 8) */
+template <typename T>
+__device__ __forceinline__ void fused_cmv8(const T (&er)[8], const T (&ei)[8], T br, T bi, T& sr_out,
+                                           T& si_out) {
+    T sr = T(0), si = T(0);
+    RD_ASM2(T, RD_CMV8_BODY,
+            : "+v"(sr), "+v"(si)
+            : "v"(br), "v"(bi), "v"(er[0]), "v"(er[1]), "v"(er[2]), "v"(er[3]), "v"(er[4]),
+              "v"(er[5]), "v"(er[6]), "v"(er[7]), "v"(ei[0]), "v"(ei[1]), "v"(ei[2]), "v"(ei[3]),
+              "v"(ei[4]), "v"(ei[5]), "v"(ei[6]), "v"(ei[7]));
+    sr_out = sr;
+    si_out = si;
+}
+#undef RD_CMV8_BODY
 #undef RD_CMV
 
 /* Four columns J0..J0+3 of a model row (FP64):  lin += u(lane j) * k[j] and
@@ -141,6 +176,22 @@ __device__ __forceinline__ void fused_gj_real_k(T (&a)[16], T f) {
 #undef RD_GJR_BODY
 #undef RD_GJR
 
+/* The same step for the 8-column engine (m <= 8). */
+#define RD_GJR8(OP, J) OP " %" #J ", %" #J ", -%8 row_newbcast:%9 row_mask:0xf bank_mask:0xf\n\t"
+#define RD_GJR8_BODY(OP)                                                                          \
+    "s_nop 1\n\t"                                                                                 \
+    RD_GJR8(OP, 0) RD_GJR8(OP, 1) RD_GJR8(OP, 2) RD_GJR8(OP, 3) RD_GJR8(OP, 4) RD_GJR8(OP, 5)     \
+    RD_GJR8(OP, 6) RD_GJR8(OP, 7) "s_nop 1"
+template <int KK, typename T>
+__device__ __forceinline__ void fused_gj_real8_k(T (&a)[8], T f) {
+    RD_ASM2(T, RD_GJR8_BODY,
+            : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]), "+v"(a[6]),
+              "+v"(a[7])
+            : "v"(f), "n"(KK));
+}
+#undef RD_GJR8_BODY
+#undef RD_GJR8
+
 /* Gauss-Jordan elimination step with pivot lane KK (complex), for every
  * column j, with (ur, ui) the pivot row's entry of column j:
  *   ar[j] = (ar[j] + ui fi) - ur fr,   ai[j] = (ai[j] - ur fi) - ui fr.
@@ -179,20 +230,58 @@ __device__ __forceinline__ void fused_gj_cplx_k(T (&ar)[16], T (&ai)[16], T fr, 
 #undef RD_GJC
 #undef RD_GJD
 
-/* Run-time pivot lane (a constant after the caller's loop is unrolled). */
-template <typename T>
-__device__ __forceinline__ void fused_gj_real(T (&a)[16], T f, int kk) {
+/* The same step for the 8-column engine (m <= 8); four sweeps of eight, so
+ * a register written in one sweep is read through DPP eight or more
+ * instructions later. */
+#define RD_GJA8(OP, R, I) OP " %" #R ", %" #I ", %17 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n\t"
+#define RD_GJB8(OP, R, I) OP " %" #I ", %" #R ", -%17 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n\t"
+#define RD_GJC8(OP, R, I) OP " %" #R ", %" #R ", -%16 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n\t"
+#define RD_GJD8(OP, R, I) OP " %" #I ", %" #I ", -%16 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n\t"
+#define RD_SWEEP8(S, OP) \
+    S(OP, 0, 8) S(OP, 1, 9) S(OP, 2, 10) S(OP, 3, 11) S(OP, 4, 12) S(OP, 5, 13) S(OP, 6, 14) S(OP, 7, 15)
+#define RD_GJC8_BODY(OP)                                                                          \
+    "s_nop 1\n\t" RD_SWEEP8(RD_GJA8, OP) RD_SWEEP8(RD_GJB8, OP) RD_SWEEP8(RD_GJC8, OP)           \
+    RD_SWEEP8(RD_GJD8, OP) "s_nop 1"
+template <int KK, typename T>
+__device__ __forceinline__ void fused_gj_cplx8_k(T (&ar)[8], T (&ai)[8], T fr, T fi) {
+    RD_ASM2(T, RD_GJC8_BODY,
+            : "+v"(ar[0]), "+v"(ar[1]), "+v"(ar[2]), "+v"(ar[3]), "+v"(ar[4]), "+v"(ar[5]),
+              "+v"(ar[6]), "+v"(ar[7]), "+v"(ai[0]), "+v"(ai[1]), "+v"(ai[2]), "+v"(ai[3]),
+              "+v"(ai[4]), "+v"(ai[5]), "+v"(ai[6]), "+v"(ai[7])
+            : "v"(fr), "v"(fi), "n"(KK));
+}
+#undef RD_GJC8_BODY
+#undef RD_SWEEP8
+#undef RD_GJA8
+#undef RD_GJB8
+#undef RD_GJC8
+#undef RD_GJD8
+
+/* Run-time pivot lane (a constant after the caller's loop is unrolled);
+ * NC: columns of the engine (16, or 8 for m <= 8). */
+template <int NC, typename T>
+__device__ __forceinline__ void fused_gj_real(T (&a)[NC], T f, int kk) {
+    static_assert(NC == 8 || NC == 16, "8 or 16 columns");
     switch (kk) {
-#define RD_C(K) case K: fused_gj_real_k<K>(a, f); break;
+#define RD_C(K)                                                                                   \
+    case K:                                                                                       \
+        if constexpr (NC == 16) fused_gj_real_k<K>(a, f);                                         \
+        else if constexpr (K < 8) fused_gj_real8_k<K>(a, f);                                      \
+        break;
         RD_C(0) RD_C(1) RD_C(2) RD_C(3) RD_C(4) RD_C(5) RD_C(6) RD_C(7)
         RD_C(8) RD_C(9) RD_C(10) RD_C(11) RD_C(12) RD_C(13) RD_C(14) RD_C(15)
 #undef RD_C
     }
 }
-template <typename T>
-__device__ __forceinline__ void fused_gj_cplx(T (&ar)[16], T (&ai)[16], T fr, T fi, int kk) {
+template <int NC, typename T>
+__device__ __forceinline__ void fused_gj_cplx(T (&ar)[NC], T (&ai)[NC], T fr, T fi, int kk) {
+    static_assert(NC == 8 || NC == 16, "8 or 16 columns");
     switch (kk) {
-#define RD_C(K) case K: fused_gj_cplx_k<K>(ar, ai, fr, fi); break;
+#define RD_C(K)                                                                                   \
+    case K:                                                                                       \
+        if constexpr (NC == 16) fused_gj_cplx_k<K>(ar, ai, fr, fi);                               \
+        else if constexpr (K < 8) fused_gj_cplx8_k<K>(ar, ai, fr, fi);                            \
+        break;
         RD_C(0) RD_C(1) RD_C(2) RD_C(3) RD_C(4) RD_C(5) RD_C(6) RD_C(7)
         RD_C(8) RD_C(9) RD_C(10) RD_C(11) RD_C(12) RD_C(13) RD_C(14) RD_C(15)
 #undef RD_C

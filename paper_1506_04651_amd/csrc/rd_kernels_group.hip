@@ -71,7 +71,7 @@ __device__ __forceinline__ void advance_group(Cell& cell, const StepParams& P) {
     if (cell.phase == PH_START) cell.template start<FIXED>(P);
 }
 
-template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool FUSE>
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool FUSE, int NC>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_group_onelaunch(LaunchArgs a, int m) {
     __shared__ double tab[GroupTable::DOUBLES];
@@ -80,7 +80,7 @@ k_group_onelaunch(LaunchArgs a, int m) {
     load_table<Model>(tab, a.params, m, BLOCK);
     const int64_t c = (int64_t)blockIdx.x * (BLOCK / kGroup) + threadIdx.x / kGroup;
     if (c >= a.n) return;
-    GroupCell<Model, LT, FUSE> cell;
+    GroupCell<Model, LT, FUSE, NC> cell;
     init_cell(cell, tab, m);
     cell.load(sP, a.states, a.n, c, a.hcell);
     while (cell.phase != PH_IDLE) advance_group<FIXED, FSMIN>(cell, sP);
@@ -88,14 +88,14 @@ k_group_onelaunch(LaunchArgs a, int m) {
     if (cell.status != ST_OK && cell.q == 0) atomicAdd(a.nfail, 1ull);
 }
 
-template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool FUSE>
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool FUSE, int NC>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_group_persistent(LaunchArgs a, int m) {
     __shared__ double tab[GroupTable::DOUBLES];
     __shared__ StepParams sP;
     stage_params(sP, a.P);
     load_table<Model>(tab, a.params, m, BLOCK);
-    GroupCell<Model, LT, FUSE> cell;
+    GroupCell<Model, LT, FUSE, NC> cell;
     init_cell(cell, tab, m);
     int64_t c = -1;
     bool alive = true;
@@ -144,36 +144,41 @@ k_group_persistent(LaunchArgs a, int m) {
 }
 
 /* the species count travels in StepParams::m */
-template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool FUSE>
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool FUSE, int NC>
 hipError_t launch_group_one(const LaunchArgs& a, int grid, hipStream_t s) {
     constexpr int cells = BLOCK / kGroup;
     if (grid <= 0) grid = (int)((a.n + cells - 1) / cells);
-    hipLaunchKernelGGL((k_group_onelaunch<Model, LT, FIXED, BLOCK, WPE, FSMIN, FUSE>), dim3(grid),
+    hipLaunchKernelGGL((k_group_onelaunch<Model, LT, FIXED, BLOCK, WPE, FSMIN, FUSE, NC>), dim3(grid),
                        dim3(BLOCK), 0, s, a, (int)a.P.m);
     return hipGetLastError();
 }
 
-template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool FUSE>
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool FUSE, int NC>
 hipError_t launch_group_pers(const LaunchArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_group_persistent<Model, LT, FIXED, BLOCK, WPE, FSMIN, FUSE>), dim3(grid),
+    hipLaunchKernelGGL((k_group_persistent<Model, LT, FIXED, BLOCK, WPE, FSMIN, FUSE, NC>), dim3(grid),
                        dim3(BLOCK), 0, s, a, (int)a.P.m);
     return hipGetLastError();
 }
 
 /* FUSE: broadcasts fused into the multiply-adds (rd_group_fused.h), in FP64
- * and, for the mixed kernels' factors and solves, in FP32. */
+ * and, for the mixed kernels' factors and solves, in FP32.  NC: columns per
+ * lane; the 8-column kernels are registered under m = 8 and serve m = 5..8,
+ * the 16-column ones under m = 16 for m = 9..16. */
+#define RD_GONE_X(KIND, MODEL, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, NC, NAME)                    \
+    {KIND, 0, NC, PREC, 1, FIXED, VAR, BLOCK, BLOCK / kGroup, NAME,                                 \
+     &launch_group_one<MODEL, LT, FIXED, BLOCK, WPE, FS, true, NC>,                              \
+     (const void*)&k_group_onelaunch<MODEL, LT, FIXED, BLOCK, WPE, FS, true, NC>}
+#define RD_GPERS_X(KIND, MODEL, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, FUSE, NC, NAME)             \
+    {KIND, 0, NC, PREC, 0, FIXED, VAR, BLOCK, BLOCK / kGroup, NAME,                                 \
+     &launch_group_pers<MODEL, LT, FIXED, BLOCK, WPE, FS, FUSE, NC>,                             \
+     (const void*)&k_group_persistent<MODEL, LT, FIXED, BLOCK, WPE, FS, FUSE, NC>}
 #define RD_GONE(KIND, MODEL, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, NAME)                          \
-    {KIND, 0, 16, PREC, 1, FIXED, VAR, BLOCK, BLOCK / kGroup, NAME,                                 \
-     &launch_group_one<MODEL, LT, FIXED, BLOCK, WPE, FS, true>,                                  \
-     (const void*)&k_group_onelaunch<MODEL, LT, FIXED, BLOCK, WPE, FS, true>}
-#define RD_GPERS_X(KIND, MODEL, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, FUSE, NAME)                 \
-    {KIND, 0, 16, PREC, 0, FIXED, VAR, BLOCK, BLOCK / kGroup, NAME,                                 \
-     &launch_group_pers<MODEL, LT, FIXED, BLOCK, WPE, FS, FUSE>,                                 \
-     (const void*)&k_group_persistent<MODEL, LT, FIXED, BLOCK, WPE, FS, FUSE>}
+    RD_GONE_X(KIND, MODEL, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, 16, NAME)
 #define RD_GPERS(KIND, MODEL, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, NAME)                         \
-    RD_GPERS_X(KIND, MODEL, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, true, NAME)
+    RD_GPERS_X(KIND, MODEL, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, true, 16, NAME)
+#define RD_GPERS8(KIND, MODEL, PREC, LT, VAR, WPE, FS, NAME)                                      \
+    RD_GPERS_X(KIND, MODEL, PREC, LT, false, VAR, 256, WPE, FS, true, 8, NAME)
 
-/* m is marked 16 in the table: these kernels serve every 5 <= m <= 16 */
 static const KernelEntry g_group_table[] = {
     RD_GONE(2, GroupKinetics, 0, double, false, 1, 256, 1, 1, "kinetics.g16.fp64.onelaunch.b256"),
     RD_GONE(2, GroupKinetics, 1, float, false, 1, 256, 1, 1, "kinetics.g16.mixed.onelaunch.b256"),
@@ -188,24 +193,50 @@ static const KernelEntry g_group_table[] = {
     RD_GPERS(2, GroupKinetics, 0, double, false, 5, 256, 3, 2, "kinetics.g16.fp64.persistent.b256.w3.fs2"),
     RD_GPERS(2, GroupKinetics, 1, float, false, 5, 256, 3, 2, "kinetics.g16.mixed.persistent.b256.w3.fs2"),
     /* the same kernel as variant 1 with separate DPP moves and FMAs */
-    RD_GPERS_X(2, GroupKinetics, 0, double, false, 6, 256, 2, 4, false,
+    RD_GPERS_X(2, GroupKinetics, 0, double, false, 6, 256, 2, 4, false, 16,
                "kinetics.g16.fp64.persistent.b256.w2.fs4.unfused"),
     RD_GPERS(2, GroupKinetics, 1, float, false, 6, 256, 3, 3, "kinetics.g16.mixed.persistent.b256.w3.fs3"),
     RD_GPERS(2, GroupKinetics, 0, double, false, 7, 256, 2, 3, "kinetics.g16.fp64.persistent.b256.w2.fs3"),
     RD_GPERS(2, GroupKinetics, 1, float, false, 7, 256, 2, 3, "kinetics.g16.mixed.persistent.b256.w2.fs3"),
     RD_GPERS(2, GroupKinetics, 1, float, false, 8, 128, 3, 4, "kinetics.g16.mixed.persistent.b128.w3.fs4"),
-    RD_GPERS_X(2, GroupKinetics, 1, float, false, 9, 256, 3, 4, false,
+    RD_GPERS_X(2, GroupKinetics, 1, float, false, 9, 256, 3, 4, false, 16,
                "kinetics.g16.mixed.persistent.b256.w3.fs4.unfused"),
     RD_GONE(2, GroupKinetics, 0, double, true, 1, 256, 1, 1, "kinetics.g16.fp64.onelaunch.fixed"),
     RD_GPERS(2, GroupKinetics, 0, double, true, 1, 256, 1, 1, "kinetics.g16.fp64.persistent.fixed"),
+    /* 8 columns (m = 5..8) */
+    RD_GONE_X(2, GroupKinetics, 0, double, false, 1, 256, 1, 1, 8, "kinetics.g16c8.fp64.onelaunch.b256"),
+    RD_GONE_X(2, GroupKinetics, 1, float, false, 1, 256, 1, 1, 8, "kinetics.g16c8.mixed.onelaunch.b256"),
+    RD_GPERS8(2, GroupKinetics, 0, double, 1, 3, 4, "kinetics.g16c8.fp64.persistent.b256.w3.fs4"),
+    RD_GPERS8(2, GroupKinetics, 1, float, 1, 4, 4, "kinetics.g16c8.mixed.persistent.b256.w4.fs4"),
+    RD_GPERS8(2, GroupKinetics, 0, double, 2, 2, 4, "kinetics.g16c8.fp64.persistent.b256.w2.fs4"),
+    RD_GPERS8(2, GroupKinetics, 1, float, 2, 3, 4, "kinetics.g16c8.mixed.persistent.b256.w3.fs4"),
+    RD_GPERS8(2, GroupKinetics, 0, double, 3, 4, 4, "kinetics.g16c8.fp64.persistent.b256.w4.fs4"),
+    RD_GPERS8(2, GroupKinetics, 1, float, 3, 3, 2, "kinetics.g16c8.mixed.persistent.b256.w3.fs2"),
+    RD_GPERS8(2, GroupKinetics, 0, double, 4, 3, 2, "kinetics.g16c8.fp64.persistent.b256.w3.fs2"),
+    RD_GPERS_X(2, GroupKinetics, 0, double, false, 5, 256, 3, 4, false, 8,
+               "kinetics.g16c8.fp64.persistent.b256.w3.fs4.unfused"),
+    RD_GPERS_X(2, GroupKinetics, 1, float, false, 4, 256, 3, 4, false, 8,
+               "kinetics.g16c8.mixed.persistent.b256.w3.fs4.unfused"),
+    RD_GONE_X(2, GroupKinetics, 0, double, true, 1, 256, 1, 1, 8, "kinetics.g16c8.fp64.onelaunch.fixed"),
+    RD_GPERS_X(2, GroupKinetics, 0, double, true, 1, 256, 1, 1, true, 8,
+               "kinetics.g16c8.fp64.persistent.fixed"),
     RD_GONE(4, GroupLinear, 0, double, false, 1, 256, 1, 1, "linear.g16.fp64.onelaunch.b256"),
     RD_GONE(4, GroupLinear, 1, float, false, 1, 256, 1, 1, "linear.g16.mixed.onelaunch.b256"),
     RD_GPERS(4, GroupLinear, 0, double, false, 1, 256, 2, 4, "linear.g16.fp64.persistent.b256.w2.fs4"),
     RD_GPERS(4, GroupLinear, 1, float, false, 1, 256, 3, 4, "linear.g16.mixed.persistent.b256.w3.fs4"),
-    RD_GPERS_X(4, GroupLinear, 0, double, false, 2, 256, 2, 4, false,
+    RD_GPERS_X(4, GroupLinear, 0, double, false, 2, 256, 2, 4, false, 16,
                "linear.g16.fp64.persistent.b256.w2.fs4.unfused"),
     RD_GONE(4, GroupLinear, 0, double, true, 1, 256, 1, 1, "linear.g16.fp64.onelaunch.fixed"),
     RD_GPERS(4, GroupLinear, 0, double, true, 1, 256, 1, 1, "linear.g16.fp64.persistent.fixed"),
+    RD_GONE_X(4, GroupLinear, 0, double, false, 1, 256, 1, 1, 8, "linear.g16c8.fp64.onelaunch.b256"),
+    RD_GONE_X(4, GroupLinear, 1, float, false, 1, 256, 1, 1, 8, "linear.g16c8.mixed.onelaunch.b256"),
+    RD_GPERS8(4, GroupLinear, 0, double, 1, 3, 4, "linear.g16c8.fp64.persistent.b256.w3.fs4"),
+    RD_GPERS8(4, GroupLinear, 1, float, 1, 4, 4, "linear.g16c8.mixed.persistent.b256.w4.fs4"),
+    RD_GPERS_X(4, GroupLinear, 0, double, false, 2, 256, 3, 4, false, 8,
+               "linear.g16c8.fp64.persistent.b256.w3.fs4.unfused"),
+    RD_GONE_X(4, GroupLinear, 0, double, true, 1, 256, 1, 1, 8, "linear.g16c8.fp64.onelaunch.fixed"),
+    RD_GPERS_X(4, GroupLinear, 0, double, true, 1, 256, 1, 1, true, 8,
+               "linear.g16c8.fp64.persistent.fixed"),
 };
 
 const KernelEntry* group_kernel_table(int* count) {

@@ -59,6 +59,23 @@ def test_variants_listed(lib):
         rd.set_default_variant(rd.OREGONATOR, 3, rd.FP64, rd.PERSISTENT, 999)
 
 
+def test_group_variant_sets(lib):
+    """Kinetics and linear models with 5..8 species share the 8-column kernel
+    set, with 9..16 the 16-column set; ids and names agree across each set."""
+    import paper_1506_04651_amd as rd
+    for kind in (rd.KINETICS, rd.LINEAR):
+        for prec in (rd.FP64, rd.MIXED):
+            n8 = [rd.variant_count(kind, m, prec, rd.PERSISTENT) for m in (5, 6, 7, 8)]
+            n16 = [rd.variant_count(kind, m, prec, rd.PERSISTENT) for m in (9, 12, 16)]
+            assert len(set(n8)) == 1 and n8[0] >= 1 and len(set(n16)) == 1 and n16[0] >= 1
+            assert all(".g16c8." in rd.variant_name(kind, 6, prec, rd.PERSISTENT, v)
+                       for v in range(1, n8[0] + 1))
+            assert all(".g16." in rd.variant_name(kind, 10, prec, rd.PERSISTENT, v)
+                       for v in range(1, n16[0] + 1))
+            assert rd.variant_name(kind, 7, prec, rd.ONE_LAUNCH, 1).startswith(
+                ("kinetics.g16c8", "linear.g16c8"))
+
+
 def test_validation_before_device_use(lib):
     """Invalid calls return RD_EINVAL from host-side checks; empty batches
     return 0 without touching a device."""

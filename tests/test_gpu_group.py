@@ -65,7 +65,7 @@ def test_kinetics16_full_batch_sampled(rd, orc):
     assert np.all(s1 <= s0 * (1 + 10 * w.rtol))
 
 
-@pytest.mark.parametrize("m", [5, 7, 12, 16])
+@pytest.mark.parametrize("m", [5, 7, 8, 9, 12, 16])
 def test_kinetics_other_m(rd, orc, m):
     w = W.kinetics16(n=384, m=m, seed=100 + m)
     say("kinetics m", m)
@@ -168,18 +168,19 @@ def test_group_claim_order_other_m(rd, orc, m):
     assert cell.max() <= 10 * w.rtol
 
 
-@pytest.mark.parametrize("m", [16, 7])
+@pytest.mark.parametrize("m", [16, 8, 7])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_group_variants_fused_and_unfused_identical(rd, m, precision):
     """Every persistent variant of the 16-lane engine, including the ones
     whose row broadcasts are separate DPP moves instead of fused DPP
-    multiply-adds, gives the same states and counters (m = 16 takes the fused
-    matrix-vector solves, m = 7 the loops)."""
+    multiply-adds, gives the same states and counters (m = 16: 16-column
+    kernels with the fused matrix-vector solves; m = 7: 8-column kernels,
+    solves as loops)."""
     w = W.kinetics16(n=6000, m=m, seed=21 + m)
     a, sa, _ = run_gpu(rd, w, precision=precision)
     names = []
-    for v in range(1, rd.variant_count(rd.KINETICS, 16, precision, 0) + 1):
-        names.append(rd.variant_name(rd.KINETICS, 16, precision, 0, v))
+    for v in range(1, rd.variant_count(rd.KINETICS, m, precision, 0) + 1):
+        names.append(rd.variant_name(rd.KINETICS, m, precision, 0, v))
         d, sd, _ = run_gpu(rd, w, precision=precision, variant=v)
         assert np.array_equal(a, d) and np.array_equal(sa, sd), names[-1]
     assert any(n.endswith(".unfused") for n in names)
