@@ -2,9 +2,13 @@
 
 The library compiles several variants of each kernel: work-group size, the
 waves-per-SIMD target the register allocator is held to (higher occupancy at
-the price of spills), and where the per-cell matrices live (registers or
-LDS).  Which one is fastest depends on the model, m, the precision and on the
-distribution of per-cell cost in the batch, so the choice is measured: every
+the price of spills), how many lanes must wait before the step-end block runs
+(batching), whether the step parameters are staged in LDS or kept in scalar
+registers, the wave issue priorities of the persistent schedule and, for the
+16-lane kernels, fused or separate broadcasts.  Every variant computes the same
+per-cell arithmetic.  Which one is fastest depends on the model, m, the
+precision and on the distribution of per-cell cost in the batch, so the choice
+is measured: every
 variant is timed on the caller's own batch (HIP events on the launch stream),
 the fastest becomes the library default for (kind, m, precision, schedule),
 and the result is cached in a JSON file keyed by device name.
