@@ -16,7 +16,9 @@ direction):
 - details d_{j,k} = u_{j,k} - prediction (eq. for the detail, §2.2);
 - thresholds eps_j = 2^{(d/2)(j-J)} eps (§2.2) in the L2 norm over species,
   each species scaled by s_i: a node's children are kept when
-  (1/m) sum_i (d_i / s_i)^2 >= eps_j^2 for some child;
+  (1/m) sum_i (d_i / s_i)^2 >= eps_j^2 for some child (compression); with
+  refinement on, a node whose own detail is significant gets children too
+  (§2.2: nodes whose details exceed eps_j are refined; §3.1, refinement);
 - grading (§2.2, graded tree): whenever a node has children, the 3^d
   neighbours of that node must exist (their parents get children too),
   enforced from the finest level to the root;
@@ -24,7 +26,13 @@ direction):
   abscissa (bits of x_1, x_2[, x_3] interleaved, most significant first)
   left-aligned in the top 48 bits, the level in the next 4 bits, 12 free bits;
 - reconstruction: tree values by projection of the leaves, then every node
-  outside the tree predicted level by level from the coarser level.
+  outside the tree predicted level by level from the coarser level;
+- adaptation of a leaf set to its values (§3.1, refinement and coarsening):
+  the levels of the reconstruction (tree values, predicted values elsewhere),
+  their details, the flags and grading above, and the leaf set of the result:
+  children created by refinement carry predicted values, nodes whose
+  children are no longer significant become leaves with their projected
+  values.
 
 Storage convention (both here and in the tests): every level in Morton order,
 index k = interleave(x, y[, z]) with x the most significant bit of each group,
@@ -159,14 +167,17 @@ def detail_norm2(dj, scale):
     return acc * (1.0 / m)
 
 
-def refine_flags(levels, dets, d, J, eps, scale):
-    """R_j[k] (j = 0..J-1): node (j, k) has children in the graded tree."""
+def refine_flags(levels, dets, d, J, eps, scale, refine=False):
+    """R_j[k] (j = 0..J-1): node (j, k) has children in the graded tree.
+    refine: a node of level < J with a significant detail has children."""
     nc = 1 << d
     R = [np.zeros(levels[j].shape[1], dtype=bool) for j in range(J)]
     for j in range(1, J + 1):
         eps_j2 = (eps * eps) * np.ldexp(1.0, d * (j - J))   # eps_j^2 = 2^(d (j-J)) eps^2
         sig = detail_norm2(dets[j], scale) >= eps_j2
         R[j - 1] |= sig.reshape(-1, nc).any(axis=1)
+        if refine and j < J:
+            R[j] |= sig
     # grading, finest to coarsest
     for j in range(J - 1, 0, -1):
         ks = np.nonzero(R[j])[0]
@@ -184,14 +195,20 @@ def refine_flags(levels, dets, d, J, eps, scale):
     return R
 
 
-def leaves(U_fine_morton, d, J, eps, scale=None):
+def leaves(U_fine_morton, d, J, eps, scale=None, refine=False):
     """Leaf set of the graded tree: (keys uint64 in Morton order, values
     [m, n_leaves], per-level leaf counts [J+1])."""
     m = U_fine_morton.shape[0]
     scale = np.ones(m) if scale is None else np.asarray(scale, dtype=np.float64)
     levels = project(U_fine_morton, d, J)
     dets = details(levels, d, J)
-    R = refine_flags(levels, dets, d, J, eps, scale) if J >= 1 else []
+    R = refine_flags(levels, dets, d, J, eps, scale, refine) if J >= 1 else []
+    return leaf_set(levels, R, d, J)
+
+
+def leaf_set(levels, R, d, J):
+    """Keys (Morton order), values and per-level counts of the leaves of the
+    tree given by the flags R over the level arrays."""
     keys, vals, lev = [], [], []
     counts = np.zeros(J + 1, dtype=np.int64)
     for j in range(J + 1):
@@ -238,6 +255,12 @@ def key_index(keys, d):
 def reconstruct(keys, vals, d, J):
     """Fine-level field (Morton order) from a leaf set: tree values by
     projection of the leaves, nodes outside the tree predicted."""
+    return tree_levels(keys, vals, d, J)[J]
+
+
+def tree_levels(keys, vals, d, J):
+    """Every level of the reconstruction of a leaf set: tree nodes valued by
+    projection of the leaves, the others predicted from the level above."""
     m = vals.shape[0]
     lev = key_level(keys)
     idx = key_index(keys, d)
@@ -260,9 +283,21 @@ def reconstruct(keys, vals, d, J):
             s = s + tree_val[j][:, ch[:, c]]
         tree_val[j - 1][:, par] = s * (1.0 / nc)
         in_tree[j - 1][par] = True
-    V = tree_val[0].copy()
+    V = [tree_val[0].copy()]
     for j in range(1, J + 1):
         k = np.arange(1 << (d * j))
-        pred = predict(V, d, j - 1, k)
-        V = np.where(in_tree[j][None, :], tree_val[j], pred)
+        pred = predict(V[j - 1], d, j - 1, k)
+        V.append(np.where(in_tree[j][None, :], tree_val[j], pred))
     return V
+
+
+def adapt(keys, vals, d, J, eps, scale=None, refine=True):
+    """Leaf set adapted to the values of a leaf set: details on the levels of
+    its reconstruction (zero at predicted nodes), flags with or without
+    refinement, grading, leaves."""
+    m = vals.shape[0]
+    scale = np.ones(m) if scale is None else np.asarray(scale, dtype=np.float64)
+    levels = tree_levels(keys, vals, d, J)
+    dets = details(levels, d, J)
+    R = refine_flags(levels, dets, d, J, eps, scale, refine)
+    return leaf_set(levels, R, d, J)

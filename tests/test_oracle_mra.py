@@ -165,3 +165,93 @@ def test_reconstruction(d, J):
             assert np.allclose(lv[j][:, idx[sel]], vals[:, sel], rtol=0, atol=1e-12)
     assert all(a >= b for a, b in zip(errs, errs[1:]))
     assert errs[-1] <= 20 * 1e-4
+
+
+def tree_nodes(keys, d):
+    """(level, index) of every node of the tree a leaf set spans."""
+    nodes = set()
+    for lv, k in zip(M.key_level(keys), M.key_index(keys, d)):
+        lv, k = int(lv), int(k)
+        while True:
+            nodes.add((lv, k))
+            if lv == 0:
+                break
+            lv, k = lv - 1, k >> d
+    return nodes
+
+
+@pytest.mark.parametrize("d,J,eps", [(2, 6, 1e-3), (3, 4, 1e-3)])
+def test_adapt_without_refinement_is_idempotent(d, J, eps):
+    """A leaf set built from a field is the fixed point of adaptation without
+    refinement: the tree values are the same averages, the nodes outside the
+    tree have zero details, so flags, grading and leaves are unchanged."""
+    U = front_field(d, J)
+    k0, v0, c0 = M.leaves(U, d, J, eps)
+    k1, v1, c1 = M.adapt(k0, v0, d, J, eps, refine=False)
+    assert np.array_equal(k0, k1) and np.array_equal(v0, v1) and np.array_equal(c0, c1)
+
+
+@pytest.mark.parametrize("d,J,eps", [(2, 6, 1e-3), (2, 7, 1e-2), (3, 4, 1e-3)])
+def test_adapt_with_refinement(d, J, eps):
+    """Refinement: every node below the finest level whose detail is
+    significant has children; the adapted tree contains the old one; new
+    leaves carry the values predicted from their parents' level; the result
+    tiles the domain and is graded; the fine field it reconstructs is the old
+    one up to rounding."""
+    U = front_field(d, J)
+    scale = np.ones(U.shape[0])
+    k0, v0, _ = M.leaves(U, d, J, eps)
+    k1, v1, _ = M.adapt(k0, v0, d, J, eps, refine=True)
+    old, new = tree_nodes(k0, d), tree_nodes(k1, d)
+    assert old <= new and len(new) > len(old)
+    lv1, ix1 = M.key_level(k1), M.key_index(k1, d)
+    start = ix1 << (d * (J - lv1))
+    end = (ix1 + 1) << (d * (J - lv1))
+    assert start[0] == 0 and end[-1] == (1 << (d * J)) and np.array_equal(start[1:], end[:-1])
+    levels = M.tree_levels(k0, v0, d, J)
+    dets = M.details(levels, d, J)
+    leafset = set(zip(lv1.tolist(), ix1.tolist()))
+    for j in range(1, J):
+        sig = np.nonzero(M.detail_norm2(dets[j], scale) >= eps * eps * 2.0 ** (d * (j - J)))[0]
+        assert not any((j, int(k)) in leafset for k in sig)       # significant nodes are refined
+    for j in range(1, J + 1):                                     # new leaves: predicted values
+        sel = np.nonzero(lv1 == j)[0]
+        fresh = [i for i in sel if (j, int(ix1[i])) not in old]
+        if fresh:
+            pred = M.predict(levels[j - 1], d, j - 1, ix1[fresh])
+            assert np.array_equal(v1[:, fresh], pred)
+    R = M.refine_flags(levels, dets, d, J, eps, scale, refine=True)
+    for j in range(1, J):                                         # graded
+        ks = np.nonzero(R[j])[0]
+        co = M.deinterleave(ks, d, j)
+        for off in np.ndindex(*([3] * d)):
+            nb = [co[a] + off[a] - 1 for a in range(d)]
+            ok = np.ones(ks.size, dtype=bool)
+            for a in range(d):
+                ok &= (nb[a] >= 0) & (nb[a] < (1 << j))
+            assert np.all(R[j - 1][M.interleave(tuple(c[ok] for c in nb), j) >> d])
+    assert np.allclose(M.reconstruct(k1, v1, d, J), M.reconstruct(k0, v0, d, J), rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("refine", [False, True])
+def test_adapt_coarsens_a_flat_leaf_set(refine):
+    """All leaf values equal: every detail vanishes and the tree collapses to
+    the root, which holds that value."""
+    d, J = 2, 6
+    k0, v0, _ = M.leaves(front_field(d, J), d, J, 1e-3)
+    flat = np.full_like(v0, 0.25)
+    k1, v1, c1 = M.adapt(k0, flat, d, J, 1e-3, refine=refine)
+    assert k1.size == 1 and M.key_level(k1)[0] == 0 and np.all(v1 == 0.25) and c1[0] == 1
+
+
+def test_leaves_with_refinement_contain_the_plain_tree():
+    d, J, eps = 2, 7, 3e-3
+    U = front_field(d, J)
+    kp, _, _ = M.leaves(U, d, J, eps)
+    kr, vr, _ = M.leaves(U, d, J, eps, refine=True)
+    assert tree_nodes(kp, d) < tree_nodes(kr, d)
+    lev, idx = M.key_level(kr), M.key_index(kr, d)
+    levels = M.project(U, d, J)
+    for j in np.unique(lev):
+        sel = lev == j
+        assert np.array_equal(vr[:, sel], levels[j][:, idx[sel]])
