@@ -211,6 +211,10 @@ typedef struct {
                              eps_j = 2^((dim/2)(j - J)) eps                        */
     const double* scale;  /* HOST, m per-species detail scales s_i > 0, or null
                              (all 1)                                              */
+    int32_t refine;       /* 0: compression only (a node has children when one of
+                             them is significant); 1: also refine every node below
+                             the finest level whose own detail is significant
+                             (§2.2; children with predicted values)               */
 } rd_mra_params;
 
 /*
@@ -219,8 +223,9 @@ typedef struct {
  * prediction, the prediction being the third-order centred interpolation
  * (l = 1) applied as a tensor product one direction at a time, with even
  * reflection at the domain edge; a node gets children when one of them has
- * (1/m) sum_i (d_i / s_i)^2 >= eps_j^2; grading: a node with children makes
- * the parents of its 3^dim neighbours get children (finest to coarsest).
+ * (1/m) sum_i (d_i / s_i)^2 >= eps_j^2 (and, with params->refine, when its
+ * own detail does); grading: a node with children makes the parents of its
+ * 3^dim neighbours get children (finest to coarsest).
  * fine: DEVICE [m][2^(dim J)] float64, x fastest (cell x + N (y + N z)).
  * Output in Morton order of the leaves: keys DEVICE [n_leaves] uint64 (the
  * level-j Morton index, bits of x, y[, z] interleaved with x most significant,
@@ -245,6 +250,23 @@ int64_t rd_mra_leaves(const double* fine, int32_t m, const rd_mra_params* params
 int64_t rd_mra_reconstruct(const uint64_t* keys, const double* values, int64_t n_leaves,
                            int32_t m, const rd_mra_params* params, double* fine,
                            void* hip_stream);
+
+/*
+ * Adaptation of a leaf set to its current values, for instance after a
+ * reaction step (refinement and coarsening, §3.1; thresholds §2.2): the
+ * levels of its reconstruction (tree nodes by projection of the leaves, the
+ * other nodes predicted, so their details are zero), then the details, flags
+ * (params->refine as in rd_mra_leaves), grading and leaves of rd_mra_leaves.
+ * New leaves carry predicted values; nodes whose children are no longer
+ * significant become leaves holding their projected values.  keys, values:
+ * the input leaf set (DEVICE, as written by rd_mra_leaves; keys that do not
+ * name a node are ignored).  out_keys, out_values, capacity, level_counts and
+ * the return value as in rd_mra_leaves; the outputs must not overlap the
+ * inputs.  Synchronous.
+ */
+int64_t rd_mra_adapt(const uint64_t* keys, const double* values, int64_t n_leaves, int32_t m,
+                     const rd_mra_params* params, uint64_t* out_keys, double* out_values,
+                     int64_t capacity, int64_t* level_counts, void* hip_stream);
 
 /* ------------------------------------------------------------------------ */
 /* Serving: a session admits reaction-step requests into an HBM arena of a    */

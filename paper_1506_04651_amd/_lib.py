@@ -44,7 +44,7 @@ class RdGrid(ctypes.Structure):
 
 class RdMraParams(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("levels", ctypes.c_int32), ("eps", ctypes.c_double),
-                ("scale", ctypes.POINTER(ctypes.c_double))]
+                ("scale", ctypes.POINTER(ctypes.c_double)), ("refine", ctypes.c_int32)]
 
 
 class RdRequestInfo(ctypes.Structure):
@@ -92,6 +92,10 @@ SIGNATURES = {
     "rd_mra_reconstruct": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                             ctypes.c_int32, ctypes.POINTER(RdMraParams),
                                             ctypes.c_void_p, ctypes.c_void_p]),
+    "rd_mra_adapt": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_int32, ctypes.POINTER(RdMraParams),
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
     "rd_strang_step": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(RdGrid),
                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                         ctypes.POINTER(RdModel), ctypes.POINTER(RdOptions),

@@ -149,27 +149,29 @@ def strang_step(states, shape, h, diff, dt, rtol, atol, kind, params, *, stats=N
     return _check(r)
 
 
-def _mra_params(dim, levels, eps, scale, m):
+def _mra_params(dim, levels, eps, scale, m, refine=False):
     sc = None if scale is None else np.ascontiguousarray(scale, dtype=np.float64)
     if sc is not None and sc.size != m:
         raise ValueError("scale needs one value per species")
     p = _lib.RdMraParams(int(dim), int(levels), float(eps),
-                         None if sc is None else sc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+                         None if sc is None else sc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                         1 if refine else 0)
     return p, sc
 
 
-def mra_leaves(fine, dim, levels, eps, *, scale=None, stream=None):
+def mra_leaves(fine, dim, levels, eps, *, scale=None, refine=False, stream=None):
     """Leaf set of the graded multiresolution tree of `fine` ([m, 2^(dim levels)]
     float64 CUDA tensor, x fastest).  Returns (keys int64 CUDA tensor holding
     the uint64 node keys in Morton order, values [m, n_leaves] CUDA tensor,
-    per-level leaf counts as a list)."""
+    per-level leaf counts as a list).  refine: nodes with significant details
+    get children too."""
     import torch
     lib = _lib.load()
     _check_states(fine)
     m = int(fine.shape[0])
     if int(fine.shape[1]) != 1 << (dim * levels):
         raise ValueError("fine must hold 2^(dim*levels) cells per species")
-    p, keep = _mra_params(dim, levels, eps, scale, m)
+    p, keep = _mra_params(dim, levels, eps, scale, m, refine)
     sh = _stream_handle(stream)
     n = _check(lib.rd_mra_leaves(ctypes.c_void_p(fine.data_ptr()), m, ctypes.byref(p), None, None, 0,
                                  None, sh))
@@ -200,6 +202,30 @@ def mra_reconstruct(keys, values, dim, levels, *, scale=None, stream=None):
                                   _stream_handle(stream)))
     del keep
     return out
+
+
+def mra_adapt(keys, values, dim, levels, eps, *, scale=None, refine=True, stream=None):
+    """Leaf set adapted to the values of a leaf set (refinement and
+    coarsening): returns (keys, values, per-level counts) as mra_leaves."""
+    import torch
+    lib = _lib.load()
+    _check_states(values)
+    m, n = int(values.shape[0]), int(values.shape[1])
+    if keys.dtype != torch.int64 or not keys.is_cuda or tuple(keys.shape) != (n,):
+        raise ValueError("keys must be an int64 CUDA tensor of n_leaves entries")
+    p, keep = _mra_params(dim, levels, eps, scale, m, refine)
+    sh = _stream_handle(stream)
+    kp, vp = ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(values.data_ptr())
+    nn = _check(lib.rd_mra_adapt(kp, vp, n, m, ctypes.byref(p), None, None, 0, None, sh))
+    okeys = torch.empty(nn, dtype=torch.int64, device=values.device)
+    ovals = torch.empty((m, nn), dtype=torch.float64, device=values.device)
+    counts = (ctypes.c_int64 * (levels + 1))()
+    n2 = _check(lib.rd_mra_adapt(kp, vp, n, m, ctypes.byref(p), ctypes.c_void_p(okeys.data_ptr()),
+                                 ctypes.c_void_p(ovals.data_ptr()), nn, counts, sh))
+    del keep
+    if n2 != nn:
+        raise RuntimeError("leaf count changed between calls")
+    return okeys, ovals, list(counts)
 
 
 def last_kernel_ms() -> float:

@@ -162,9 +162,11 @@ __global__ void k_project(Pyr P, int j) {
     }
 }
 
-/* details of the children of level-(j-1) node p and its refine flag */
+/* details of the children of level-(j-1) node p and its refine flag; with
+ * refine, a significant child below the finest level gets children too */
 template <int D>
-__global__ void k_detail_flags(Pyr P, int j, double eps_j2, const double* __restrict__ scale) {
+__global__ void k_detail_flags(Pyr P, int j, double eps_j2, const double* __restrict__ scale,
+                               int refine) {
     const int jc = j - 1;
     const int64_t np = (int64_t)1 << (D * jc);
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -184,7 +186,9 @@ __global__ void k_detail_flags(Pyr P, int j, double eps_j2, const double* __rest
             const double q = dd / scale[i];
             acc = (i == 0) ? q * q : acc + q * q;
         }
-        sig = sig || (acc * invm >= eps_j2);
+        const bool sc = acc * invm >= eps_j2;
+        sig = sig || sc;
+        if (refine && sc && j < P.J) P.R[P.off[j] + p * NC + c] = 1;
     }
     if (sig) P.R[P.off[jc] + p] = 1;
 }
@@ -417,49 +421,27 @@ static int setup_pyr(const rd_mra_params* p, int32_t m, hipStream_t s, Pyr& P, d
 
 static unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-}  // namespace rd
-
-using namespace rd;
-
-extern "C" {
-
-int64_t rd_mra_leaves(const double* fine, int32_t m, const rd_mra_params* p, uint64_t* keys,
-                      double* values, int64_t capacity, int64_t* level_counts, void* hip_stream) {
-    if (!mra_params_valid(p, m) || !fine || capacity < 0) {
-        set_error("invalid MRA arguments");
-        return RD_EINVAL;
-    }
-    hipStream_t s = (hipStream_t)hip_stream;
-    Pyr P{};
-    double* sc = nullptr;
-    unsigned* bcount = nullptr;
-    unsigned long long* boff = nullptr;
-    int64_t nb = 0;
-    if (int r = setup_pyr(p, m, s, P, &sc, &bcount, &boff, &nb)) return r;
-    std::vector<double> hs(m, 1.0);
-    if (p->scale) hs.assign(p->scale, p->scale + m);
-    const int d = P.d, J = P.J;
-    const int64_t nfine = (int64_t)1 << (d * J);
 #define MRA_TRY(e)                                                                              \
     do {                                                                                        \
         hipError_t e_ = (e);                                                                    \
         if (e_ != hipSuccess) { set_error("%s: %s", #e, hipGetErrorString(e_)); return RD_EDEVICE; } \
     } while (0)
-    MRA_TRY(hipMemcpyAsync(sc, hs.data(), sizeof(double) * m, hipMemcpyHostToDevice, s));
-    MRA_TRY(hipMemsetAsync(P.R, 0, (size_t)P.total, s));
+
+/* flags (details, optional refinement, grading) over the pyramid P.U and the
+ * leaf set they define; P.U holds every level on entry */
+static int64_t flags_and_leaves(Pyr& P, const rd_mra_params* p, hipStream_t s, const double* sc,
+                                unsigned* bcount, unsigned long long* boff, int64_t nb,
+                                uint64_t* keys, double* values, int64_t capacity,
+                                int64_t* level_counts) {
+    const int d = P.d, J = P.J;
     const int B = 256;
-    if (d == 2) hipLaunchKernelGGL(k_to_morton<2>, dim3(blocks_for(nfine, B)), dim3(B), 0, s, fine, P);
-    else hipLaunchKernelGGL(k_to_morton<3>, dim3(blocks_for(nfine, B)), dim3(B), 0, s, fine, P);
-    for (int j = J; j >= 1; --j) {
-        const int64_t np = (int64_t)1 << (d * (j - 1));
-        if (d == 2) hipLaunchKernelGGL(k_project<2>, dim3(blocks_for(np, B)), dim3(B), 0, s, P, j);
-        else hipLaunchKernelGGL(k_project<3>, dim3(blocks_for(np, B)), dim3(B), 0, s, P, j);
-    }
+    MRA_TRY(hipMemsetAsync(P.R, 0, (size_t)P.total, s));
     for (int j = 1; j <= J; ++j) {
         const int64_t np = (int64_t)1 << (d * (j - 1));
         const double e2 = (p->eps * p->eps) * std::ldexp(1.0, d * (j - J));
-        if (d == 2) hipLaunchKernelGGL(k_detail_flags<2>, dim3(blocks_for(np, B)), dim3(B), 0, s, P, j, e2, (const double*)sc);
-        else hipLaunchKernelGGL(k_detail_flags<3>, dim3(blocks_for(np, B)), dim3(B), 0, s, P, j, e2, (const double*)sc);
+        const int rf = p->refine ? 1 : 0;
+        if (d == 2) hipLaunchKernelGGL(k_detail_flags<2>, dim3(blocks_for(np, B)), dim3(B), 0, s, P, j, e2, sc, rf);
+        else hipLaunchKernelGGL(k_detail_flags<3>, dim3(blocks_for(np, B)), dim3(B), 0, s, P, j, e2, sc, rf);
     }
     for (int j = J - 1; j >= 1; --j) {
         const int64_t nj = (int64_t)1 << (d * j);
@@ -490,21 +472,11 @@ int64_t rd_mra_leaves(const double* fine, int32_t m, const rd_mra_params* p, uin
     return nl;
 }
 
-int64_t rd_mra_reconstruct(const uint64_t* keys, const double* values, int64_t n_leaves,
-                           int32_t m, const rd_mra_params* p, double* fine, void* hip_stream) {
-    if (!mra_params_valid(p, m) || !fine || n_leaves < 1 || !keys || !values) {
-        set_error("invalid MRA arguments");
-        return RD_EINVAL;
-    }
-    hipStream_t s = (hipStream_t)hip_stream;
-    Pyr P{};
-    double* sc = nullptr;
-    unsigned* bcount = nullptr;
-    unsigned long long* boff = nullptr;
-    int64_t nb = 0;
-    if (int r = setup_pyr(p, m, s, P, &sc, &bcount, &boff, &nb)) return r;
+/* every level of the reconstruction of a leaf set into P.U: tree nodes by
+ * projection of the leaves, the others predicted from the level above */
+static int tree_levels(Pyr& P, const uint64_t* keys, const double* values, int64_t n_leaves,
+                       hipStream_t s) {
     const int d = P.d, J = P.J;
-    const int64_t nfine = (int64_t)1 << (d * J);
     const int B = 256;
     MRA_TRY(hipMemsetAsync(P.T, 0, (size_t)P.total, s));
     hipLaunchKernelGGL(k_scatter_leaves, dim3(blocks_for(n_leaves, B)), dim3(B), 0, s, P, d, keys,
@@ -519,11 +491,94 @@ int64_t rd_mra_reconstruct(const uint64_t* keys, const double* values, int64_t n
         if (d == 2) hipLaunchKernelGGL(k_fill_down<2>, dim3(blocks_for(nj, B)), dim3(B), 0, s, P, j);
         else hipLaunchKernelGGL(k_fill_down<3>, dim3(blocks_for(nj, B)), dim3(B), 0, s, P, j);
     }
+    MRA_TRY(hipGetLastError());
+    return 0;
+}
+
+static int upload_scale(const rd_mra_params* p, int32_t m, double* sc, hipStream_t s) {
+    std::vector<double> hs(m, 1.0);
+    if (p->scale) hs.assign(p->scale, p->scale + m);
+    MRA_TRY(hipMemcpyAsync(sc, hs.data(), sizeof(double) * m, hipMemcpyHostToDevice, s));
+    /* the host vector is released on return: wait for the copy */
+    MRA_TRY(hipStreamSynchronize(s));
+    return 0;
+}
+
+}  // namespace rd
+
+using namespace rd;
+
+extern "C" {
+
+int64_t rd_mra_leaves(const double* fine, int32_t m, const rd_mra_params* p, uint64_t* keys,
+                      double* values, int64_t capacity, int64_t* level_counts, void* hip_stream) {
+    if (!mra_params_valid(p, m) || !fine || capacity < 0) {
+        set_error("invalid MRA arguments");
+        return RD_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    Pyr P{};
+    double* sc = nullptr;
+    unsigned* bcount = nullptr;
+    unsigned long long* boff = nullptr;
+    int64_t nb = 0;
+    if (int r = setup_pyr(p, m, s, P, &sc, &bcount, &boff, &nb)) return r;
+    if (int r = upload_scale(p, m, sc, s)) return r;
+    const int d = P.d, J = P.J;
+    const int64_t nfine = (int64_t)1 << (d * J);
+    const int B = 256;
+    if (d == 2) hipLaunchKernelGGL(k_to_morton<2>, dim3(blocks_for(nfine, B)), dim3(B), 0, s, fine, P);
+    else hipLaunchKernelGGL(k_to_morton<3>, dim3(blocks_for(nfine, B)), dim3(B), 0, s, fine, P);
+    for (int j = J; j >= 1; --j) {
+        const int64_t np = (int64_t)1 << (d * (j - 1));
+        if (d == 2) hipLaunchKernelGGL(k_project<2>, dim3(blocks_for(np, B)), dim3(B), 0, s, P, j);
+        else hipLaunchKernelGGL(k_project<3>, dim3(blocks_for(np, B)), dim3(B), 0, s, P, j);
+    }
+    return flags_and_leaves(P, p, s, sc, bcount, boff, nb, keys, values, capacity, level_counts);
+}
+
+int64_t rd_mra_reconstruct(const uint64_t* keys, const double* values, int64_t n_leaves,
+                           int32_t m, const rd_mra_params* p, double* fine, void* hip_stream) {
+    if (!mra_params_valid(p, m) || !fine || n_leaves < 1 || !keys || !values) {
+        set_error("invalid MRA arguments");
+        return RD_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    Pyr P{};
+    double* sc = nullptr;
+    unsigned* bcount = nullptr;
+    unsigned long long* boff = nullptr;
+    int64_t nb = 0;
+    if (int r = setup_pyr(p, m, s, P, &sc, &bcount, &boff, &nb)) return r;
+    if (int r = tree_levels(P, keys, values, n_leaves, s)) return r;
+    const int d = P.d, J = P.J;
+    const int64_t nfine = (int64_t)1 << (d * J);
+    const int B = 256;
     if (d == 2) hipLaunchKernelGGL(k_from_morton<2>, dim3(blocks_for(nfine, B)), dim3(B), 0, s, fine, P);
     else hipLaunchKernelGGL(k_from_morton<3>, dim3(blocks_for(nfine, B)), dim3(B), 0, s, fine, P);
     MRA_TRY(hipGetLastError());
     MRA_TRY(hipStreamSynchronize(s));
     return 0;
+}
+
+int64_t rd_mra_adapt(const uint64_t* keys, const double* values, int64_t n_leaves, int32_t m,
+                     const rd_mra_params* p, uint64_t* out_keys, double* out_values,
+                     int64_t capacity, int64_t* level_counts, void* hip_stream) {
+    if (!mra_params_valid(p, m) || n_leaves < 1 || !keys || !values || capacity < 0) {
+        set_error("invalid MRA arguments");
+        return RD_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    Pyr P{};
+    double* sc = nullptr;
+    unsigned* bcount = nullptr;
+    unsigned long long* boff = nullptr;
+    int64_t nb = 0;
+    if (int r = setup_pyr(p, m, s, P, &sc, &bcount, &boff, &nb)) return r;
+    if (int r = upload_scale(p, m, sc, s)) return r;
+    if (int r = tree_levels(P, keys, values, n_leaves, s)) return r;
+    return flags_and_leaves(P, p, s, sc, bcount, boff, nb, out_keys, out_values, capacity,
+                            level_counts);
 }
 
 }  // extern "C"

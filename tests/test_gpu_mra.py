@@ -80,3 +80,53 @@ def test_bz_adapted_grid_pipeline(rd, orc):
     assert err <= 1e-8
     rec = rd.mra_reconstruct(keys, v, d, J)
     assert rec.shape == ft.shape and torch.isfinite(rec).all()
+
+
+@pytest.mark.parametrize("d,J,eps", [(2, 8, 1e-3), (3, 5, 1e-3), (2, 7, 3e-2)])
+def test_leaf_set_with_refinement_parity(rd, d, J, eps):
+    f = front_field_rowmajor(d, J, m=2, seed=J + 1)
+    say("mra refine parity d", d, "J", J, "eps", eps)
+    ft = torch.tensor(f, dtype=torch.float64, device="cuda")
+    keys, vals, counts = rd.mra_leaves(ft, d, J, eps, refine=True)
+    ko, vo, co = M.leaves(M.row_major_to_morton(f, d, J), d, J, eps, refine=True)
+    assert np.array_equal(keys.cpu().numpy().view(np.uint64), ko)
+    assert np.array_equal(np.array(counts), co)
+    assert np.array_equal(vals.cpu().numpy(), vo)
+
+
+def leaf_centres(keys, d):
+    lev, idx = M.key_level(keys), M.key_index(keys, d)
+    out = np.zeros((d, keys.size))
+    for j in np.unique(lev):
+        sel = lev == j
+        co = M.deinterleave(idx[sel], d, int(j))
+        for a in range(d):
+            out[a, sel] = (co[a] + 0.5) / (1 << int(j))
+    return out
+
+
+@pytest.mark.parametrize("d,J,eps", [(2, 8, 1e-3), (3, 5, 1e-3)])
+@pytest.mark.parametrize("refine", [False, True])
+@pytest.mark.parametrize("change", ["bump", "flatten"])
+def test_adapt_parity(rd, d, J, eps, refine, change):
+    """Adaptation after the values change: a leaf set from the oracle, its
+    values changed on the CPU (a bump away from the fronts: new significant
+    details; or the fronts flattened in half of the domain: details vanish
+    and the tree coarsens there), then the GPU and the oracle adapt it:
+    identical keys, values and per-level counts."""
+    f = front_field_rowmajor(d, J, m=2, seed=J)
+    ko, vo, _ = M.leaves(M.row_major_to_morton(f, d, J), d, J, eps)
+    x = leaf_centres(ko, d)
+    if change == "bump":
+        bump = 0.3 * np.exp(-np.sum((x - 0.2) ** 2, axis=0) / 0.005)
+        v2 = vo + bump[None, :] * np.array([[1.0], [0.5]])
+    else:
+        v2 = np.where(x[0][None, :] > 0.5, np.array([[0.7], [0.2]]), vo)
+    ka, va, ca = M.adapt(ko, v2, d, J, eps, refine=refine)
+    say("adapt d", d, "J", J, "refine", refine, "leaves", ko.size, "->", ka.size)
+    kt = torch.tensor(ko.view(np.int64), device="cuda")
+    vt = torch.tensor(np.ascontiguousarray(v2), dtype=torch.float64, device="cuda")
+    kg, vg, cg = rd.mra_adapt(kt, vt, d, J, eps, refine=refine)
+    assert np.array_equal(kg.cpu().numpy().view(np.uint64), ka)
+    assert np.array_equal(np.array(cg), ca)
+    assert np.array_equal(vg.cpu().numpy(), va)
