@@ -409,7 +409,7 @@ int prepare(double* states, int64_t n, int32_t m, double dt, double rtol, double
 struct ThreadTiming {
     hipEvent_t a = nullptr, b = nullptr;
     bool valid = false;
-    unsigned long long* host = nullptr; /* pinned readback word */
+    unsigned long long* host = nullptr; /* pinned readback words (2) */
 };
 static thread_local ThreadTiming g_tt;
 
@@ -418,7 +418,7 @@ static int ensure_thread_objects() {
         HIP_TRY(hipEventCreate(&g_tt.a));
         HIP_TRY(hipEventCreate(&g_tt.b));
     }
-    if (!g_tt.host) HIP_TRY(hipHostMalloc((void**)&g_tt.host, sizeof(unsigned long long), 0));
+    if (!g_tt.host) HIP_TRY(hipHostMalloc((void**)&g_tt.host, 2 * sizeof(unsigned long long), 0));
     return 0;
 }
 
@@ -565,6 +565,37 @@ int64_t rd_reaction_step_ex(double* states, int64_t n_cells, int32_t m, double d
     HIP_TRY(hipStreamSynchronize(s));
     return (int64_t)*g_tt.host;
 }
+
+}  // extern "C"
+
+namespace rd {
+
+/* Enqueue one reaction step and, behind it on the same stream, the copy of
+ * its failed-cell count into pinned host word `word` (0 or 1) of this
+ * thread; nothing is awaited.  The count is valid once the stream has
+ * reached that point (reaction_count). */
+int64_t reaction_enqueue(double* states, int64_t n_cells, int32_t m, double dt, double rtol,
+                         double atol, const rd_model* model, const rd_options* opts,
+                         int32_t* stats, hipStream_t s, int word) {
+    Prepared pr;
+    int r = prepare(states, n_cells, m, dt, rtol, atol, model, opts, stats, &pr);
+    if (r < 0) return r;
+    if (int e = ensure_thread_objects()) return e;
+    g_tt.host[word] = 0;
+    if (n_cells == 0) return 0;
+    unsigned long long* nfail = nullptr;
+    r = launch_prepared(pr, s, opts && opts->use_graph, &nfail);
+    if (r < 0) return r;
+    HIP_TRY(hipMemcpyAsync(g_tt.host + word, nfail, sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, s));
+    return 0;
+}
+
+int64_t reaction_count(int word) { return (int64_t)g_tt.host[word]; }
+
+}  // namespace rd
+
+extern "C" {
 
 int64_t rd_reaction_step(double* states, int64_t n_cells, int32_t m, double dt, double rtol,
                          double atol, const rd_model* model) {

@@ -61,6 +61,15 @@ void* stream_workspace(DevCtx& c, hipStream_t s, size_t bytes, int* err);
 int enqueue_order(DevCtx& c, Prepared& pr, hipStream_t s, unsigned long long* counters,
                   bool* cleared);
 
+/* One reaction step enqueued on stream s with its failed-cell count copied,
+ * behind it, into this thread's pinned host word `word` (0 or 1); returns 0
+ * or a negative call-level error.  reaction_count(word) reads the count once
+ * the stream has passed that copy. */
+int64_t reaction_enqueue(double* states, int64_t n_cells, int32_t m, double dt, double rtol,
+                         double atol, const rd_model* model, const rd_options* opts,
+                         int32_t* stats, hipStream_t s, int word);
+int64_t reaction_count(int word);
+
 /* Grid for a persistent kernel: resident workgroups on the device, capped by
  * the number of workgroups the cells would fill. */
 int persistent_grid(const DevCtx& c, const KernelEntry* e, int64_t n);

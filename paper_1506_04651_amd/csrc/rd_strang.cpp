@@ -170,16 +170,21 @@ int64_t rd_strang_step(double* states, int32_t m, const rd_grid* grid, double dt
         set_error("per-cell warm start is not supported by the Strang driver");
         return RD_EINVAL;
     }
-    const int64_t r1 = rd_reaction_step_ex(states, n, m, 0.5 * dt, rtol, atol, model, opts, stats,
-                                           hip_stream, 0);
+    /* R, D, R in stream order with no host wait in between; the two failure
+     * counts land in pinned host words and are read after one synchronization */
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int64_t r1 = reaction_enqueue(states, n, m, 0.5 * dt, rtol, atol, model, opts, stats, s, 0);
     if (r1 < 0) return r1;
-    const int64_t sd = diffusion_enqueue(states, m, grid, dt, 0, (hipStream_t)hip_stream);
+    const int64_t sd = diffusion_enqueue(states, m, grid, dt, 0, s);
     if (sd < 0) return sd;
-    const int64_t r2 = rd_reaction_step_ex(states, n, m, 0.5 * dt, rtol, atol, model, opts,
-                                           stats ? stats + (size_t)RD_NSTATS * n : nullptr,
-                                           hip_stream, 0);
+    const int64_t r2 = reaction_enqueue(states, n, m, 0.5 * dt, rtol, atol, model, opts,
+                                        stats ? stats + (size_t)RD_NSTATS * n : nullptr, s, 1);
     if (r2 < 0) return r2;
-    return r1 + r2;
+    if (hipError_t e = hipStreamSynchronize(s); e != hipSuccess) {
+        set_error("hipStreamSynchronize: %s", hipGetErrorString(e));
+        return RD_EDEVICE;
+    }
+    return reaction_count(0) + reaction_count(1);
 }
 
 }  // extern "C"
