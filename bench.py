@@ -116,8 +116,8 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}): the reaction step has no "
-              "cross-cell communication, so more GPUs would each run an independent shard; "
-              "see DESIGN.md for how the path shards.", file=sys.stderr)
+              "cross-cell communication, so more GPUs would each run their own persistent kernel "
+              "on a contiguous, cost-balanced range of the Morton-ordered cells.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
