@@ -170,6 +170,30 @@ def test_diffusion_and_strang_validation(lib):
                               ctypes.byref(md), ctypes.byref(o), None, None) == -1
 
 
+def test_mra_validation(lib):
+    """Malformed multiresolution calls are rejected before any device work."""
+    from paper_1506_04651_amd import _lib
+    dummy = ctypes.c_void_p(1)
+    sc = (ctypes.c_double * 2)(1.0, 0.0)
+    bad = [_lib.RdMraParams(1, 5, 1e-3, None, 0), _lib.RdMraParams(2, 0, 1e-3, None, 0),
+           _lib.RdMraParams(3, 11, 1e-3, None, 0), _lib.RdMraParams(2, 5, -1.0, None, 0),
+           _lib.RdMraParams(2, 5, float("nan"), None, 0),
+           _lib.RdMraParams(2, 5, 1e-3, ctypes.cast(sc, ctypes.POINTER(ctypes.c_double)), 1)]
+    for p in bad:
+        assert lib.rd_mra_leaves(dummy, 2, ctypes.byref(p), None, None, 0, None, None) == -1
+        assert lib.rd_mra_reconstruct(dummy, dummy, 10, 2, ctypes.byref(p), dummy, None) == -1
+        assert lib.rd_mra_adapt(dummy, dummy, 10, 2, ctypes.byref(p), None, None, 0, None, None) == -1
+    good = _lib.RdMraParams(2, 5, 1e-3, None, 1)
+    assert lib.rd_mra_leaves(None, 2, ctypes.byref(good), None, None, 0, None, None) == -1
+    assert lib.rd_mra_leaves(dummy, 2, ctypes.byref(good), None, None, -1, None, None) == -1
+    assert lib.rd_mra_leaves(dummy, 0, ctypes.byref(good), None, None, 0, None, None) == -1
+    assert lib.rd_mra_adapt(None, dummy, 10, 2, ctypes.byref(good), None, None, 0, None, None) == -1
+    assert lib.rd_mra_adapt(dummy, None, 10, 2, ctypes.byref(good), None, None, 0, None, None) == -1
+    assert lib.rd_mra_adapt(dummy, dummy, 0, 2, ctypes.byref(good), None, None, 0, None, None) == -1
+    assert lib.rd_mra_adapt(dummy, dummy, 10, 2, ctypes.byref(good), None, None, -1, None, None) == -1
+    assert lib.rd_mra_reconstruct(dummy, dummy, 10, 2, ctypes.byref(good), None, None) == -1
+
+
 def test_product_path_does_not_reference_the_oracle():
     pkg = os.path.join(ROOT, "paper_1506_04651_amd")
     for dp, _, files in os.walk(pkg):
