@@ -12,10 +12,14 @@
 - Reconstruction: lossless at eps = 0, error shrinking with eps, and the
   projection of the reconstruction returns every leaf value.
 """
+import os
+
 import numpy as np
 import pytest
 
 from oracle import mra as M
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def zcurve(d, j):
@@ -255,3 +259,48 @@ def test_leaves_with_refinement_contain_the_plain_tree():
     for j in np.unique(lev):
         sel = lev == j
         assert np.array_equal(vr[:, sel], levels[j][:, idx[sel]])
+
+
+def test_prediction_matches_the_paper_1d_operator():
+    """tests/golden/mr_prediction_1d.txt: the paper's 1D prediction (§2.2)
+    worked by hand.  A 2D coarse level that varies only along x reduces the
+    tensor-product prediction to the 1D operator: the children at x = 2k and
+    2k + 1 of an interior node k carry exactly the fixture's values (a wrong
+    sign or a swapped child fails)."""
+    rows = np.loadtxt(os.path.join(GOLDEN, "mr_prediction_1d.txt"))
+    d, jc = 2, 3
+    N = 1 << jc
+    for um, u0, up, e0, e1 in rows:
+        xs = np.full(N, 7.0)
+        xs[2], xs[3], xs[4] = um, u0, up          # node k = 3 with its two neighbours
+        co = M.deinterleave(np.arange(N * N), d, jc)
+        Uc = xs[co[0]][None, :]                   # constant along y
+        ky = 5                                    # interior row
+        for cx, want in ((0, e0), (1, e1)):
+            for cy in (0, 1):
+                child = M.interleave((np.array([2 * 3 + cx]), np.array([2 * ky + cy])), jc + 1)
+                assert M.predict(Uc, d, jc, child)[0][0] == want
+
+
+def test_thresholds_match_the_paper():
+    """tests/golden/mr_thresholds.txt: eps_j = 2^((d/2)(j-J)) eps (§2.2), worked
+    by hand.  A field equal to v on the cells below one level-j node and 0
+    elsewhere has, at level j, the detail (1 - 2^-d) v at that node (an
+    interior one: its parent averages it with 2^d - 1 zero siblings, the zero
+    neighbours add nothing to the prediction), smaller details at its siblings
+    (2^-d v) and neighbours (at most d 2^-d v / 8), coarser details below
+    their own thresholds, and no finer details.  So the node and its siblings
+    are leaves exactly when (1 - 2^-d) v >= eps_j: just above, level j holds
+    2^d leaves; just below, none."""
+    rows = np.loadtxt(os.path.join(GOLDEN, "mr_thresholds.txt"))
+    for d, J, j, eps, eps_j in rows:
+        d, J, j = int(d), int(J), int(j)
+        half = 1 << (j - 1)                             # an interior level-j node
+        node = int(M.interleave(tuple(np.array([half]) for _ in range(d)), j)[0])
+        span = 1 << (d * (J - j))
+        vcrit = eps_j / (1.0 - 2.0 ** -d)
+        for f, want in ((1 + 1e-9, 1 << d), (1 - 1e-9, 0)):
+            U = np.zeros((1, 1 << (d * J)))
+            U[0, node * span:(node + 1) * span] = vcrit * f
+            _, _, counts = M.leaves(U, d, J, eps)
+            assert counts[j] == want, (d, J, j, f, counts)
