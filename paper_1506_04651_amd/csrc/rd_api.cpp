@@ -135,6 +135,8 @@ DevCtx* current_ctx() {
     }
     if ((e = hipMemset(c->slots, 0, sizeof(unsigned long long) * 2 * kSlots)) != hipSuccess) {
         set_error("hipMemset(counter slots): %s", hipGetErrorString(e));
+        hipFree(c->slots);
+        delete c;
         return nullptr;
     }
     g_ctx[dev] = c;
@@ -314,6 +316,7 @@ static const double* device_params(DevCtx& c, int kind, int m, const std::vector
     e = hipMemcpy(d, block.data(), sizeof(double) * block.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         set_error("hipMemcpy(params): %s", hipGetErrorString(e));
+        hipFree(d);
         *err = RD_EDEVICE;
         return nullptr;
     }
@@ -488,6 +491,7 @@ static int launch_prepared(Prepared& pr, hipStream_t s, bool use_graph, unsigned
                 hipGraph_t dummy = nullptr;
                 hipStreamEndCapture(s, &dummy);
                 if (dummy) hipGraphDestroy(dummy);
+                hipFree(v.counters);
                 return r;
             }
             a.order = pr.args.order;
@@ -497,10 +501,17 @@ static int launch_prepared(Prepared& pr, hipStream_t s, bool use_graph, unsigned
             if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
                 set_error("graph capture failed: %s / %s / %s", hipGetErrorString(e1),
                           hipGetErrorString(e2), hipGetErrorString(e3));
+                if (g) hipGraphDestroy(g);
+                hipFree(v.counters);
                 return RD_EDEVICE;
             }
-            HIP_TRY(hipGraphInstantiate(&v.exec, g, nullptr, nullptr, 0));
-            HIP_TRY(hipGraphDestroy(g));
+            const hipError_t ei = hipGraphInstantiate(&v.exec, g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (ei != hipSuccess) {
+                set_error("hipGraphInstantiate: %s", hipGetErrorString(ei));
+                hipFree(v.counters);
+                return RD_EDEVICE;
+            }
             it = g_graphs.emplace(key, v).first;
         }
         HIP_TRY(hipEventRecord(g_tt.a, s));

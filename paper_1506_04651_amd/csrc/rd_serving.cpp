@@ -240,6 +240,16 @@ size_t rd_request_bytes(int64_t n_cells, int32_t m, int32_t with_stats) {
     return b;
 }
 
+/* Release what a partly created session holds (no worker thread yet). */
+static void free_partial_session(rd_session* s) {
+    for (hipStream_t st : s->streams) hipStreamDestroy(st);
+    for (hipEvent_t ev : s->free_events) hipEventDestroy(ev);
+    if (s->counters) hipFree(s->counters);
+    if (s->host_fail) hipHostFree(s->host_fail);
+    if (s->arena_base) hipFree(s->arena_base);
+    delete s;
+}
+
 int32_t rd_session_create(rd_session** out, int32_t device, size_t hbm_budget_bytes,
                           const rd_options* defaults, int32_t n_streams) {
     if (!out || hbm_budget_bytes < 256) { set_error("bad session arguments"); return RD_EINVAL; }
@@ -269,6 +279,7 @@ int32_t rd_session_create(rd_session** out, int32_t device, size_t hbm_budget_by
         hipStream_t st;
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
             set_error("hipStreamCreate failed");
+            free_partial_session(s);
             return RD_EDEVICE;
         }
         s->streams.push_back(st);
@@ -276,6 +287,7 @@ int32_t rd_session_create(rd_session** out, int32_t device, size_t hbm_budget_by
     if (hipMalloc((void**)&s->counters, 2 * kSessionSlots * sizeof(unsigned long long)) != hipSuccess ||
         hipHostMalloc((void**)&s->host_fail, kSessionSlots * sizeof(unsigned long long), 0) != hipSuccess) {
         set_error("session workspace allocation failed");
+        free_partial_session(s);
         return RD_ENOMEM;
     }
     for (int i = kSessionSlots - 1; i >= 0; --i) {
@@ -283,6 +295,7 @@ int32_t rd_session_create(rd_session** out, int32_t device, size_t hbm_budget_by
         hipEvent_t ev;
         if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
             set_error("hipEventCreate failed");
+            free_partial_session(s);
             return RD_EDEVICE;
         }
         s->free_events.push_back(ev);
