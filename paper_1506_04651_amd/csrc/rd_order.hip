@@ -44,29 +44,6 @@ __global__ void k_order_init(unsigned* hist, unsigned long long* counters) {
     if (counters && threadIdx.x < 2) counters[threadIdx.x] = 0ull;
 }
 
-/* Adds one to lh[b] for every active lane of the wave with one LDS atomic
- * per distinct bucket, and returns the lane's slot in its bucket (the count
- * before the add plus the lane's rank among the active lanes of that bucket).
- * Called by every lane of the wave. */
-__device__ __forceinline__ unsigned wave_bucket_add(unsigned* lh, int b, bool active) {
-    const unsigned lane = __lane_id();
-    const unsigned long long below = (1ull << lane) - 1ull;
-    unsigned long long rest = __ballot(active);
-    unsigned slot = 0u;
-    while (rest) {
-        const int leader = __ffsll((long long)rest) - 1;
-        const int lb = __shfl(b, leader);
-        const bool mine = active && b == lb;
-        const unsigned long long same = __ballot(mine);
-        unsigned base = 0u;
-        if ((int)lane == leader) base = atomicAdd(&lh[lb], (unsigned)__popcll(same));
-        base = __shfl(base, leader);
-        if (mine) slot = base + (unsigned)__popcll(same & below);
-        rest &= ~same;
-    }
-    return slot;
-}
-
 /* max_i |f_i(u0)| dt / (atol' + rtol' |u0_i|) of cell c, for a model with a
  * compile-time species count */
 template <class Model>
@@ -118,37 +95,51 @@ struct GroupKey {
     }
 };
 
+/* Cells per thread of the two counting-sort kernels: cell k * kOrderBlock +
+ * threadIdx.x of the block's span of kOrderCells cells (coalesced for each
+ * k).  Four cells per thread cut the blocks, and so the global atomics on
+ * the 2 x kBuckets shared counters, by four. */
+constexpr int kOrderCpt = 4;
+constexpr int kOrderCells = kOrderBlock * kOrderCpt;
+
+__device__ __forceinline__ int bucket_of(double key) {
+    if (!(key > 0.0) || !__builtin_isfinite(key)) return 0;
+    /* floor(kSub log2(key)), approximately: the exponent field and the
+     * leading mantissa bits (subnormals clamp low) */
+    const long long bits = __double_as_longlong(key);
+    const int e = (int)((bits >> 52) & 0x7ff) - 1023;
+    const int q = (int)((bits >> 50) & (kSub - 1));
+    const int b = (e - kLog2Min) * kSub + q;
+    return b < 0 ? 0 : (b >= kBuckets ? kBuckets - 1 : b);
+}
+
+/* Bucket of every cell, and the counts per bucket (an LDS histogram per
+ * block, added to the global one with one atomic per nonzero bucket). */
 template <class Key>
 __global__ void __launch_bounds__(kOrderBlock) k_order_cost(LaunchArgs a, unsigned char* bucket,
                                                             unsigned* hist) {
     __shared__ unsigned lh[kBuckets];
     if (threadIdx.x < kBuckets) lh[threadIdx.x] = 0u;
     __syncthreads();
-    const int64_t c = (int64_t)blockIdx.x * kOrderBlock + threadIdx.x;
-    const bool act = c < a.n;
-    int b = 0;
-    if (act) {
-        const double key = Key::key(a, c);
-        if (key > 0.0 && __builtin_isfinite(key)) {
-            /* floor(kSub log2(key)), approximately: the exponent field and
-             * the leading mantissa bits (subnormals clamp low) */
-            const long long bits = __double_as_longlong(key);
-            const int e = (int)((bits >> 52) & 0x7ff) - 1023;
-            const int q = (int)((bits >> 50) & (kSub - 1));
-            b = (e - kLog2Min) * kSub + q;
-            b = b < 0 ? 0 : (b >= kBuckets ? kBuckets - 1 : b);
+    const int64_t c0 = (int64_t)blockIdx.x * kOrderCells + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kOrderCpt; ++k) {
+        const int64_t c = c0 + (int64_t)k * kOrderBlock;
+        if (c < a.n) {
+            const int b = bucket_of(Key::key(a, c));
+            bucket[c] = (unsigned char)b;
+            atomicAdd(&lh[b], 1u);
         }
-        bucket[c] = (unsigned char)b;
     }
-    wave_bucket_add(lh, b, act);
     __syncthreads();
     if (threadIdx.x < kBuckets && lh[threadIdx.x]) atomicAdd(&hist[threadIdx.x], lh[threadIdx.x]);
 }
 
 /* Each block finds where the buckets start (most expensive bucket first:
  * start[b] = number of cells in buckets above b) from the global counts,
- * ranks its cells inside their buckets, reserves one range per bucket from
- * the bucket's cursor and writes the cell indices there. */
+ * ranks its cells inside their buckets (LDS atomics: any order inside a
+ * bucket is valid), reserves one range per bucket from the bucket's cursor
+ * and writes the cell indices there. */
 __global__ void __launch_bounds__(kOrderBlock) k_order_scatter(const unsigned char* bucket,
                                                                unsigned* hist, int32_t* order,
                                                                int64_t n) {
@@ -178,15 +169,24 @@ __global__ void __launch_bounds__(kOrderBlock) k_order_scatter(const unsigned ch
         }
     }
     __syncthreads();
-    const int64_t c = (int64_t)blockIdx.x * kOrderBlock + threadIdx.x;
-    const bool act = c < n;
-    const int b = act ? (int)bucket[c] : 0;
-    const unsigned local = wave_bucket_add(lcount, b, act);
+    const int64_t c0 = (int64_t)blockIdx.x * kOrderCells + threadIdx.x;
+    int b[kOrderCpt];
+    unsigned local[kOrderCpt];
+#pragma unroll
+    for (int k = 0; k < kOrderCpt; ++k) {
+        const int64_t c = c0 + (int64_t)k * kOrderBlock;
+        b[k] = c < n ? (int)bucket[c] : 0;
+        local[k] = c < n ? atomicAdd(&lcount[b[k]], 1u) : 0u;
+    }
     __syncthreads();
     if (threadIdx.x < kBuckets && lcount[threadIdx.x])
         lbase[threadIdx.x] += atomicAdd(&hist[kBuckets + threadIdx.x], lcount[threadIdx.x]);
     __syncthreads();
-    if (act) order[lbase[b] + local] = (int32_t)c;
+#pragma unroll
+    for (int k = 0; k < kOrderCpt; ++k) {
+        const int64_t c = c0 + (int64_t)k * kOrderBlock;
+        if (c < n) order[lbase[b[k]] + local[k]] = (int32_t)c;
+    }
 }
 
 template <class Key>
@@ -194,7 +194,7 @@ hipError_t launch_order(const LaunchArgs& a, void* ws, int32_t* order,
                         unsigned long long* counters, hipStream_t s) {
     unsigned char* bucket = (unsigned char*)ws;
     unsigned* hist = (unsigned*)((char*)ws + align_up((size_t)a.n));
-    const int grid = (int)((a.n + kOrderBlock - 1) / kOrderBlock);
+    const int grid = (int)((a.n + kOrderCells - 1) / kOrderCells);
     hipLaunchKernelGGL(k_order_init, dim3(1), dim3(2 * kBuckets), 0, s, hist, counters);
     hipLaunchKernelGGL(k_order_cost<Key>, dim3(grid), dim3(kOrderBlock), 0, s, a, bucket, hist);
     hipLaunchKernelGGL(k_order_scatter, dim3(grid), dim3(kOrderBlock), 0, s,
