@@ -61,6 +61,11 @@ hipError_t launch_reset(unsigned long long* p, int n, hipStream_t s) {
     RD_PERS_P(KIND, MODEL, M, PREC, LT, 25, 128, 3, 32, 4, TAG ".persistent.b128.w3.fs32.p4"), \
     RD_PERS_P(KIND, MODEL, M, PREC, LT, 26, 128, 3, 28, 3, TAG ".persistent.b128.w3.fs28.p3"), \
     RD_PERS(KIND, MODEL, M, PREC, LT, false, 27, 128, 3, 40, TAG ".persistent.b128.w3.fs40"),  \
+    RD_PERS_P(KIND, MODEL, M, PREC, LT, 28, 128, 3, 40, 2, TAG ".persistent.b128.w3.fs40.p2"), \
+    RD_PERS_P(KIND, MODEL, M, PREC, LT, 29, 128, 3, 64, 2, TAG ".persistent.b128.w3.fs64.p2"), \
+    RD_PERS_U(KIND, MODEL, M, PREC, LT, 30, 128, 3, 40, 2, 64, 40, TAG ".persistent.b128.w3.fs40.p2.u64"), \
+    RD_PERS_U(KIND, MODEL, M, PREC, LT, 31, 128, 3, 40, 2, 40, 64, TAG ".persistent.b128.w3.fs40.p2.l64"), \
+    RD_PERS_U(KIND, MODEL, M, PREC, LT, 32, 128, 3, 40, 2, 64, 64, TAG ".persistent.b128.w3.fs40.p2.u64.l64"), \
     RD_ONE(KIND, MODEL, M, PREC, LT, false, 2, 256, 1, 16, TAG ".onelaunch.b256.fs16"),       \
     RD_ONE(KIND, MODEL, M, PREC, LT, false, 3, 256, 1, 1, TAG ".onelaunch.b256.fs1")
 

@@ -22,7 +22,7 @@ namespace rd {
  * individual lanes but never changes what a cell computes. */
 template <class Model, typename LT, bool FIXED, int BLOCK, int FSMIN>
 __device__ __forceinline__ void advance(SmallCell<Model, LT, BLOCK>& cell, const Model& md,
-                                        const StepParams& P) {
+                                        const StepParams& P, int fsmin = FSMIN) {
     if (cell.phase == PH_NEWTON) {
         const int o = cell.newton(md, P);
         if (o != NW_CONTINUE) {
@@ -34,7 +34,7 @@ __device__ __forceinline__ void advance(SmallCell<Model, LT, BLOCK>& cell, const
     if (FSMIN > 1) {
         const unsigned long long wmask = __ballot(waits);
         if (wmask == 0ull) return;
-        if ((unsigned)__popcll(wmask) < (unsigned)FSMIN && __ballot(cell.phase == PH_NEWTON) != 0ull)
+        if ((unsigned)__popcll(wmask) < (unsigned)fsmin && __ballot(cell.phase == PH_NEWTON) != 0ull)
             return;
     }
     if (cell.phase == PH_END) cell.template finish<FIXED>(md, P, cell.outcome);
@@ -79,20 +79,26 @@ constexpr unsigned kClaimChunk = 16;
  * below 3 span, else 0.  Priorities only arbitrate instruction issue between
  * ready waves; they change no result. */
 template <int PDIV>
-__device__ __forceinline__ void claim_priority(unsigned long long held, unsigned long long lanes) {
+__device__ __forceinline__ int claim_priority(unsigned long long held, unsigned long long lanes) {
     const unsigned long long span = (lanes + PDIV - 1) / PDIV;
-    if (__ballot(held < span)) __builtin_amdgcn_s_setprio(3);
-    else if (__ballot(held < 2 * span)) __builtin_amdgcn_s_setprio(2);
-    else if (__ballot(held < 3 * span)) __builtin_amdgcn_s_setprio(1);
-    else __builtin_amdgcn_s_setprio(0);
+    if (__ballot(held < span)) { __builtin_amdgcn_s_setprio(3); return 3; }
+    if (__ballot(held < 2 * span)) { __builtin_amdgcn_s_setprio(2); return 2; }
+    if (__ballot(held < 3 * span)) { __builtin_amdgcn_s_setprio(1); return 1; }
+    __builtin_amdgcn_s_setprio(0);
+    return 0;
 }
 
 /* PLDS: the step parameters are staged in LDS and re-read each pass (true),
  * or read from the kernel arguments, where the compiler keeps them in scalar
  * registers across the loop (false).  Same arithmetic either way.  PDIV > 0:
- * wave issue priorities from claim positions (claim_priority). */
+ * wave issue priorities from claim positions (claim_priority).  Step-end
+ * batching threshold of a wave: FSL during its first claim round (every lane
+ * started its cell in the same pass, and the claim order put cells of
+ * similar cost side by side, so the lanes stay nearly in phase and waiting
+ * for all of them costs little), then FSU while the wave holds cells at the
+ * top priority, else FSMIN. */
 template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool PLDS = true,
-          int PDIV = 0>
+          int PDIV = 0, int FSU = FSMIN, int FSL = FSMIN>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_persistent(LaunchArgs a) {
     using L = SmallLds<Model::M>;
@@ -113,6 +119,8 @@ k_persistent(LaunchArgs a) {
     const unsigned long long below = (1ull << lane) - 1ull;
     unsigned long long qnext = 0, qend = 0; /* wave-uniform */
     unsigned long long held = ~0ull;         /* claim position of the cell held */
+    int fs = FSL;                            /* wave-uniform step-end batching threshold */
+    int claims = 0;                          /* claim rounds of the wave so far */
     for (;;) {
         const bool need = alive && cell.phase == PH_IDLE;
         if (need && c >= 0) {
@@ -150,11 +158,16 @@ k_persistent(LaunchArgs a) {
                     alive = false;
                 }
             }
-            if (PDIV > 0) claim_priority<PDIV>(held, (unsigned long long)gridDim.x * BLOCK);
+            const int prio =
+                PDIV > 0 ? claim_priority<PDIV>(held, (unsigned long long)gridDim.x * BLOCK) : 0;
+            if (FSU != FSMIN || FSL != FSMIN) {
+                ++claims;
+                fs = claims == 1 ? FSL : (prio == 3 ? FSU : FSMIN);
+            }
         }
         if (__ballot(alive) == 0ull) break;
         if (PLDS) __asm__ volatile("" ::: "memory"); /* re-read sP from LDS each pass */
-        advance<Model, LT, FIXED, BLOCK, FSMIN>(cell, md, sP);
+        advance<Model, LT, FIXED, BLOCK, FSMIN>(cell, md, sP, fs);
     }
 }
 
@@ -167,10 +180,10 @@ hipError_t launch_one(const LaunchArgs& a, int grid, hipStream_t s) {
 }
 
 template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool PLDS = true,
-          int PDIV = 0>
+          int PDIV = 0, int FSU = FSMIN, int FSL = FSMIN>
 hipError_t launch_pers(const LaunchArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_persistent<Model, LT, FIXED, BLOCK, WPE, FSMIN, PLDS, PDIV>), dim3(grid),
-                       dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL((k_persistent<Model, LT, FIXED, BLOCK, WPE, FSMIN, PLDS, PDIV, FSU, FSL>),
+                       dim3(grid), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
@@ -186,6 +199,10 @@ hipError_t launch_pers(const LaunchArgs& a, int grid, hipStream_t s) {
     {KIND, fd_jac_of<MODEL>::value ? 1 : 0, M, PREC, 0, false, VAR, BLOCK, BLOCK, NAME,           \
      &launch_pers<MODEL, LT, false, BLOCK, WPE, FS, true, PDIV>,                                \
      (const void*)&k_persistent<MODEL, LT, false, BLOCK, WPE, FS, true, PDIV>}
+#define RD_PERS_U(KIND, MODEL, M, PREC, LT, VAR, BLOCK, WPE, FS, PDIV, FSU, FSL, NAME)          \
+    {KIND, fd_jac_of<MODEL>::value ? 1 : 0, M, PREC, 0, false, VAR, BLOCK, BLOCK, NAME,           \
+     &launch_pers<MODEL, LT, false, BLOCK, WPE, FS, true, PDIV, FSU, FSL>,                      \
+     (const void*)&k_persistent<MODEL, LT, false, BLOCK, WPE, FS, true, PDIV, FSU, FSL>}
 #define RD_PERS(KIND, MODEL, M, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, NAME)                      \
     {KIND, fd_jac_of<MODEL>::value ? 1 : 0, M, PREC, 0, FIXED, VAR, BLOCK, BLOCK, NAME,                                          \
      &launch_pers<MODEL, LT, FIXED, BLOCK, WPE, FS>,                                            \
@@ -200,14 +217,16 @@ enum { K_OREG = 1, K_KIN = 2, K_NAG = 3, K_LIN = 4, K_ROB = 5, K_BC = 6 };
  * kernels (3 where the engine fits 168 registers with few spills, else 1);
  * the persistent kernels give waves that hold early claim positions (the
  * costliest cells under the longest-first order) a higher issue priority
- * (claim_priority with PDIV = 2) */
+ * (claim_priority with PDIV = 2), and batch step ends at 48 waiting lanes,
+ * or at all lanes while a wave still holds its first claims (its lanes then
+ * started together on cells of similar cost) or holds the costliest cells */
 #define RD_MODEL_SET_W(KIND, MODEL, M, TAG, WPE)                                                      \
     RD_ONE(KIND, MODEL, M, 0, double, false, 1, 256, 1, 32, TAG ".fp64.onelaunch.b256.fs32"),        \
     RD_ONE(KIND, MODEL, M, 1, float, false, 1, 256, 1, 32, TAG ".mixed.onelaunch.b256.fs32"),         \
-    RD_PERS_P(KIND, MODEL, M, 0, double, 1, 128, WPE, 40, 2,                                        \
-              TAG ".fp64.persistent.b128.w" RD_STR(WPE) ".fs40.p2"),                                \
-    RD_PERS_P(KIND, MODEL, M, 1, float, 1, 128, WPE, 40, 2,                                         \
-              TAG ".mixed.persistent.b128.w" RD_STR(WPE) ".fs40.p2"),                               \
+    RD_PERS_U(KIND, MODEL, M, 0, double, 1, 128, WPE, 48, 2, 64, 64,                                \
+              TAG ".fp64.persistent.b128.w" RD_STR(WPE) ".fs48.p2.u64.l64"),                        \
+    RD_PERS_U(KIND, MODEL, M, 1, float, 1, 128, WPE, 48, 2, 64, 64,                                 \
+              TAG ".mixed.persistent.b128.w" RD_STR(WPE) ".fs48.p2.u64.l64"),                       \
     RD_ONE(KIND, MODEL, M, 0, double, true, 1, 256, 1, 1, TAG ".fp64.onelaunch.fixed"),             \
     RD_PERS(KIND, MODEL, M, 0, double, true, 1, 256, 1, 1, TAG ".fp64.persistent.fixed")
 #define RD_MODEL_SET(KIND, MODEL, M, TAG) RD_MODEL_SET_W(KIND, MODEL, M, TAG, 3)
