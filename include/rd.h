@@ -193,7 +193,13 @@ int64_t rd_diffusion_step(double* states, int32_t m, const rd_grid* grid, double
  * R_{dt/2}, in place, synchronous on hip_stream.  stats nullable: DEVICE
  * [2][RD_NSTATS][n] int32, the counters of the first and second reaction half.
  * opts->h_cells must be null.  Returns the sum of the failed-cell counts of
- * the two reaction halves, or a negative error.
+ * the two reaction halves, or a negative error.  With opts->use_graph and a
+ * non-null stream, the whole split step (both reaction halves with their
+ * claim-order passes, the diffusion stages, the failure-count copies) is
+ * recorded once as one hipGraph per (stream, states, stats, model constants,
+ * options, grid, coefficients, dt) and replayed on later calls with the same
+ * arguments; the graph keeps its own counters and pinned result words, so
+ * replays of one graph must not overlap (the stream orders them).
  */
 int64_t rd_strang_step(double* states, int32_t m, const rd_grid* grid, double dt, double rtol,
                        double atol, const rd_model* model, const rd_options* opts,

@@ -94,6 +94,22 @@ def main():
         b.record(stream)
         b.synchronize()
         out["strang_ms"] = a.elapsed_time(b)
+        # whole split steps on a side stream, eager and replayed from one
+        # recorded graph, alternating (the field keeps evolving)
+        side = torch.cuda.Stream()
+        tt = {"eager": [], "graph": []}
+        for k in range(2 * args.strang_steps + 2):
+            mode = "graph" if k % 2 else "eager"
+            with torch.cuda.stream(side):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(side)
+                api.strang_step(u, shape, h, BZ_DIFF, args.dt, w.rtol, w.atol, w.kind, w.params,
+                                stream=side, use_graph=(mode == "graph"))
+                b.record(side)
+            b.synchronize()
+            if k >= 2:
+                tt[mode].append(a.elapsed_time(b))
+        out["strang_ms_median"] = {k: float(np.median(v)) for k, v in tt.items()}
         out["strang_breakdown_ms_median"] = {k: float(np.median(v)) for k, v in times.items()}
         tot = sum(out["strang_breakdown_ms_median"].values())
         out["reaction_share"] = (out["strang_breakdown_ms_median"]["R1"] +

@@ -479,11 +479,9 @@ static int launch_prepared(Prepared& pr, hipStream_t s, bool use_graph, unsigned
             a.nfail = v.counters + 1;
             hipGraph_t g = nullptr;
             /* workspace is allocated before the capture starts */
-            if (pr.entry->schedule == RD_PERSISTENT && pr.order) {
-                int err = 0;
-                const size_t need = (((size_t)pr.args.n * 4 + 255) & ~(size_t)255) +
-                                    order_workspace_bytes(pr.args.n);
-                if (!stream_workspace(*c, s, need, &err)) return err;
+            if (int r = ensure_workspace(pr, s)) {
+                hipFree(v.counters);
+                return r;
             }
             HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             bool cleared = false;
@@ -534,6 +532,33 @@ static int launch_prepared(Prepared& pr, hipStream_t s, bool use_graph, unsigned
     g_tt.valid = true;
     *nfail_out = pr.args.nfail;
     return 0;
+}
+
+/* Enqueue a prepared reaction step whose two counters (claim position,
+ * failed cells) are `counters`: the claim-order kernels, which also clear
+ * them, or a clearing kernel, then the step's kernel.  Nothing is allocated
+ * when the stream's claim-order workspace already holds ensure_workspace's
+ * size, so it can be recorded into a graph. */
+int enqueue_prepared(Prepared& pr, hipStream_t s, unsigned long long* counters) {
+    DevCtx* c = current_ctx();
+    if (!c) return RD_EDEVICE;
+    pr.args.counter = counters;
+    pr.args.nfail = counters + 1;
+    bool cleared = false;
+    if (int r = enqueue_order(*c, pr, s, counters, &cleared)) return r;
+    if (!cleared) HIP_TRY(launch_reset(counters, 2, s));
+    HIP_TRY(pr.entry->launch(pr.args, pr.grid, s));
+    return 0;
+}
+
+int ensure_workspace(const Prepared& pr, hipStream_t s) {
+    if (pr.entry->schedule != RD_PERSISTENT || !pr.order) return 0;
+    DevCtx* c = current_ctx();
+    if (!c) return RD_EDEVICE;
+    int err = 0;
+    const size_t need = (((size_t)pr.args.n * 4 + 255) & ~(size_t)255) +
+                        order_workspace_bytes(pr.args.n);
+    return stream_workspace(*c, s, need, &err) ? 0 : (err ? err : RD_ENOMEM);
 }
 
 }  // namespace rd

@@ -61,6 +61,12 @@ void* stream_workspace(DevCtx& c, hipStream_t s, size_t bytes, int* err);
 int enqueue_order(DevCtx& c, Prepared& pr, hipStream_t s, unsigned long long* counters,
                   bool* cleared);
 
+/* A prepared reaction step enqueued on stream s with the given counters
+ * (claim position, failed cells; cleared by the enqueued work); no host
+ * wait, no allocation once ensure_workspace(pr, s) has run.  0 or RD_E*. */
+int enqueue_prepared(Prepared& pr, hipStream_t s, unsigned long long* counters);
+int ensure_workspace(const Prepared& pr, hipStream_t s);
+
 /* One reaction step enqueued on stream s with its failed-cell count copied,
  * behind it, into this thread's pinned host word `word` (0 or 1); returns 0
  * or a negative call-level error.  reaction_count(word) reads the count once

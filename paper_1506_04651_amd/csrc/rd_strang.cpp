@@ -93,8 +93,17 @@ static bool grid_valid(const rd_grid* g, int32_t m) {
     return true;
 }
 
-static int64_t diffusion_enqueue(double* states, int32_t m, const rd_grid* grid, double dt,
-                                 int32_t stages, hipStream_t s) {
+/* One diffusion step, validated and with its RKC stages computed. */
+struct DiffPlan {
+    int dim = 0, stages = 0;
+    double mut1tau = 0.0;
+    std::vector<RkcStage> st;
+    DiffGrid g{};
+    size_t vec = 0; /* m * cells */
+};
+
+static int64_t diffusion_plan(int32_t m, const rd_grid* grid, double dt, int32_t stages,
+                              DiffPlan* p) {
     if (m < 1 || m > RD_MAX_M || !grid_valid(grid, m)) {
         set_error("invalid grid or species count");
         return RD_EINVAL;
@@ -104,39 +113,163 @@ static int64_t diffusion_enqueue(double* states, int32_t m, const rd_grid* grid,
         return RD_EINVAL;
     }
     const int64_t n = (int64_t)grid->nx * grid->ny * grid->nz;
-    if (!states) { set_error("states is null"); return RD_EINVAL; }
     double emax = 0.0;
     for (int i = 0; i < m; ++i) emax = std::fmax(emax, grid->diff[i]);
     const double rho = 4.0 * grid->dim * emax / (grid->h * grid->h); /* Gershgorin */
-    const int sc = stages > 0 ? (stages < 2 ? 2 : stages) : rkc_stage_count(dt * rho);
+    p->dim = grid->dim;
+    p->stages = stages > 0 ? (stages < 2 ? 2 : stages) : rkc_stage_count(dt * rho);
+    rkc_weights(p->stages, dt, p->mut1tau, p->st);
+    p->g = DiffGrid{grid->nx, grid->ny, grid->nz, n, 1.0 / (grid->h * grid->h)};
+    p->vec = (size_t)m * (size_t)n;
+    return 0;
+}
+
+/* The stage kernels of a planned step; w: 4 vec doubles of workspace. */
+static int diffusion_launch(double* states, int32_t m, const DiffPlan& p, const double* eps_dev,
+                            double* w, hipStream_t s) {
+    hipError_t e = launch_rkc(p.dim, states, states, w, w + p.vec, w + 2 * p.vec, w + 3 * p.vec, m,
+                              p.g, eps_dev, p.mut1tau, p.st.data(), p.stages, s);
+    if (e != hipSuccess) {
+        set_error("diffusion launch: %s", hipGetErrorString(e));
+        return RD_EDEVICE;
+    }
+    return 0;
+}
+
+static int64_t diffusion_enqueue(double* states, int32_t m, const rd_grid* grid, double dt,
+                                 int32_t stages, hipStream_t s) {
+    DiffPlan p;
+    if (int64_t r = diffusion_plan(m, grid, dt, stages, &p)) return r;
+    if (!states) { set_error("states is null"); return RD_EINVAL; }
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) {
         set_error("no current device");
         return RD_EDEVICE;
     }
-    const size_t vec = (size_t)m * (size_t)n;
     double* w = nullptr;
-    if (int r = diff_workspace(dev, s, 4 * vec + 256, &w)) return r;
-    double* f0 = w;
-    double* b0 = w + vec;
-    double* b1 = w + 2 * vec;
-    double* b2 = w + 3 * vec;
-    double* eps = w + 4 * vec;
+    if (int r = diff_workspace(dev, s, 4 * p.vec + 256, &w)) return r;
+    double* eps = w + 4 * p.vec;
     if (hipMemcpyAsync(eps, grid->diff, sizeof(double) * m, hipMemcpyHostToDevice, s) != hipSuccess) {
         set_error("hipMemcpyAsync(eps) failed");
         return RD_EDEVICE;
     }
-    double mut1tau = 0.0;
-    std::vector<RkcStage> st;
-    rkc_weights(sc, dt, mut1tau, st);
-    DiffGrid g{grid->nx, grid->ny, grid->nz, n, 1.0 / (grid->h * grid->h)};
-    hipError_t e = launch_rkc(grid->dim, states, states, f0, b0, b1, b2, m, g, eps, mut1tau,
-                              st.data(), sc, s);
-    if (e != hipSuccess) {
-        set_error("diffusion launch: %s", hipGetErrorString(e));
+    if (int r = diffusion_launch(states, m, p, eps, w, s)) return r;
+    return p.stages;
+}
+
+/* ---------------------------------------------------------------- graphs */
+/* A whole split step R_{dt/2} D_dt R_{dt/2} recorded as one graph: both
+ * reaction halves with counters of their own, the failure counts copied to
+ * pinned host words, and the diffusion stages with the coefficients in a
+ * device buffer of the graph.  Keyed by everything the recorded work
+ * depends on; workspaces are allocated before the capture. */
+struct StrangGraph {
+    hipGraphExec_t exec = nullptr;
+    unsigned long long* counters = nullptr; /* 4: claim + failures, per half */
+    unsigned long long* host = nullptr;     /* pinned: failures per half */
+    double* eps = nullptr;                  /* device copy of the coefficients */
+};
+static std::mutex g_sg_mu;
+static std::map<std::vector<unsigned char>, StrangGraph> g_sg;
+
+template <class T>
+static void put(std::vector<unsigned char>& k, const T& v) {
+    const unsigned char* b = (const unsigned char*)&v;
+    k.insert(k.end(), b, b + sizeof(T));
+}
+
+static void free_strang_graph(StrangGraph& g) {
+    if (g.exec) hipGraphExecDestroy(g.exec);
+    if (g.counters) hipFree(g.counters);
+    if (g.host) hipHostFree(g.host);
+    if (g.eps) hipFree(g.eps);
+    g = StrangGraph{};
+}
+
+static int64_t strang_graph_step(double* states, int32_t m, const rd_grid* grid, double dt,
+                                 double rtol, double atol, const rd_model* model,
+                                 const rd_options* opts, int32_t* stats, hipStream_t s) {
+    const int64_t n = (int64_t)grid->nx * grid->ny * grid->nz;
+    Prepared p1, p2;
+    int r = prepare(states, n, m, 0.5 * dt, rtol, atol, model, opts, stats, &p1);
+    if (r < 0) return r;
+    r = prepare(states, n, m, 0.5 * dt, rtol, atol, model, opts,
+                stats ? stats + (size_t)RD_NSTATS * n : nullptr, &p2);
+    if (r < 0) return r;
+    DiffPlan dp;
+    if (int64_t e = diffusion_plan(m, grid, dt, 0, &dp)) return e;
+    if (n == 0) return 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) { set_error("no current device"); return RD_EDEVICE; }
+
+    std::vector<unsigned char> key;
+    put(key, dev); put(key, s); put(key, states); put(key, stats); put(key, p1.entry);
+    put(key, p1.args.params); put(key, p1.args.P); put(key, p1.grid); put(key, p1.order);
+    put(key, grid->dim); put(key, grid->nx); put(key, grid->ny); put(key, grid->nz);
+    put(key, grid->h); put(key, dt);
+    for (int i = 0; i < m; ++i) put(key, grid->diff[i]);
+
+    StrangGraph run;
+    {
+        std::lock_guard<std::mutex> lk(g_sg_mu);
+        auto it = g_sg.find(key);
+        if (it == g_sg.end()) {
+            StrangGraph g;
+            double* w = nullptr;
+            if (hipMalloc((void**)&g.counters, 4 * sizeof(unsigned long long)) != hipSuccess ||
+                hipHostMalloc((void**)&g.host, 2 * sizeof(unsigned long long), 0) != hipSuccess ||
+                hipMalloc((void**)&g.eps, sizeof(double) * m) != hipSuccess ||
+                hipMemcpy(g.eps, grid->diff, sizeof(double) * m, hipMemcpyHostToDevice) != hipSuccess) {
+                set_error("allocation of the split-step graph failed");
+                free_strang_graph(g);
+                return RD_ENOMEM;
+            }
+            if ((r = ensure_workspace(p1, s)) != 0 || (r = diff_workspace(dev, s, 4 * dp.vec + 256, &w)) != 0) {
+                free_strang_graph(g);
+                return r;
+            }
+            if (hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal); e != hipSuccess) {
+                set_error("hipStreamBeginCapture: %s", hipGetErrorString(e));
+                free_strang_graph(g);
+                return RD_EDEVICE;
+            }
+            int rc = enqueue_prepared(p1, s, g.counters);
+            if (rc == 0 && hipMemcpyAsync(g.host, g.counters + 1, sizeof(unsigned long long),
+                                          hipMemcpyDeviceToHost, s) != hipSuccess)
+                rc = RD_EDEVICE;
+            if (rc == 0) rc = diffusion_launch(states, m, dp, g.eps, w, s);
+            if (rc == 0) rc = enqueue_prepared(p2, s, g.counters + 2);
+            if (rc == 0 && hipMemcpyAsync(g.host + 1, g.counters + 3, sizeof(unsigned long long),
+                                          hipMemcpyDeviceToHost, s) != hipSuccess)
+                rc = RD_EDEVICE;
+            hipGraph_t gr = nullptr;
+            const hipError_t ee = hipStreamEndCapture(s, &gr);
+            if (rc == 0 && ee != hipSuccess) {
+                set_error("hipStreamEndCapture: %s", hipGetErrorString(ee));
+                rc = RD_EDEVICE;
+            }
+            if (rc == 0 && hipGraphInstantiate(&g.exec, gr, nullptr, nullptr, 0) != hipSuccess) {
+                set_error("hipGraphInstantiate failed");
+                rc = RD_EDEVICE;
+            }
+            if (gr) hipGraphDestroy(gr);
+            if (rc != 0) {
+                free_strang_graph(g);
+                return rc;
+            }
+            it = g_sg.emplace(std::move(key), g).first;
+        }
+        run = it->second; /* entries are never erased: the handles stay valid */
+    }
+    if (hipError_t e = hipGraphLaunch(run.exec, s); e != hipSuccess) {
+        set_error("hipGraphLaunch: %s", hipGetErrorString(e));
         return RD_EDEVICE;
     }
-    return sc;
+    if (hipError_t e = hipStreamSynchronize(s); e != hipSuccess) {
+        set_error("hipStreamSynchronize: %s", hipGetErrorString(e));
+        return RD_EDEVICE;
+    }
+    return (int64_t)(run.host[0] + run.host[1]);
 }
 
 }  // namespace rd
@@ -170,9 +303,13 @@ int64_t rd_strang_step(double* states, int32_t m, const rd_grid* grid, double dt
         set_error("per-cell warm start is not supported by the Strang driver");
         return RD_EINVAL;
     }
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (opts && opts->use_graph && s != nullptr) {
+        if (!states && n > 0) { set_error("states is null"); return RD_EINVAL; }
+        return strang_graph_step(states, m, grid, dt, rtol, atol, model, opts, stats, s);
+    }
     /* R, D, R in stream order with no host wait in between; the two failure
      * counts land in pinned host words and are read after one synchronization */
-    hipStream_t s = (hipStream_t)hip_stream;
     const int64_t r1 = reaction_enqueue(states, n, m, 0.5 * dt, rtol, atol, model, opts, stats, s, 0);
     if (r1 < 0) return r1;
     const int64_t sd = diffusion_enqueue(states, m, grid, dt, 0, s);

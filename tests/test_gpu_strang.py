@@ -88,3 +88,38 @@ def test_complexity_on_strang_evolved_field(rd):
     s = CX.summary(c)
     say("complexity after Strang evolution", s)
     assert s["min"] >= 8 and 0.0 < s["time_share_below_17"] <= 1.0
+
+
+def test_strang_graph_replay_matches_eager(rd):
+    """The whole split step recorded as one graph (both reaction halves with
+    their claim-order passes, the diffusion stages, the failure counts): every
+    replay, with the program's own eager work in between, gives the eager
+    step's states, counters and failure count bitwise; a second states buffer
+    records a graph of its own."""
+    N = 128
+    shape, h = (N, N), 1.0 / N
+    w = W.oregonator_2d_paper(side=N, dt=1e-3)
+    u0 = torch.tensor(w.states, dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+    ref = u0.clone()
+    st_ref = torch.zeros((2, 9, w.n), dtype=torch.int32, device="cuda")
+    say("strang eager reference", shape)
+    with torch.cuda.stream(s):
+        r_ref = rd.strang_step(ref, shape, h, BZ_DIFF, w.dt, w.rtol, w.atol, w.kind, w.params,
+                               stats=st_ref, stream=s)
+    s.synchronize()
+    bufs = [torch.empty_like(u0), torch.empty_like(u0)]
+    st = torch.zeros_like(st_ref)
+    for rep in range(5):
+        u = bufs[0] if rep < 4 else bufs[1]
+        say("strang graph replay", rep)
+        with torch.cuda.stream(s):
+            u.copy_(u0)
+            st.zero_()
+            r = rd.strang_step(u, shape, h, BZ_DIFF, w.dt, w.rtol, w.atol, w.kind, w.params,
+                               stats=st, stream=s, use_graph=True)
+        s.synchronize()
+        assert r == r_ref
+        assert torch.equal(u, ref) and torch.equal(st, st_ref)
+        torch.cuda.synchronize()
+        _ = (u0 * 2.0).sum().item()
