@@ -45,7 +45,13 @@ def load():
         return _lib
     if not os.path.exists(LIB):
         build_oracle()
-    lib = ctypes.CDLL(LIB)
+    _lib = bind(ctypes.CDLL(LIB))
+    return _lib
+
+
+def bind(lib):
+    """Declare the argument and result types of the oracle's entry points on
+    a loaded library (also used by the tests for separately built copies)."""
     lib.rdo_reaction_step.restype = ctypes.c_int64
     lib.rdo_reaction_step.argtypes = [
         ctypes.POINTER(ctypes.c_double), ctypes.c_int64, ctypes.c_int32,
@@ -64,7 +70,6 @@ def load():
                                    ctypes.POINTER(ctypes.c_double)]
     lib.rdo_constants.restype = None
     lib.rdo_constants.argtypes = [ctypes.POINTER(ctypes.c_double)]
-    _lib = lib
     return lib
 
 

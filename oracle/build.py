@@ -12,15 +12,20 @@ SRC = os.path.join(HERE, "radau5_oracle.cpp")
 LIB = os.path.join(HERE, "liboracle.so")
 
 
-def build_oracle(verbose: bool = False) -> str:
+def compile_oracle(src: str, out: str, verbose: bool = False) -> str:
+    """Compile an oracle source file into the shared library `out`."""
     cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math",
            "-fPIC", "-shared", "-pthread", "-Wall", "-Wextra",
-           "-o", LIB + ".tmp", SRC]
+           "-I", HERE, "-o", out + ".tmp", src]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def build_oracle(verbose: bool = False) -> str:
+    return compile_oracle(SRC, LIB, verbose)
 
 
 if __name__ == "__main__":

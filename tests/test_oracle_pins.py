@@ -418,3 +418,25 @@ def test_p9_nagumo_derivative_bound(orc):
     for u in np.linspace(0, 1, 101):
         _, J = orc.model_eval(orc.NAGUMO, [k], np.array([u]))
         assert abs(J[0, 0]) <= 3 * k
+
+
+# ---------------------------------------------------------------------------
+# P10 simplified Newton on linear problems
+# ---------------------------------------------------------------------------
+def test_p10_linear_newton_exact_in_one_iteration(orc):
+    """For f = K u the stage equations are linear, and the simplified Newton
+    matrix I - h A (x) K is their exact matrix: the first iteration solves
+    them, the second increment is rounding (its contraction theta is tiny),
+    so a step from zero start values takes exactly two iterations, and no
+    adaptive step needs more (HW §IV.8).  A wrong operand in the Newton
+    matrix (a transposed J or A) slows the contraction and shows here."""
+    rng = np.random.default_rng(12)
+    for m in (3, 5):
+        K = rng.normal(size=(m, m)) * 3.0 - 8.0 * np.eye(m)
+        K[0, m - 1] += 40.0  # strongly nonsymmetric
+        y0 = rng.uniform(0.2, 1.0, m)
+        for h in (0.05, 0.4):
+            y1, _, k, failed = orc.single_step(y0, h, 1e-6, 1e-9, orc.LINEAR, K, tol_transform=0)
+            assert not failed and k == 2, (m, h, k)
+        y, st, ret = orc.reaction_step(y0[:, None], 2.0, 1e-6, 1e-9, orc.LINEAR, K)
+        assert ret == 0 and st[8, 0] <= 2 * st[1, 0], st[:, 0]
