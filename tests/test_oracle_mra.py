@@ -304,3 +304,64 @@ def test_thresholds_match_the_paper():
             U[0, node * span:(node + 1) * span] = vcrit * f
             _, _, counts = M.leaves(U, d, J, eps)
             assert counts[j] == want, (d, J, j, f, counts)
+
+
+def test_prediction_at_the_domain_edges():
+    """tests/golden/mr_prediction_edges_1d.txt: at the two ends of a row the
+    missing coarse neighbour is the edge node itself (even reflection across
+    the boundary face), worked by hand; checked on a 2D level that varies
+    only along x, at both children of the first and of the last node."""
+    rows = np.loadtxt(os.path.join(GOLDEN, "mr_prediction_edges_1d.txt"))
+    d, jc = 2, 3
+    N = 1 << jc
+    co = M.deinterleave(np.arange(N * N), d, jc)
+    for side, ue, ui, c0, c1 in rows:
+        xs = np.full(N, 5.0)
+        k = 0 if side == 0 else N - 1
+        xs[k] = ue
+        xs[1 if side == 0 else N - 2] = ui
+        Uc = xs[co[0]][None, :]
+        for cx, want in ((0, c0), (1, c1)):
+            child = M.interleave((np.array([2 * k + cx]), np.array([7])), jc + 1)
+            assert M.predict(Uc, d, jc, child)[0][0] == want, (side, cx)
+
+
+def test_thresholds_average_over_species():
+    """The detail norm is the mean over species of (d_i / s_i)^2 (R28): with
+    a second, identically zero species the leaf transition of the single-node
+    field of the threshold test moves to (1 - 2^-d) v = sqrt(2) eps_j."""
+    d, J, j, eps = 2, 6, 4, 1e-3
+    eps_j = eps * 2.0 ** ((d / 2) * (j - J))
+    half = 1 << (j - 1)
+    node = int(M.interleave(tuple(np.array([half]) for _ in range(d)), j)[0])
+    span = 1 << (d * (J - j))
+    vcrit = np.sqrt(2.0) * eps_j / (1.0 - 2.0 ** -d)
+    for f, want in ((1 + 1e-9, 1 << d), (1 - 1e-9, 0)):
+        U = np.zeros((2, 1 << (d * J)))
+        U[0, node * span:(node + 1) * span] = vcrit * f
+        _, _, counts = M.leaves(U, d, J, eps)
+        assert counts[j] == want, (f, counts)
+
+
+@pytest.mark.parametrize("d,J", [(2, 6), (3, 4)])
+def test_grading_around_an_isolated_cell(d, J):
+    """One nonzero fine cell: the tree refines down to it, and every node
+    with children has the parents of all its 3^d neighbours refined too
+    (R30), on every side of the feature."""
+    N = 1 << J
+    U = np.zeros((1, 1 << (d * J)))
+    c = tuple(np.array([N // 2 - 1 + a]) for a in range(d))
+    U[0, M.interleave(c, J)[0]] = 1.0
+    levels = M.project(U, d, J)
+    dets = M.details(levels, d, J)
+    R = M.refine_flags(levels, dets, d, J, 1e-3, np.ones(1))
+    assert R[J - 1].any()
+    for j in range(1, J):
+        ks = np.nonzero(R[j])[0]
+        co = M.deinterleave(ks, d, j)
+        for off in np.ndindex(*([3] * d)):
+            nb = [co[a] + off[a] - 1 for a in range(d)]
+            ok = np.ones(ks.size, dtype=bool)
+            for a in range(d):
+                ok &= (nb[a] >= 0) & (nb[a] < (1 << j))
+            assert np.all(R[j - 1][M.interleave(tuple(cc[ok] for cc in nb), j) >> d]), (j, off)

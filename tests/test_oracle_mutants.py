@@ -1,12 +1,14 @@
 """Mutation check of the oracle's pins (CPU, no GPU).
 
-The pins in test_oracle_pins.py are meant to catch a dropped term, a wrong
-sign or index, or a transposed operand anywhere in the oracle.  This test
-plants such mistakes, one at a time, in a copy of the oracle's source,
-compiles each copy with the oracle's own build flags, binds it in place of
-the oracle, and runs the pins against it: every planted mistake must make at
-least one pin fail.  The unmodified source goes through the same pipeline and
-must pass every pin, so a failure is the planted mistake's doing.
+The pins (test_oracle_pins.py, test_oracle_mra.py, test_oracle_diffusion.py)
+are meant to catch a dropped term, a wrong sign or index, or a transposed
+operand anywhere in the oracle.  This test plants such mistakes, one at a
+time, in a copy of an oracle source: the C++ Radau5 oracle (compiled with the
+oracle's own build flags and bound in place of the oracle), the
+multiresolution and the diffusion oracles (imported under another name and
+put in place of the module the pins call).  Every planted mistake must make
+at least one pin fail.  The unmodified sources go through the same pipelines
+and must pass every pin, so a failure is the planted mistake's doing.
 
 Not planted: the step-size controller's constants, the Newton stopping
 tolerance, the Newton start values and the pivot choice.  They steer which
@@ -139,3 +141,125 @@ def test_planted_mistake_fails_a_pin(builds, name):
     failed = _run_pins(builds[name])
     print(f"{name}: caught by {failed}")
     assert failed, f"no pin catches the planted mistake '{name}'"
+
+
+# ---------------------------------------------------------------------------
+# The Python oracles: multiresolution (oracle/mra.py) and diffusion
+# (oracle/diffusion.py).  A mutated copy is imported under another name and
+# put in place of the module the pins call.
+# ---------------------------------------------------------------------------
+PY_MUTANTS = {
+    "mra": [
+        ("projection weight", "levels[j - 1] = s * (1.0 / nc)", "levels[j - 1] = s * (1.0 / (nc - 1))"),
+        ("prediction sign", "sgn = [np.where(s == 0, 0.125, -0.125) for s in sub]",
+         "sgn = [np.where(s == 0, -0.125, 0.125) for s in sub]"),
+        ("prediction y difference", "        return rows[0] + sgn[1] * (rows[-1] - rows[1])",
+         "        return rows[0] + sgn[1] * (rows[1] - rows[-1])"),
+        ("prediction 3D z weight", "    return planes[0] + sgn[2] * (planes[-1] - planes[1])",
+         "    return planes[0] + sgn[1] * (planes[-1] - planes[1])"),
+        ("edge reflection", "c = np.where(c < 0, 0, np.where(c >= N, N - 1, c))",
+         "c = np.where(c < 0, 1, np.where(c >= N, N - 1, c))"),
+        ("detail sign", "out[j] = levels[j] - predict(levels[j - 1], d, j - 1, k)",
+         "out[j] = levels[j] + predict(levels[j - 1], d, j - 1, k)"),
+        ("detail norm mean", "return acc * (1.0 / m)", "return acc"),
+        ("threshold exponent", "eps_j2 = (eps * eps) * np.ldexp(1.0, d * (j - J))",
+         "eps_j2 = (eps * eps) * np.ldexp(1.0, (j - J))"),
+        ("children test any", "R[j - 1] |= sig.reshape(-1, nc).any(axis=1)",
+         "R[j - 1] |= sig.reshape(-1, nc).all(axis=1)"),
+        ("grading neighbourhood", "nb = [coords[a] + off[a] - 1 for a in range(d)]",
+         "nb = [coords[a] + off[a] for a in range(d)]"),
+        ("Morton bit order", "out |= ((np.asarray(c, dtype=np.int64) >> b) & 1) << (d * b + (d - 1 - a))",
+         "out |= ((np.asarray(c, dtype=np.int64) >> b) & 1) << (d * b + a)"),
+        ("key level field", "lev = np.uint64(j << KEY_LEVEL_SHIFT)", "lev = np.uint64(j << (KEY_LEVEL_SHIFT + 1))"),
+        ("tree parent average", "tree_val[j - 1][:, par] = s * (1.0 / nc)",
+         "tree_val[j - 1][:, par] = s * (1.0 / (nc + 1))"),
+    ],
+    "diffusion": [
+        ("Chebyshev second derivative", "d2T[j + 1] = 4 * dT[j] + 2 * x * d2T[j] - d2T[j - 1]",
+         "d2T[j + 1] = 2 * dT[j] + 2 * x * d2T[j] - d2T[j - 1]"),
+        ("w1 inverted", "w1 = dT[s] / d2T[s]", "w1 = d2T[s] / dT[s]"),
+        ("nu sign", "nu[j] = -b[j] / b[j - 2]", "nu[j] = b[j] / b[j - 2]"),
+        ("gamma index", "gamt[j] = -a[j - 1] * mut[j]", "gamt[j] = -a[j] * mut[j]"),
+        ("Laplacian flux sign", "out[tuple(hi)] -= fwd", "out[tuple(hi)] += fwd"),
+        ("Laplacian scale", "return (out / (h * h)).ravel()", "return (out / h).ravel()"),
+        ("first stage weight", 'y_prev = y0 + c["mut"][1] * dt * F0', "y_prev = y0 + dt * F0"),
+        ("stage uses Y0 twice", 'c["nu"][j] * y_prev2 + c["mut"][j] * dt * Fj',
+         'c["nu"][j] * y0 + c["mut"][j] * dt * Fj'),
+        ("damping", "w0 = 1.0 + eps / (s * s)", "w0 = 1.0 + eps / s"),
+    ],
+}
+
+
+def _py_pins(kind, orc):
+    from tests import test_oracle_diffusion as PD
+    from tests import test_oracle_mra as PM
+    if kind == "mra":
+        return PM, "M", [
+            ("Morton order", lambda: PM.test_morton_order_and_round_trip(2, 3)),
+            ("Morton order 3D", lambda: PM.test_morton_order_and_round_trip(3, 2)),
+            ("quadratic prediction 2D", lambda: PM.test_prediction_exact_for_quadratics(2)),
+            ("quadratic prediction 3D", lambda: PM.test_prediction_exact_for_quadratics(3)),
+            ("projection", lambda: PM.test_projection_is_the_average_of_covered_cells(2, 5)),
+            ("leaf set", lambda: PM.test_leaf_set_properties(2, 6, 1e-3)),
+            ("leaf set 3D", lambda: PM.test_leaf_set_properties(3, 4, 1e-3)),
+            ("reconstruction", lambda: PM.test_reconstruction(2, 6)),
+            ("adapt idempotent", lambda: PM.test_adapt_without_refinement_is_idempotent(2, 6, 1e-3)),
+            ("1D prediction golden", lambda: PM.test_prediction_matches_the_paper_1d_operator()),
+            ("thresholds golden", lambda: PM.test_thresholds_match_the_paper()),
+            ("edge prediction golden", lambda: PM.test_prediction_at_the_domain_edges()),
+            ("species mean", lambda: PM.test_thresholds_average_over_species()),
+            ("grading isolated 2D", lambda: PM.test_grading_around_an_isolated_cell(2, 6)),
+            ("grading isolated 3D", lambda: PM.test_grading_around_an_isolated_cell(3, 4)),
+        ]
+    return PD, "D", [
+        ("stability polynomial", lambda: PD.test_rkc_stability_polynomial(5)),
+        ("second order", lambda: PD.test_rkc_second_order(4)),
+        ("stage rule", lambda: PD.test_rkc_stage_rule_is_stable(400.0)),
+        ("Laplacian", lambda: PD.test_laplacian_constants_mass_and_modes((16, 12))),
+        ("step on a mode", lambda: PD.test_diffusion_step_on_a_mode_and_mass()),
+        ("Strang order", lambda: PD.test_strang_second_order_self_convergence(orc)),
+    ]
+
+
+def _run_py_pins(kind, text, orc, tmp_dir, stop_at_first=True):
+    import importlib.util
+    path = os.path.join(tmp_dir, f"mut_{kind}_{abs(hash(text))}.py")
+    with open(path, "w") as fh:
+        fh.write(text)
+    spec = importlib.util.spec_from_file_location(f"oracle_mut_{kind}", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    pins_mod, attr, pins = _py_pins(kind, orc)
+    saved = getattr(pins_mod, attr)
+    setattr(pins_mod, attr, mod)
+    failed = []
+    try:
+        with np.errstate(all="ignore"):
+            for name, pin in pins:
+                try:
+                    pin()
+                except Exception:
+                    failed.append(name)
+                    if stop_at_first:
+                        break
+    finally:
+        setattr(pins_mod, attr, saved)
+    return failed
+
+
+def _py_source(kind):
+    with open(os.path.join(os.path.dirname(SRC), f"{kind}.py")) as fh:
+        return fh.read()
+
+
+@pytest.mark.parametrize("kind", ["mra", "diffusion"])
+def test_unmodified_python_oracle_passes_every_pin(orc, tmp_path, kind):
+    assert _run_py_pins(kind, _py_source(kind), orc, tmp_path, stop_at_first=False) == []
+
+
+@pytest.mark.parametrize("kind,name", [(k, m[0]) for k in PY_MUTANTS for m in PY_MUTANTS[k]])
+def test_planted_mistake_in_python_oracle_fails_a_pin(orc, tmp_path, kind, name):
+    old, new = next((o, n) for nm, o, n in PY_MUTANTS[kind] if nm == name)
+    failed = _run_py_pins(kind, _apply(_py_source(kind), old, new), orc, tmp_path)
+    print(f"{kind} / {name}: caught by {failed}")
+    assert failed, f"no pin catches the planted mistake '{name}' in oracle/{kind}.py"
