@@ -10,7 +10,7 @@ work-stealing kernel; the one-launch-per-batch schedule and the mixed
 precision path are timed beside it.
 
 Prints ONE JSON line (see the keys below).  --gpus N with N > 1 exits: the
-reaction step needs no communication and this build measures one GPU.
+reaction step needs no communication, and the benchmark runs on one GPU.
 """
 import argparse
 import hashlib
