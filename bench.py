@@ -69,6 +69,28 @@ def time_path(rd, torch, w, u0, steps, warmup, **opts):
             "value": w.n * steps / wall, "out": u}
 
 
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def step_histogram(nstep):
+    """Per-cell step counts (attempts) of one launch: octave bins and
+    percentiles."""
+    import numpy as np
+    edges = [1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1 << 30]
+    counts, _ = np.histogram(nstep, bins=edges)
+    return {"bin_lo": edges[:-1], "cells": [int(c) for c in counts],
+            "p50": float(np.percentile(nstep, 50)), "p90": float(np.percentile(nstep, 90)),
+            "p99": float(np.percentile(nstep, 99)), "max": int(nstep.max())}
+
+
 def kernel_source_sha():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1506_04651_amd", "csrc")
@@ -217,6 +239,18 @@ def main():
         cpu = {"value": passes * s.n / el, "unit": "cell-integrations/s", "cores": nth,
                "kind": "oracle",
                "sample": f"{s.n} cells of {w.name} (seeded sample), {passes} passes, {el:.1f} s"}
+        # one host core, on a smaller seeded sample, about 2 s
+        n1 = min(w.n, 16384 if w.m <= 4 else 64)
+        s1 = w.subset(W.sample_indices(w.n, n1, 78)) if n1 < w.n else w
+        passes, el = 0, 0.0
+        while passes == 0 or el < 2.0:
+            t0 = time.perf_counter()
+            oracle.reaction_step(s1.states, s1.dt, s1.rtol, s1.atol, s1.kind, s1.params, nthreads=1)
+            el += time.perf_counter() - t0
+            passes += 1
+        cpu["one_core"] = {"value": passes * s1.n / el,
+                           "sample": f"{s1.n} cells (seeded sample), {passes} passes, {el:.1f} s"}
+        cpu["cpu_model"] = host_cpu_model()
 
     line = {
         "metric": METRIC,
@@ -248,6 +282,7 @@ def main():
         "compare": compare,
         "autotune_ms": tuning,
         "counters_mean": {k: float(stats[i].mean()) for i, k in enumerate(rd.STAT_NAMES)},
+        "nstep_hist": step_histogram(stats[1]),
     }
     print(json.dumps(line), flush=True)
 
