@@ -11,13 +11,17 @@ from .build import BUILD, HIPCC
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def main():
+def build() -> str:
     os.makedirs(BUILD, exist_ok=True)
     exe = os.path.join(BUILD, "peak_probe")
     subprocess.run([HIPCC, "--offload-arch=gfx950", "-O3", "-Xclang", "-target-feature",
                     "-Xclang", "-packed-fp32-ops", os.path.join(HERE, "peak_probe.hip"), "-o", exe],
                    check=True, capture_output=True)
-    return subprocess.run([exe]).returncode
+    return exe
+
+
+def main():
+    return subprocess.run([build()]).returncode
 
 
 if __name__ == "__main__":
