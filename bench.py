@@ -166,7 +166,8 @@ def main():
                       if (p, s) != (prec, sched)]
         for p, s in paths:
             log("autotune precision", p, "schedule", s)
-            r = autotune.tune(u0, w.dt, w.rtol, w.atol, w.kind, w.params, p, s, reps=2)
+            r = autotune.tune(u0, w.dt, w.rtol, w.atol, w.kind, w.params, p, s,
+                              reps=7 if w.m <= 4 else 2)
             tuning[f"precision{p}_schedule{s}"] = {r["names"][v]: round(ms, 4)
                                                    for v, ms in r["ms"].items()}
 

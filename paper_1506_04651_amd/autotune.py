@@ -34,22 +34,26 @@ def _device_name():
     return torch.cuda.get_device_name(0)
 
 
+def _launch_ms(u, states0, dt, rtol, atol, kind, params, precision, schedule, variant):
+    """Milliseconds of one step of one variant on a fresh copy of the states."""
+    import torch
+    stream = torch.cuda.current_stream()
+    u.copy_(states0)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    api.reaction_step(u, dt, rtol, atol, kind, params, precision=precision,
+                      schedule=schedule, variant=variant, async_=True)
+    b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b)
+
+
 def time_variant(states0, dt, rtol, atol, kind, params, precision, schedule, variant, reps=3):
     """Median milliseconds of `reps` launches of one variant (after one warm-up)."""
     import torch
     u = torch.empty_like(states0)
-    stream = torch.cuda.current_stream()
-    times = []
-    for i in range(reps + 1):
-        u.copy_(states0)
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        api.reaction_step(u, dt, rtol, atol, kind, params, precision=precision,
-                          schedule=schedule, variant=variant, async_=True)
-        b.record(stream)
-        b.synchronize()
-        if i:
-            times.append(a.elapsed_time(b))
+    times = [_launch_ms(u, states0, dt, rtol, atol, kind, params, precision, schedule, variant)
+             for _ in range(reps + 1)][1:]
     times.sort()
     return times[len(times) // 2], u
 
@@ -64,24 +68,38 @@ def tune(states0, dt, rtol, atol, kind, params, precision=FP64, schedule=PERSIST
     m = int(states0.shape[0])
     nv = api.variant_count(kind, m, precision, schedule)
     res = {"ms": {}, "names": {}, "rejected": []}
+    # correctness first: one launch of each variant, compared with variant 1
     ref = None
+    u = torch.empty_like(states0)
+    ok = []
     for v in range(1, nv + 1):
-        if api.variant_name(kind, m, precision, schedule, v) is None:
-            continue
-        ms, out = time_variant(states0, dt, rtol, atol, kind, params, precision, schedule, v, reps)
         name = api.variant_name(kind, m, precision, schedule, v)
+        if name is None:
+            continue
+        _launch_ms(u, states0, dt, rtol, atol, kind, params, precision, schedule, v)
         if ref is None:
-            ref = out.clone()
-        elif not torch.equal(out, ref):
+            ref = u.clone()
+        elif not torch.equal(u, ref):
             res["rejected"].append(v)
             if verbose:
                 print(f"  variant {v} {name}: output differs from variant 1, rejected",
                       file=sys.stderr)
             continue
-        res["ms"][v] = ms
+        ok.append(v)
         res["names"][v] = name
+    # then `reps` rounds over all variants, so that clock and cache drift
+    # falls on every variant alike; the median per variant
+    times = {v: [] for v in ok}
+    for _ in range(reps):
+        for v in ok:
+            times[v].append(_launch_ms(u, states0, dt, rtol, atol, kind, params, precision,
+                                       schedule, v))
+    for v in ok:
+        t = sorted(times[v])
+        res["ms"][v] = t[len(t) // 2]
         if verbose:
-            print(f"  variant {v:2d} {name:45s} {ms:8.3f} ms", file=sys.stderr, flush=True)
+            print(f"  variant {v:2d} {res['names'][v]:45s} {res['ms'][v]:8.3f} ms",
+                  file=sys.stderr, flush=True)
     best = min(res["ms"], key=res["ms"].get)
     res["best"] = best
     if apply:
