@@ -6,14 +6,14 @@ substep length, the schedule and the claim order, runs the reaction step on
 the GPU (FP64) and in the oracle on the same states, and checks: the same
 failed-cell count and per-cell status codes, and every cell within the
 tolerance scale of the oracle, |y - y_oracle| <= 10 (atol + rtol |y_oracle|)
-per component.  That is the bar here rather than 1e-8 relative: in some of
-these regimes (strict tolerances on smooth linear problems) the step-size
-controller settles where the ratio of new to old step is within rounding of
-1, the threshold of keeping the step and its factorization, so GPU and oracle
-rounding take that decision differently in many cells and their step
-sequences separate at the level of the local error tolerance (the
-identical-decision parity at 1e-8 is checked on the workloads of the other
-tests).  The share of cells with identical counters is reported."""
+per component.  That is the bar here rather than 1e-8 relative: smooth
+linear problems at strict tolerances approach two thresholds gradually (the
+first-iteration Newton test, whose factor grows while steps converge in one
+iteration, and the controller's keep-the-step test), so GPU and oracle
+rounding cross them at different steps in many cells and the step sequences
+separate at the level of the local error tolerance (the identical-decision
+parity at 1e-8 is checked on the workloads of the other tests).  The share
+of cells with identical counters is reported."""
 import numpy as np
 import pytest
 
