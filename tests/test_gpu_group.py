@@ -52,13 +52,13 @@ def test_kinetics16_full_batch_sampled(rd, orc):
     say("kinetics16 full batch n", w.n)
     y, st, ret = run_gpu(rd, w)
     assert ret == 0
-    idx = W.sample_indices(w.n, 1024, 41)
+    idx = W.sample_indices(w.n, 8192, 41)
     s = w.subset(idx)
     yo, sto, reto = run_oracle(orc, s)
     assert reto == 0
     rep = compare(y[:, idx], st[:, idx], yo, sto, w.atol, label="kin16 full sampled")
     assert rep["max_err_same_trace"] <= 1e-8
-    assert rep["trace_divergent"] <= 4
+    assert rep["trace_divergent"] <= 16
     # invariant of every cell at any size: with G >= 0 and 1^T K = 0 the total
     # mass can only decrease, by the quadratic loss term
     s0, s1 = w.states.sum(axis=0), y.sum(axis=0)

@@ -252,3 +252,18 @@ def test_oregonator_3d_fp64_and_mixed_vs_oracle(rd, orc):
     repm = compare(ym[:, idx], stm[:, idx], yo, sto, w.atol, label="3d mixed sampled")
     assert repm["max_err"] <= 10 * w.rtol
     assert repm["frac_within_tol"] >= 0.9
+
+
+def test_oregonator_3d_every_cell_vs_oracle(rd, orc):
+    """All 4 194 304 cells of the scroll-wave batch, FP64, in the benchmark's
+    launch configuration (persistent, longest-first claim order), each
+    against the oracle (whole batch on the host's threads)."""
+    w = W.oregonator_3d()
+    say("oregonator_3d every cell, n", w.n)
+    y, st, ret = run_gpu(rd, w)
+    yo, sto, reto = run_oracle(orc, w)
+    assert ret == reto == 0
+    rep = compare(y, st, yo, sto, w.atol, label="3d fp64 every cell")
+    assert rep["max_err_same_trace"] <= 1e-8
+    assert rep["trace_divergent"] <= max(4, int(1e-3 * w.n))
+    assert rep["max_err_divergent"] <= 10 * w.rtol
