@@ -239,7 +239,9 @@ def main():
             passes += 1
         cpu = {"value": passes * s.n / el, "unit": "cell-integrations/s", "cores": nth,
                "kind": "oracle",
-               "sample": f"{s.n} cells of {w.name} (seeded sample), {passes} passes, {el:.1f} s"}
+               "sample": (f"all {s.n} cells of {w.name}" if ns == w.n else
+                          f"{s.n} cells of {w.name} (seeded sample)") +
+                         f", {passes} passes, {el:.1f} s"}
         # one host core, on a smaller seeded sample, about 2 s
         n1 = min(w.n, 16384 if w.m <= 4 else 64)
         s1 = w.subset(W.sample_indices(w.n, n1, 78)) if n1 < w.n else w
