@@ -208,6 +208,9 @@ static void scheduler(rd_session* s) {
             admitted_any = true;
             if (!launch_request(s, r)) {
                 set_error("session launch failed");
+                /* part of the request may be queued: let it drain before its
+                 * arena range can be handed to another request */
+                hipStreamSynchronize(s->streams[r->stream]);
                 complete(s, r, RD_EDEVICE);
                 s->cv_done.notify_all();
             } else {
