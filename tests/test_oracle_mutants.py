@@ -26,6 +26,8 @@ import pytest
 
 import oracle
 from oracle.build import SRC, compile_oracle
+from paper_1506_04651_amd import workloads as W
+from tests import test_oracle_fd_bytecode as PF
 from tests import test_oracle_pins as P
 
 # (name, text in radau5_oracle.cpp, replacement)
@@ -68,6 +70,20 @@ MUTANTS = [
     ("kinetics loss transposed", "loss += G[i * m + j] * y[j];",
      "loss += G[j * m + i] * y[j];"),
     ("Robertson f3 index", "out[2] = k3 * y[1] * y[1];", "out[2] = k3 * y[1] * y[2];"),
+    # the extensions: forward-difference Jacobian, bytecode model, warm start
+    ("FD increment without sqrt",
+     "const double dj = std::sqrt(2.220446049250313e-16 * std::max(1e-5, std::fabs(y[j])));",
+     "const double dj = 2.220446049250313e-16 * std::max(1e-5, std::fabs(y[j]));"),
+    ("FD column transposed", "J[i * m + j] = (fp[i] - fy[i]) / dj;",
+     "J[j * m + i] = (fp[i] - fy[i]) / dj;"),
+    ("bytecode SUB operands", "case RDO_BC_SUB: r[d] = r[a] - r[b]; break;",
+     "case RDO_BC_SUB: r[d] = r[b] - r[a]; break;"),
+    ("bytecode POW operands", "case RDO_BC_POW: r[d] = std::pow(r[a], r[b]); break;",
+     "case RDO_BC_POW: r[d] = std::pow(r[b], r[a]); break;"),
+    ("bytecode writes constants", "            if (d < m + C) return false;\n            written[d] = true;",
+     "            written[d] = true;"),
+    ("warm start ignored", "integrate_(y, dt, st, h_pre, h_io && *h_io > 0.0 ? *h_io : 0.0);",
+     "integrate_(y, dt, st, h_pre, 0.0);"),
 ]
 
 # the pins, each a call on the bound oracle module
@@ -85,6 +101,14 @@ PINS = [
     ("p9 models", lambda o: P.test_p9_models_against_finite_differences(o)),
     ("p10 Newton", lambda o: P.test_p10_linear_newton_exact_in_one_iteration(o)),
     ("p8 brute force", lambda o: P.test_p8_brute_force_oregonator(o, "2d", 6)),
+    ("FD vs analytic", lambda o: PF.test_fd_jacobian_matches_analytic(o, "oregonator")),
+    ("FD increment", lambda o: PF.test_fd_increment(o, 2e-5)),
+    ("bytecode random programs", lambda o: PF.test_bytecode_random_programs(o, 3)),
+    ("bytecode like built-in", lambda o: PF.test_bytecode_integrates_like_builtin(
+        o, lambda: W.robertson_program(), 5, [0.04, 1e4, 3e7], 3)),
+    ("bytecode rejects", lambda o: PF.test_bytecode_invalid_programs_rejected(
+        o, np.array([2, 1, 2.0, W.BC_ADD, 1, 0, 0, W.BC_OUT, 0, 1, 0], dtype=float), 1)),
+    ("warm start equals h0", lambda o: PF.test_warm_start_equals_h0(o)),
 ]
 
 
