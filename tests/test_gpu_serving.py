@@ -45,9 +45,9 @@ def small_stream(pools, n_req, seed, max_cells):
 
 def test_mix_equals_alone(rd, pools):
     from paper_1506_04651_amd import serving
-    reqs = small_stream(pools, 40, 3, 20000)
+    reqs = small_stream(pools, 50, 3, 20000)
     budget = 4 << 20  # small: admission has to wait for earlier requests
-    say("serving mix, 40 requests, budget", budget)
+    say("serving mix, 50 requests, budget", budget)
     with rd.Session(budget, n_streams=4, precision=rd.MIXED) as s:
         recs, wall, outs = serving.replay(s, reqs, pools, time_scale=1.0, keep_outputs=True)
     assert all(r is not None and r["status"] == 0 for r in recs)
