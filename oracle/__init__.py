@@ -68,6 +68,10 @@ def bind(lib):
     lib.rdo_model_eval.argtypes = [ctypes.POINTER(_Model), ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_double)]
+    lib.rdo_start_values.restype = ctypes.c_int32
+    lib.rdo_start_values.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                     ctypes.c_double, ctypes.c_double,
+                                     ctypes.POINTER(ctypes.c_double)]
     lib.rdo_constants.restype = None
     lib.rdo_constants.argtypes = [ctypes.POINTER(ctypes.c_double)]
     return lib
@@ -135,6 +139,22 @@ def single_step(y0, h, rtol, atol, kind, params, tol_transform=1, newton_max=7):
     if rc != 0:
         raise ValueError(f"rdo_single_step returned {rc}")
     return y1, (float(err[0]), float(err[1])), int(info[0]), bool(info[1])
+
+
+def start_values(zold, h, h_old):
+    """Newton start values of the next step (test hook): ``zold`` [3, m] are
+    the stage increments of the last accepted step of size ``h_old``; returns
+    the [3, m] increments of the collocation cubic continued over a step h."""
+    lib = load()
+    zold = np.ascontiguousarray(zold, dtype=np.float64)
+    if zold.ndim != 2 or zold.shape[0] != 3:
+        raise ValueError("zold must be [3, m]")
+    m = zold.shape[1]
+    z = np.zeros((3, m))
+    rc = lib.rdo_start_values(_dptr(zold), m, float(h), float(h_old), _dptr(z))
+    if rc != 0:
+        raise ValueError(f"rdo_start_values returned {rc}")
+    return z
 
 
 def model_eval(kind, params, y, m=None):

@@ -817,6 +817,22 @@ extern "C" int32_t rdo_single_step(const double* y0, int32_t m, double h,
     return 0;
 }
 
+extern "C" int32_t rdo_start_values(const double* zold, int32_t m, double h,
+                                    double h_old, double* z) {
+    if (!zold || !z || m < 1 || !(h > 0.0) || !(h_old > 0.0)) return RDO_EINVAL;
+    Model md;
+    md.kind = RDO_LINEAR;
+    md.m = m;
+    md.p.assign((size_t)m * m, 0.0);
+    const Tols tl = make_tols(1e-6, 1e-6, 1);
+    Opts op;
+    Cell cell(md, tl, op);
+    std::copy(zold, zold + 3 * m, cell.zold.begin());
+    cell.start_values(h, true, h_old);
+    std::copy(cell.Z.begin(), cell.Z.end(), z);
+    return 0;
+}
+
 extern "C" int32_t rdo_model_eval(const rdo_model* model, const double* y,
                                   double* f, double* J) {
     Model md;

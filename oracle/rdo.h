@@ -119,6 +119,14 @@ int32_t rdo_single_step(const double* y0, int32_t m, double h, double rtol,
                         const rdo_model* model, double* y1, double* err,
                         int32_t* info);
 
+/* Newton start values (test hook): the stage increments zold[3][m] of the
+ * last accepted step of size h_old define the collocation cubic q(s), s in
+ * units of h_old from the end of that step: q(-1) = -z3, q(c_i - 1) = z_i - z3
+ * (i = 1, 2), q(0) = 0.  Writes z[i*m + r] = q(c_i h / h_old) for the next
+ * step of size h (Hairer & Wanner §IV.8, starting values).  0 or RDO_EINVAL. */
+int32_t rdo_start_values(const double* zold, int32_t m, double h, double h_old,
+                         double* z);
+
 /* Model hook (tests): f(y) into f[m] and the Jacobian into J[m*m]
  * (row-major, J[i*m+j] = d f_i / d y_j); either output may be null. */
 int32_t rdo_model_eval(const rdo_model* model, const double* y, double* f,

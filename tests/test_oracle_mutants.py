@@ -11,7 +11,7 @@ at least one pin fail.  The unmodified sources go through the same pipelines
 and must pass every pin, so a failure is the planted mistake's doing.
 
 Not planted: the step-size controller's constants, the Newton stopping
-tolerance, the Newton start values and the pivot choice.  They steer which
+tolerance and the pivot choice.  They steer which
 steps and iterations are taken, not what a step computes, and the paper does
 not fix them; the pins see them only through accuracy, which such changes
 keep (a planted change of the stopping tolerance passes every pin: parity
@@ -82,6 +82,13 @@ MUTANTS = [
      "case RDO_BC_POW: r[d] = std::pow(r[b], r[a]); break;"),
     ("bytecode writes constants", "            if (d < m + C) return false;\n            written[d] = true;",
      "            written[d] = true;"),
+    # Newton start values: the collocation cubic of the last accepted step
+    ("start values node", "const double sn[4] = {-1.0, RK.c[0] - 1.0, RK.c[1] - 1.0, 0.0};",
+     "const double sn[4] = {-1.0, RK.c[0], RK.c[1] - 1.0, 0.0};"),
+    ("start values v1 sign", "const double v1 = zold[0 * m + r] - z3;",
+     "const double v1 = zold[0 * m + r] + z3;"),
+    ("start values step ratio", "const double s = RK.c[i] * h / h_old;",
+     "const double s = RK.c[i] * h_old / h;"),
     ("warm start ignored", "integrate_(y, dt, st, h_pre, h_io && *h_io > 0.0 ? *h_io : 0.0);",
      "integrate_(y, dt, st, h_pre, 0.0);"),
 ]
@@ -109,6 +116,7 @@ PINS = [
     ("bytecode rejects", lambda o: PF.test_bytecode_invalid_programs_rejected(
         o, np.array([2, 1, 2.0, W.BC_ADD, 1, 0, 0, W.BC_OUT, 0, 1, 0], dtype=float), 1)),
     ("warm start equals h0", lambda o: PF.test_warm_start_equals_h0(o)),
+    ("p11 start values", lambda o: P.test_p11_start_values_reproduce_a_cubic(o, 2.5)),
 ]
 
 

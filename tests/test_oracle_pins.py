@@ -440,3 +440,50 @@ def test_p10_linear_newton_exact_in_one_iteration(orc):
             assert not failed and k == 2, (m, h, k)
         y, st, ret = orc.reaction_step(y0[:, None], 2.0, 1e-6, 1e-9, orc.LINEAR, K)
         assert ret == 0 and st[8, 0] <= 2 * st[1, 0], st[:, 0]
+
+
+# ---------------------------------------------------------------------------
+# P11 Newton start values (HW §IV.8: the collocation polynomial of the last
+# accepted step, continued over the next step)
+# ---------------------------------------------------------------------------
+def _cubic(coef, t):
+    """y(t) = sum_k coef[k] t^k per component; coef [4, m]."""
+    return sum(coef[k] * t ** k for k in range(coef.shape[0]))
+
+
+@pytest.mark.parametrize("ratio", [0.3, 1.0, 2.5])
+def test_p11_start_values_reproduce_a_cubic(orc, ratio):
+    """The collocation polynomial of a step is a cubic in time; when the
+    solution itself is a cubic y(t), the stage increments of the last step
+    (t0 -> t1 = t0 + h_old) are z_i = y(t0 + c_i h_old) - y(t0), the cubic
+    through them is y(t1 + s h_old) - y(t1), and its continuation to the next
+    step's stage points gives y(t1 + c_i h) - y(t1) exactly, whatever h/h_old.
+    The nodes c come from their definition (zeros of d^2/dx^2 [x^2 (x-1)^3]),
+    the cubic is evaluated here in numpy, independently of the oracle."""
+    c = [float(v) for v in DEF["c"]]
+    rng = np.random.default_rng(11)
+    m = 4
+    coef = rng.normal(size=(4, m))
+    t0, h_old = 0.35, 0.3
+    t1 = t0 + h_old
+    h = ratio * h_old
+    zold = np.stack([_cubic(coef, t0 + ci * h_old) - _cubic(coef, t0) for ci in c])
+    expect = np.stack([_cubic(coef, t1 + ci * h) - _cubic(coef, t1) for ci in c])
+    z = orc.start_values(zold, h, h_old)
+    scale = np.abs(expect).max()
+    assert np.abs(z - expect).max() <= 1e-13 * max(1.0, scale), (z, expect)
+
+
+def test_p11_start_values_are_only_cubic(orc):
+    """A quartic solution is not reproduced (the start values come from a
+    cubic: a degree-4 term leaves an error of the size of its fourth
+    divided difference), and zero increments extrapolate to zero."""
+    c = [float(v) for v in DEF["c"]]
+    coef = np.zeros((5, 1))
+    coef[4, 0] = 1.0
+    t0, h_old, h = 0.0, 0.5, 0.5
+    zold = np.stack([_cubic(coef, t0 + ci * h_old) - _cubic(coef, t0) for ci in c])
+    expect = np.stack([_cubic(coef, t0 + h_old + ci * h) - _cubic(coef, t0 + h_old) for ci in c])
+    z = orc.start_values(zold, h, h_old)
+    assert np.abs(z - expect).max() > 1e-3
+    assert not np.any(orc.start_values(np.zeros((3, 2)), 0.1, 0.2))
