@@ -135,6 +135,9 @@ typedef struct {
                               step to end at dt; dt/N in fixed-step mode; for a
                               failed cell the step size of its last attempt (0 if
                               none).  Not accepted by sessions.                     */
+    int32_t session_streams; /* sessions only (rd_session_create): concurrent launch
+                              streams, 0 (default) = 4, at most 64; ignored by the
+                              direct entry points                                   */
 } rd_options;
 
 /* Fill *opts with the defaults above. */
@@ -290,37 +293,56 @@ typedef struct {
     int64_t n_failed;      /* cells with nonzero per-cell status                 */
     int64_t n_cells;
     uint64_t t_submit_ns;  /* CLOCK_MONOTONIC timestamps                         */
-    uint64_t t_admit_ns;
+    uint64_t t_admit_ns;   /* admitted into the arena, copies and kernel queued  */
     uint64_t t_done_ns;    /* completion observed by the session                 */
-    int64_t batch_id;      /* launch batch the request ran in                   */
+    int64_t batch_id;      /* scheduler pass that admitted the request            */
+    double kernel_start_ms;/* device time of the request's reaction-step kernel,  */
+    double kernel_end_ms;  /* ms since the session was created (-1 if unknown)    */
+    int32_t stream;        /* index of the session stream it ran on               */
+    int32_t deferred;      /* scheduler passes in which it did not fit the arena  */
 } rd_request_info;
 
 /*
  * Create a session on `device` (HIP ordinal) whose arena holds at most
- * hbm_budget_bytes.  defaults nullable.  n_streams: concurrent launch streams
- * (0 = 4).  Returns 0 or a negative error.
+ * hbm_budget_bytes of device memory (allocated here, once).  defaults
+ * nullable: the options every request of the session runs with
+ * (defaults->session_streams sets the number of launch streams; h_cells must
+ * be null).  Returns 0 or RD_EINVAL / RD_ENOMEM / RD_EDEVICE.
  */
 int32_t rd_session_create(rd_session** out, int32_t device,
-                          size_t hbm_budget_bytes, const rd_options* defaults,
-                          int32_t n_streams);
+                          size_t hbm_budget_bytes, const rd_options* defaults);
 
 /*
  * Queue a request (non-blocking).  states/stats are DEVICE pointers owned by
- * the caller and must stay valid until the request is done; stats nullable.
- * The model parameters are copied.  RD_ETOOBIG if the request can never fit the
- * budget.  *req_id receives an id for rd_poll / rd_wait.
+ * the caller and must stay valid and untouched until the request is done;
+ * stats nullable.  The model parameters are copied.  The session reads the
+ * states only after all work enqueued on the device's null stream before
+ * this call has completed (an event recorded here); rd_submit_ex takes the
+ * stream whose work the read must follow (null = the null stream).
+ * RD_ETOOBIG if the request can never fit the budget; RD_ECLOSED once the
+ * session is being destroyed.  *req_id receives an id for rd_poll / rd_wait.
  */
 int32_t rd_submit(rd_session* s, double* states, int64_t n_cells, int32_t m,
                   double dt, double rtol, double atol, const rd_model* model,
                   int32_t* stats, uint64_t* req_id);
+int32_t rd_submit_ex(rd_session* s, double* states, int64_t n_cells, int32_t m,
+                     double dt, double rtol, double atol, const rd_model* model,
+                     int32_t* stats, void* producer_stream, uint64_t* req_id);
 
-/* 0 done (info filled), 1 pending, < 0 error. info nullable. */
+/* 0 done (info filled; the request is then forgotten), 1 pending, < 0 error:
+ * the request's own error (message in rd_last_error) or RD_ENOTFOUND.  info
+ * nullable.  Results are in the caller's states once done is reported. */
 int32_t rd_poll(rd_session* s, uint64_t req_id, rd_request_info* info);
 
-/* Block until done; 0 or < 0. info nullable. */
+/* Block until done; 0 or < 0 as rd_poll.  info nullable.  Several threads may
+ * wait for, or poll, the same id: each is told the outcome once it is done,
+ * later calls get RD_ENOTFOUND. */
 int32_t rd_wait(rd_session* s, uint64_t req_id, rd_request_info* info);
 
-/* Bytes of the arena a request of this size would occupy. */
+/* Bytes of the arena a request of this size occupies: its states, its
+ * counters when with_stats, and for 8192 cells or more the claim-order
+ * scratch of its persistent launch (4 bytes per cell plus a byte per cell
+ * and a few KiB). */
 size_t rd_request_bytes(int64_t n_cells, int32_t m, int32_t with_stats);
 
 /* Drain outstanding requests, free the arena and streams. */

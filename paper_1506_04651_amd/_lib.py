@@ -33,7 +33,7 @@ class RdOptions(ctypes.Structure):
                 ("h0", ctypes.c_double), ("h_min", ctypes.c_double),
                 ("variant", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("jacobian", ctypes.c_int32),
-                ("h_cells", ctypes.c_void_p)]
+                ("h_cells", ctypes.c_void_p), ("session_streams", ctypes.c_int32)]
 
 
 class RdGrid(ctypes.Structure):
@@ -51,7 +51,9 @@ class RdRequestInfo(ctypes.Structure):
     _fields_ = [("done", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("n_failed", ctypes.c_int64), ("n_cells", ctypes.c_int64),
                 ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
-                ("t_done_ns", ctypes.c_uint64), ("batch_id", ctypes.c_int64)]
+                ("t_done_ns", ctypes.c_uint64), ("batch_id", ctypes.c_int64),
+                ("kernel_start_ms", ctypes.c_double), ("kernel_end_ms", ctypes.c_double),
+                ("stream", ctypes.c_int32), ("deferred", ctypes.c_int32)]
 
 
 # name -> (restype, argtypes); every symbol include/rd.h declares
@@ -65,12 +67,15 @@ SIGNATURES = {
                                              ctypes.POINTER(RdModel), ctypes.POINTER(RdOptions),
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
     "rd_session_create": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
-                                           ctypes.c_size_t, ctypes.POINTER(RdOptions),
-                                           ctypes.c_int32]),
+                                           ctypes.c_size_t, ctypes.POINTER(RdOptions)]),
     "rd_submit": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                    ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_double, ctypes.POINTER(RdModel), ctypes.c_void_p,
                                    ctypes.POINTER(ctypes.c_uint64)]),
+    "rd_submit_ex": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.POINTER(RdModel), ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
     "rd_poll": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64,
                                  ctypes.POINTER(RdRequestInfo)]),
     "rd_wait": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64,

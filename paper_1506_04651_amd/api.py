@@ -30,8 +30,10 @@ def _model(kind: int, m: int, params):
 
 def make_options(precision=FP64, schedule=PERSISTENT, tol_transform=1, max_steps=100000,
                  newton_max=7, fixed_steps=0, h0=0.0, h_min=0.0, variant=0,
-                 use_graph=False, order=1, jacobian=0, h_cells_ptr=None) -> RdOptions:
+                 use_graph=False, order=1, jacobian=0, h_cells_ptr=None,
+                 session_streams=0) -> RdOptions:
     o = RdOptions()
+    o.session_streams = int(session_streams)
     o.order = int(order)
     o.jacobian = int(jacobian)
     o.h_cells = h_cells_ptr
@@ -262,21 +264,24 @@ class Session:
     def __init__(self, budget_bytes: int, device: int = 0, n_streams: int = 0, **opts):
         lib = _lib.load()
         self._h = ctypes.c_void_p()
-        o = make_options(**opts)
+        o = make_options(session_streams=n_streams, **opts)
         _check(lib.rd_session_create(ctypes.byref(self._h), int(device), int(budget_bytes),
-                                     ctypes.byref(o), int(n_streams)))
+                                     ctypes.byref(o)))
         self._keep = {}
 
-    def submit(self, states, dt, rtol, atol, kind, params, stats=None) -> int:
+    def submit(self, states, dt, rtol, atol, kind, params, stats=None, stream=None) -> int:
+        """Queue a request; the session reads ``states`` after the work already
+        enqueued on ``stream`` (default: torch's current stream)."""
         lib = _lib.load()
         _check_states(states)
         m, n = int(states.shape[0]), int(states.shape[1])
         sp = _check_stats(stats, n)
         mdl, keep = _model(kind, m, params)
         rid = ctypes.c_uint64()
-        _check(lib.rd_submit(self._h, ctypes.c_void_p(states.data_ptr()), n, m, float(dt),
-                             float(rtol), float(atol), ctypes.byref(mdl),
-                             ctypes.c_void_p(sp) if sp else None, ctypes.byref(rid)))
+        _check(lib.rd_submit_ex(self._h, ctypes.c_void_p(states.data_ptr()), n, m, float(dt),
+                                float(rtol), float(atol), ctypes.byref(mdl),
+                                ctypes.c_void_p(sp) if sp else None, _stream_handle(stream),
+                                ctypes.byref(rid)))
         del keep
         self._keep[rid.value] = (states, stats)
         return rid.value

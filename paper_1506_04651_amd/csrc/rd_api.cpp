@@ -156,7 +156,14 @@ void* stream_workspace(DevCtx& c, hipStream_t s, size_t bytes, int* err) {
         return nullptr;
     }
     if (it != c.order_ws.end()) {
-        c.retired.push_back(it->second.first);
+        void* old = it->second.first;
+        if (c.graph_ws.count(old)) {
+            c.retired.push_back(old);
+        } else {
+            /* only work queued on this stream used it */
+            hipStreamSynchronize(s);
+            hipFree(old);
+        }
         it->second = {p, cap};
     } else {
         c.order_ws[s] = {p, cap};
@@ -164,25 +171,34 @@ void* stream_workspace(DevCtx& c, hipStream_t s, size_t bytes, int* err) {
     return p;
 }
 
+void pin_stream_workspace(DevCtx& c, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.order_ws.find(s);
+    if (it != c.order_ws.end()) c.graph_ws.insert(it->second.first);
+}
+
 /* Below this many cells the claim order is left natural (the sort would cost
  * more than the tail it removes). */
 constexpr int64_t kOrderMinCells = 8192;
 
+size_t order_bytes(int64_t n) {
+    if (n < kOrderMinCells || n > INT32_MAX) return 0;
+    return (((size_t)n * sizeof(int32_t) + 255) & ~(size_t)255) + order_workspace_bytes(n);
+}
+
 int enqueue_order(DevCtx& c, Prepared& pr, hipStream_t s, unsigned long long* counters,
-                  bool* cleared) {
+                  bool* cleared, void* ws_given) {
     pr.args.order = nullptr;
     if (cleared) *cleared = false;
-    if (pr.entry->schedule != RD_PERSISTENT || !pr.order || pr.args.n < kOrderMinCells ||
-        pr.args.n > INT32_MAX)
+    if (pr.entry->schedule != RD_PERSISTENT || !pr.order || order_bytes(pr.args.n) == 0)
         return 0;
     /* the 16-lane kernels are registered under m = 16 but serve 5..16:
      * the cost keys use the request's species count */
     order_fn fn = find_order_fn(pr.entry->kind, (int)pr.args.P.m);
     if (!fn) return 0;
-    const size_t wsb = order_workspace_bytes(pr.args.n);
     const size_t ordb = ((size_t)pr.args.n * sizeof(int32_t) + 255) & ~(size_t)255;
     int err = 0;
-    char* ws = (char*)stream_workspace(c, s, ordb + wsb, &err);
+    char* ws = ws_given ? (char*)ws_given : (char*)stream_workspace(c, s, order_bytes(pr.args.n), &err);
     if (!ws) return err ? err : RD_ENOMEM;
     int32_t* order = (int32_t*)ws;
     HIP_TRY(fn(pr.args, ws + ordb, order, counters, s));
@@ -505,6 +521,7 @@ static int launch_prepared(Prepared& pr, hipStream_t s, bool use_graph, unsigned
             }
             const hipError_t ei = hipGraphInstantiate(&v.exec, g, nullptr, nullptr, 0);
             hipGraphDestroy(g);
+            pin_stream_workspace(*c, s);
             if (ei != hipSuccess) {
                 set_error("hipGraphInstantiate: %s", hipGetErrorString(ei));
                 hipFree(v.counters);
@@ -552,13 +569,11 @@ int enqueue_prepared(Prepared& pr, hipStream_t s, unsigned long long* counters) 
 }
 
 int ensure_workspace(const Prepared& pr, hipStream_t s) {
-    if (pr.entry->schedule != RD_PERSISTENT || !pr.order) return 0;
+    if (pr.entry->schedule != RD_PERSISTENT || !pr.order || order_bytes(pr.args.n) == 0) return 0;
     DevCtx* c = current_ctx();
     if (!c) return RD_EDEVICE;
     int err = 0;
-    const size_t need = (((size_t)pr.args.n * 4 + 255) & ~(size_t)255) +
-                        order_workspace_bytes(pr.args.n);
-    return stream_workspace(*c, s, need, &err) ? 0 : (err ? err : RD_ENOMEM);
+    return stream_workspace(*c, s, order_bytes(pr.args.n), &err) ? 0 : (err ? err : RD_ENOMEM);
 }
 
 }  // namespace rd

@@ -8,6 +8,7 @@
 #include <atomic>
 #include <map>
 #include <mutex>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -36,9 +37,11 @@ struct DevCtx {
     std::atomic<unsigned> next_slot{0};
     std::mutex mu;
     std::map<std::vector<double>, double*> params; /* key: {kind, m, block...} */
-    /* per-stream scratch for the claim order; outgrown buffers are kept
-     * (captured graphs may still reference them) */
+    /* per-stream scratch for the claim order; an outgrown buffer is freed
+     * unless a captured graph references it (then it is kept: graphs live as
+     * long as the process) */
     std::map<hipStream_t, std::pair<void*, size_t>> order_ws;
+    std::set<void*> graph_ws;
     std::vector<void*> retired;
 };
 constexpr unsigned kSlots = 4096;
@@ -54,12 +57,21 @@ int prepare(double* states, int64_t n, int32_t m, double dt, double rtol, double
 /* Scratch of at least `bytes` for launches on stream s (claim order). */
 void* stream_workspace(DevCtx& c, hipStream_t s, size_t bytes, int* err);
 
+/* Mark stream s's current claim-order scratch as referenced by a captured
+ * graph, so that it is never freed. */
+void pin_stream_workspace(DevCtx& c, hipStream_t s);
+
+/* Bytes of claim-order scratch a persistent launch over n cells uses (0 when
+ * the batch is too small to be ordered). */
+size_t order_bytes(int64_t n);
+
 /* Enqueue the claim-order kernels for a prepared persistent launch (when the
  * options ask for it and an order kernel exists); sets pr.args.order.  The
  * order kernels then also clear `counters` (two entries, nullable) and
- * *cleared is set; otherwise the caller clears them. */
+ * *cleared is set; otherwise the caller clears them.  ws: order_bytes(n)
+ * bytes of device scratch, or null for the stream's own scratch. */
 int enqueue_order(DevCtx& c, Prepared& pr, hipStream_t s, unsigned long long* counters,
-                  bool* cleared);
+                  bool* cleared, void* ws = nullptr);
 
 /* A prepared reaction step enqueued on stream s with the given counters
  * (claim position, failed cells; cleared by the enqueued work); no host

@@ -257,6 +257,7 @@ static int64_t strang_graph_step(double* states, int32_t m, const rd_grid* grid,
                 free_strang_graph(g);
                 return rc;
             }
+            if (DevCtx* c = current_ctx()) pin_stream_workspace(*c, s);
             it = g_sg.emplace(std::move(key), g).first;
         }
         run = it->second; /* entries are never erased: the handles stay valid */

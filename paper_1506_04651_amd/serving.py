@@ -75,7 +75,12 @@ def replay(session: api.Session, requests, pools, time_scale: float = 1.0, keep_
                            "latency_ms": (info.t_done_ns - info.t_submit_ns) * 1e-6,
                            "queue_ms": (info.t_admit_ns - info.t_submit_ns) * 1e-6,
                            "failed": int(info.n_failed), "status": int(info.status),
-                           "batch": int(info.batch_id)}
+                           "batch": int(info.batch_id), "stream": int(info.stream),
+                           "deferred": int(info.deferred),
+                           "t_submit_ns": int(info.t_submit_ns),
+                           "t_admit_ns": int(info.t_admit_ns), "t_done_ns": int(info.t_done_ns),
+                           "kernel_start_ms": float(info.kernel_start_ms),
+                           "kernel_end_ms": float(info.kernel_end_ms)}
                 if not keep_outputs:
                     inputs[j] = None
         for rid in done:
@@ -92,6 +97,21 @@ def replay(session: api.Session, requests, pools, time_scale: float = 1.0, keep_
     return recs, wall, (inputs if keep_outputs else None)
 
 
+def max_concurrent_kernels(recs):
+    """Largest number of requests whose reaction-step kernels were running on
+    the device at the same instant (device timestamps of the session)."""
+    ev = []
+    for r in recs:
+        if r["kernel_start_ms"] >= 0.0 and r["kernel_end_ms"] > r["kernel_start_ms"]:
+            ev.append((r["kernel_start_ms"], 1))
+            ev.append((r["kernel_end_ms"], -1))
+    best = cur = 0
+    for _, d in sorted(ev, key=lambda e: (e[0], e[1])):
+        cur += d
+        best = max(best, cur)
+    return best
+
+
 def summarize(recs, wall):
     lat = np.array([r["latency_ms"] for r in recs])
     cells = sum(r["n"] for r in recs)
@@ -100,6 +120,8 @@ def summarize(recs, wall):
            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
            "max_ms": float(lat.max()), "mean_queue_ms": float(np.mean([r["queue_ms"] for r in recs])),
            "failed_cells": int(sum(r["failed"] for r in recs)),
+           "deferred_requests": int(sum(1 for r in recs if r["deferred"] > 0)),
+           "max_concurrent_kernels": max_concurrent_kernels(recs),
            "errors": int(sum(1 for r in recs if r["status"] != 0))}
     for pool in sorted({r["pool"] for r in recs}):
         sel = [r for r in recs if r["pool"] == pool]

@@ -7,8 +7,8 @@
  * [0, dt] is u_i(dt) = exp(K_ii dt) u_i(0).  The step must return 0 failed
  * cells and every value must lie within the tolerance scale of the exact
  * one; the full entry point with options and counters, an asynchronous call
- * on a created stream, and the error returns of invalid calls are checked
- * too.  Exit status 0 on success, 1 on a failed check, 2 on a HIP error.
+ * on a created stream, the error returns of invalid calls, and two requests
+ * through a serving session are checked too.  Exit status 0 on success, 1 on a failed check, 2 on a HIP error.
  */
 #include <hip/hip_runtime_api.h>
 #include <math.h>
@@ -105,6 +105,49 @@ int main(void) {
         if (y2[k] != y[k]) same = 0;
     check(same, "states untouched by the rejected calls");
     check(rd_last_error() != NULL, "rd_last_error available");
+
+    /* 4. the request API: two requests through a session of two streams,
+     * each equal to the direct call's result; unknown ids and oversized
+     * requests are refused */
+    rd_options so;
+    rd_default_options(&so);
+    so.session_streams = 2;
+    rd_session* sess = NULL;
+    check(rd_session_create(&sess, 0, (size_t)1 << 22, &so) == 0 && sess != NULL,
+          "rd_session_create (4 MiB budget, 2 streams)");
+    double* d2 = NULL;
+    HIP_OK(hipMalloc((void**)&d2, sizeof(double) * M * N));
+    HIP_OK(hipMemcpy(d, h, sizeof(double) * M * N, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(d2, h, sizeof(double) * M * N, hipMemcpyHostToDevice));
+    uint64_t id1 = 0, id2 = 0;
+    int sub1 = rd_submit(sess, d, N, M, dt, rtol, atol, &model, dst, &id1);
+    int sub2 = rd_submit_ex(sess, d2, N, M, dt, rtol, atol, &model, NULL, (void*)s, &id2);
+    check(sub1 == 0 && sub2 == 0 && id1 != id2, "rd_submit / rd_submit_ex queue two requests");
+    rd_request_info info1, info2;
+    check(rd_wait(sess, id1, &info1) == 0 && info1.done == 1 && info1.n_failed == 0 &&
+              info1.n_cells == N,
+          "rd_wait: first request done, no failed cell");
+    int pr = 1;
+    while (pr == 1) pr = rd_poll(sess, id2, &info2);
+    check(pr == 0 && info2.done == 1 && info2.n_failed == 0, "rd_poll: second request done");
+    check(info1.t_submit_ns <= info1.t_admit_ns && info1.t_admit_ns <= info1.t_done_ns &&
+              info1.kernel_end_ms >= info1.kernel_start_ms && info1.kernel_start_ms >= 0.0,
+          "request timestamps ordered");
+    check(rd_poll(sess, id1, NULL) == RD_ENOTFOUND, "finished id forgotten -> RD_ENOTFOUND");
+    double* y3 = (double*)malloc(sizeof(double) * M * N);
+    if (!y3) return 2;
+    HIP_OK(hipMemcpy(y3, d, sizeof(double) * M * N, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(y2, d2, sizeof(double) * M * N, hipMemcpyDeviceToHost));
+    same = 1;
+    for (int k = 0; k < M * N; ++k)
+        if (y3[k] != y[k] || y2[k] != y[k]) same = 0;
+    check(same, "session results equal the direct call's bitwise");
+    uint64_t idb = 0;
+    check(rd_submit(sess, d, (int64_t)1 << 22, M, dt, rtol, atol, &model, NULL, &idb) == RD_ETOOBIG,
+          "request above the budget -> RD_ETOOBIG");
+    check(rd_session_destroy(sess) == 0, "rd_session_destroy");
+    HIP_OK(hipFree(d2));
+    free(y3);
 
     HIP_OK(hipStreamDestroy(s));
     HIP_OK(hipFree(d));

@@ -38,13 +38,19 @@ def test_default_options(lib):
     assert (o.precision, o.schedule, o.tol_transform, o.max_steps, o.newton_max,
             o.fixed_steps, o.h0, o.h_min, o.variant, o.use_graph) == (0, 0, 1, 100000, 7, 0,
                                                                        0.0, 0.0, 0, 0)
-    assert (o.order, o.jacobian, o.h_cells) == (1, 0, None)
+    assert (o.order, o.jacobian, o.h_cells, o.session_streams) == (1, 0, None, 0)
 
 
 def test_request_bytes(lib):
     assert lib.rd_request_bytes(0, 3, 0) == 0
     assert lib.rd_request_bytes(1000, 3, 0) == 24064  # 24000 rounded up to 256
     assert lib.rd_request_bytes(1000, 3, 1) == 24064 + 36096
+    # from 8192 cells on, the claim-order scratch of the persistent launch
+    # (an int32 position and a byte per cell, plus bucket counters) is counted
+    n = 100000
+    b = lib.rd_request_bytes(n, 3, 0)
+    assert b >= 2400000 + 4 * n + n
+    assert b - (2400000 + 4 * n + n) < 64 * 1024
 
 
 def test_variants_listed(lib):

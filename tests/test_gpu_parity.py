@@ -1,11 +1,12 @@
 """GPU parity: the HIP reaction step (through the C ABI) against the CPU FP64
 oracle, cell by cell, on the same seeded inputs.
 
-Bar (FP64 path): every cell within 1e-8 relative error of the oracle
-(max_i |y_i - y_ora_i| / max(|y_ora_i|, atol)), with the per-cell counter
-traces identical except for cells where a rounding difference flips a control
-decision (accept/reject, Newton convergence): those are counted and must stay
-rare.  The oracle solves the untransformed 3m x 3m Newton system and the GPU
+Bar (FP64 path): on the benchmark workloads (the 1D, 2D and 3D BZ fields)
+every cell within 1e-8 relative error of the oracle (max_i |y_i - y_ora_i| /
+max(|y_ora_i|, atol)) and every per-cell counter trace identical.  Elsewhere
+(ragged sizes, failure cases) a rounding difference may flip a control decision
+(accept/reject, Newton convergence) in a rare cell: such cells are counted and
+must stay rare and within the tolerance scale.  The oracle solves the untransformed 3m x 3m Newton system and the GPU
 the transformed real + complex m x m systems, so both differ only by rounding.
 """
 import numpy as np
@@ -47,9 +48,8 @@ def test_oregonator_1d_all_cells(rd, orc, schedule):
     yo, sto, reto = run_oracle(orc, w)
     assert ret == reto == 0
     rep = compare(y, st, yo, sto, w.atol, label=f"1d sched{schedule}")
-    assert rep["max_err_same_trace"] <= 1e-8
-    assert rep["trace_divergent"] <= max(2, int(1e-3 * w.n))
-    assert rep["max_err"] <= 1e-8 or rep["max_err_divergent"] <= 10 * w.rtol
+    assert rep["max_err"] <= 1e-8
+    assert rep["trace_divergent"] == 0
 
 
 def test_persistent_equals_one_launch_bitwise(rd):
@@ -83,9 +83,8 @@ def test_oregonator_2d_full_field(rd, orc):
     yo, sto, reto = run_oracle(orc, w)
     assert ret == reto == 0
     rep = compare(y, st, yo, sto, w.atol, label="2d")
-    assert rep["max_err_same_trace"] <= 1e-8
-    assert rep["trace_divergent"] <= max(4, int(1e-3 * w.n))
-    assert rep["max_err_divergent"] <= 10 * w.rtol
+    assert rep["max_err"] <= 1e-8
+    assert rep["trace_divergent"] == 0
 
 
 def test_ragged_sizes_and_empty(rd, orc):
@@ -243,9 +242,8 @@ def test_oregonator_3d_fp64_and_mixed_vs_oracle(rd, orc):
     y, st, ret = run_gpu(rd, w)
     assert ret == 0
     rep = compare(y[:, idx], st[:, idx], yo, sto, w.atol, label="3d fp64 sampled")
-    assert rep["max_err_same_trace"] <= 1e-8
-    assert rep["trace_divergent"] <= max(4, int(1e-3 * s.n))
-    assert rep["max_err_divergent"] <= 10 * w.rtol
+    assert rep["max_err"] <= 1e-8
+    assert rep["trace_divergent"] == 0
     say("oregonator_3d mixed, n", w.n)
     ym, stm, retm = run_gpu(rd, w, precision=1)
     assert retm == 0
@@ -264,6 +262,5 @@ def test_oregonator_3d_every_cell_vs_oracle(rd, orc):
     yo, sto, reto = run_oracle(orc, w)
     assert ret == reto == 0
     rep = compare(y, st, yo, sto, w.atol, label="3d fp64 every cell")
-    assert rep["max_err_same_trace"] <= 1e-8
-    assert rep["trace_divergent"] <= max(4, int(1e-3 * w.n))
-    assert rep["max_err_divergent"] <= 10 * w.rtol
+    assert rep["max_err"] <= 1e-8
+    assert rep["trace_divergent"] == 0
