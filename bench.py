@@ -4,13 +4,21 @@
 One "step" is one reaction substep over a whole synthetic leaf set: the
 states are restored from a resident copy (a device-to-device copy of
 2*8*m bytes per cell) and every cell is integrated over dt with Radau5 by the
-HIP kernels.  Default workload: the 512 x 512 BZ/Oregonator spiral field
-(262 144 cells, m = 3, dt = 1/64, rtol = 1e-5, atol = 1e-8), FP64, persistent
-work-stealing kernel; the one-launch-per-batch schedule and the mixed
-precision path are timed beside it.
+HIP kernels.  Default workload: the 160^3 BZ/Oregonator scroll-wave leaf set
+(4 194 304 cells, m = 3, dt = 1/64, rtol = 1e-5, atol = 1e-8), FP64,
+persistent work-stealing kernel.  Beside it, in the same JSON line: the
+one-launch schedule and the mixed-precision path on the same cells (error
+against the FP64 result), the m = 16 kinetics batch (1 048 576 cells) in FP64
+and mixed precision, and a replay of the Poisson request stream through a
+serving session (p50 / p99 latency, aggregate rate).
 
-Prints ONE JSON line (see the keys below).  --gpus N with N > 1 exits: the
-reaction step needs no communication, and the benchmark runs on one GPU.
+Roofline: the FLOPs of a launch are counted from its per-cell counters with
+the reference per-event counts (roofline.REFERENCE_COUNTS; also with the
+counts of the kernels as written), divided by the main kernel's average
+duration from the library's HIP events on the launch stream.
+
+Prints ONE JSON line.  --gpus N with N > 1 exits: the reaction step needs no
+communication, and the benchmark runs on one GPU.
 """
 import argparse
 import hashlib
@@ -116,18 +124,80 @@ def measured_traffic(kernel_name, workload):
     return ent.get("hbm_bytes_per_launch")
 
 
+def kernel_times(rd, torch, w, u0, steps, **opts):
+    """Durations of the main kernel (the library's HIP events around it on the
+    launch stream) over `steps` launches, each awaited before the next."""
+    u = torch.empty_like(u0)
+    kms = []
+    for _ in range(steps):
+        u.copy_(u0)
+        rd.reaction_step(u, w.dt, w.rtol, w.atol, w.kind, w.params, async_=True, **opts)
+        kms.append(rd.last_kernel_ms())
+    return kms
+
+
+def counter_pass(rd, torch, w, u0, **opts):
+    """One launch with per-cell counters (identical in every launch: the
+    integration is deterministic); returns (states, counters, failed)."""
+    st = torch.zeros((9, w.n), dtype=torch.int32, device="cuda")
+    u = u0.clone()
+    nfail = rd.reaction_step(u, w.dt, w.rtol, w.atol, w.kind, w.params, stats=st, **opts)
+    return u.cpu().numpy(), st.cpu().numpy(), int(nfail)
+
+
+def roofline_block(roofline, w, stats, kernel_ms, mixed):
+    """Algorithmic FLOP/s of the dominant kernel against the vector peak (FP64;
+    for the mixed path the blended FP64 + FP32 bound)."""
+    K = w.info.get("K")
+    G = w.info.get("G")
+    ref = roofline.reference_counts(w.kind, w.m)
+    t = kernel_ms * 1e-3
+    out = {"bound": "alu", "unit": "TFLOP/s", "avg_kernel_ms": kernel_ms}
+    written = roofline.algorithmic_flops(stats, w.kind, w.m, mixed)
+    if ref is not None:
+        flops = roofline.reference_flops(stats, ref)
+        out["flops_per_launch"] = flops
+        out["counts"] = "reference per-event counts"
+        if K is not None:
+            refn = roofline.reference_counts(w.kind, w.m, K, G)
+            out["flops_per_launch_nnz"] = roofline.reference_flops(stats, refn)
+    else:
+        flops = written
+        out["flops_per_launch"] = flops
+        out["counts"] = "kernels as written"
+    out["flops_per_launch_as_written"] = written
+    out["achieved"] = flops / t / 1e12
+    if mixed and ref is not None:
+        f32 = roofline.reference_fp32_flops(stats, w.kind, w.m)
+        bound = roofline.blended_bound_s(flops - f32, f32)
+        out["peak"] = flops / bound / 1e12
+        out["peak_kind"] = "blended FP64 78.6 + FP32 157.3 TFLOP/s over the FP64/FP32 split"
+        out["frac"] = bound / t
+    else:
+        out["peak"] = roofline.PEAK_FP64_VECTOR_TFLOPS
+        out["peak_kind"] = "FP64 vector"
+        out["frac"] = out["achieved"] / roofline.PEAK_FP64_VECTOR_TFLOPS
+    out["frac_as_written"] = written / t / 1e12 / roofline.PEAK_FP64_VECTOR_TFLOPS
+    if "flops_per_launch_nnz" in out:
+        out["frac_nnz"] = out["flops_per_launch_nnz"] / t / 1e12 / roofline.PEAK_FP64_VECTOR_TFLOPS
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="oregonator_2d", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="oregonator_3d", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--schedule", default="persistent", choices=["persistent", "onelaunch"])
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--graph", action="store_true", help="replay a captured hipGraph per step")
     ap.add_argument("--no-compare", action="store_true",
-                    help="skip the one-launch and mixed-precision side measurements")
+                    help="skip every side measurement (schedules, precisions, m = 16, serving)")
+    ap.add_argument("--no-kinetics", action="store_true", help="skip the m = 16 side measurement")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving replay")
+    ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="time every compiled kernel variant first and run the fastest (the "
@@ -160,48 +230,32 @@ def main():
     tuning = {}
     if args.autotune and not args.no_autotune and args.variant == 0:
         from paper_1506_04651_amd import autotune
-        paths = [(prec, sched)]
-        if not args.no_compare:
-            paths += [(p, s) for p in (rd.FP64, rd.MIXED) for s in (rd.PERSISTENT, rd.ONE_LAUNCH)
-                      if (p, s) != (prec, sched)]
-        for p, s in paths:
-            log("autotune precision", p, "schedule", s)
-            r = autotune.tune(u0, w.dt, w.rtol, w.atol, w.kind, w.params, p, s,
+        for p in (rd.FP64, rd.MIXED):
+            log("autotune precision", p)
+            r = autotune.tune(u0, w.dt, w.rtol, w.atol, w.kind, w.params, p, sched,
                               reps=7 if w.m <= 4 else 2)
-            tuning[f"precision{p}_schedule{s}"] = {r["names"][v]: round(ms, 4)
-                                                   for v, ms in r["ms"].items()}
+            tuning[f"precision{p}"] = {r["names"][v]: round(ms, 4) for v, ms in r["ms"].items()}
 
-    # counters of one launch (identical every launch: the integration is
-    # deterministic) -> algorithmic FLOPs per launch
     log("counter pass")
-    st = torch.zeros((9, w.n), dtype=torch.int32, device="cuda")
-    u = u0.clone()
-    nfail = rd.reaction_step(u, w.dt, w.rtol, w.atol, w.kind, w.params, stats=st, **opts)
-    stats = st.cpu().numpy()
-    flops = roofline.algorithmic_flops(stats, w.kind, w.m)
-    ref_out = u.cpu().numpy()
-    del st
+    ref_out, stats, nfail = counter_pass(rd, torch, w, u0, **opts)
 
     log("timed run", args.precision, args.schedule, "steps", args.steps)
     main_run = time_path(rd, torch, w, u0, args.steps, args.warmup, **opts)
     out_main = main_run.pop("out").cpu().numpy()
     if not np.array_equal(out_main, ref_out):
         raise SystemExit("timed launches did not reproduce the counter pass bitwise")
-    # duration of the reaction-step kernel alone (the library's HIP events
-    # bracket the main kernel on its launch stream, after the counter reset
-    # and the claim-order pre-pass); steps are synchronised one by one here so
-    # each launch's events can be read
-    kms = []
-    u = torch.empty_like(u0)
-    for _ in range(max(5, args.steps // 2)):
-        u.copy_(u0)
-        rd.reaction_step(u, w.dt, w.rtol, w.atol, w.kind, w.params, async_=True, **opts)
-        kms.append(rd.last_kernel_ms())
-    kernel_ms = float(np.mean(kms))
-    avg_s = kernel_ms * 1e-3
-    achieved = flops / avg_s / 1e12
+    # the main kernel's duration over as many launches as the timed region
+    kernel_ms = float(np.mean(kernel_times(rd, torch, w, u0, args.steps, **opts)))
     kname = rd.variant_name(w.kind, w.m, prec, sched, args.variant) or "?"
+    roof = roofline_block(roofline, w, stats, kernel_ms, prec == rd.MIXED)
     traffic = measured_traffic(kname, args.workload)
+    roof["traffic"] = traffic
+    roof["traffic_source"] = ("rocprofv3 FETCH_SIZE + WRITE_SIZE of this kernel on these sources, "
+                              "scaled by a device-to-device copy" if traffic else None)
+    roof["avg_step_ms_events"] = main_run["avg_launch_ms"]
+    roof["frac_of_step_time"] = roof["frac"] * kernel_ms / main_run["avg_launch_ms"]
+    roof["algorithmic_bytes_per_launch"] = w.n * roofline.bytes_per_cell(w.m)
+    roof["hbm_gbs_algorithmic"] = roof["algorithmic_bytes_per_launch"] / (kernel_ms * 1e-3) / 1e9
 
     compare = {}
     if not args.no_compare:
@@ -212,14 +266,62 @@ def main():
             if o["precision"] == prec and o["schedule"] == sched:
                 continue
             log("side run", label)
-            r = time_path(rd, torch, w, u0, max(3, args.steps // 4), 1, **o)
+            r = time_path(rd, torch, w, u0, max(5, args.steps // 2), 1, **o)
             out = r.pop("out").cpu().numpy()
             err = np.max(np.abs(out - ref_out) / np.maximum(np.abs(ref_out), w.atol), axis=0)
-            compare[label] = {"value": r["value"], "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
-                              "kernel": rd.variant_name(w.kind, w.m, o["precision"],
-                                                        o["schedule"], 0),
-                              "max_rel_diff_vs_main": float(err.max()),
-                              "frac_within_1e-8_of_main": float(np.mean(err <= 1e-8))}
+            kms = float(np.mean(kernel_times(rd, torch, w, u0, 5, **o)))
+            ent = {"value": r["value"], "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
+                   "kernel_ms": kms,
+                   "kernel": rd.variant_name(w.kind, w.m, o["precision"], o["schedule"], 0),
+                   "max_rel_diff_vs_main": float(err.max()),
+                   "frac_within_1e-8_of_main": float(np.mean(err <= 1e-8))}
+            if o["precision"] == rd.MIXED:
+                _, st_m, _ = counter_pass(rd, torch, w, u0, **o)
+                rb = roofline_block(roofline, w, st_m, kms, True)
+                ent["roofline_frac"] = rb["frac"]
+                ent["counters_equal_main"] = bool(np.array_equal(st_m, stats))
+            compare[label] = ent
+
+        if not args.no_kinetics and args.workload != "kinetics16":
+            log("side workload kinetics16")
+            wk = make_workload("kinetics16")
+            k0 = torch.tensor(wk.states, dtype=torch.float64, device="cuda")
+            kref, kst, kfail = counter_pass(rd, torch, wk, k0, precision=rd.FP64)
+            ent = {"workload": wk.name, "n_cells": wk.n, "m": wk.m, "dt": wk.dt,
+                   "rtol": wk.rtol, "atol": wk.atol, "failed_cells": kfail}
+            for label, p in (("fp64_persistent", rd.FP64), ("mixed_persistent", rd.MIXED)):
+                r = time_path(rd, torch, wk, k0, 3, 1, precision=p)
+                out = r.pop("out").cpu().numpy()
+                kms = float(np.mean(kernel_times(rd, torch, wk, k0, 3, precision=p)))
+                st_p = kst if p == rd.FP64 else counter_pass(rd, torch, wk, k0, precision=p)[1]
+                rb = roofline_block(roofline, wk, st_p, kms, p == rd.MIXED)
+                err = np.max(np.abs(out - kref) / np.maximum(np.abs(kref), wk.atol), axis=0)
+                ent[label] = {"value": r["value"], "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
+                              "kernel_ms": kms,
+                              "kernel": rd.variant_name(wk.kind, wk.m, p, rd.PERSISTENT, 0),
+                              "roofline_frac": rb["frac"],
+                              "roofline_frac_nnz": rb.get("frac_nnz"),
+                              "roofline_frac_as_written": rb["frac_as_written"],
+                              "max_rel_diff_vs_fp64": float(err.max())}
+            compare["kinetics16"] = ent
+            del k0
+
+        if not args.no_serving:
+            log("serving replay,", args.serving_requests, "requests")
+            from paper_1506_04651_amd import serving
+            from paper_1506_04651_amd import workloads as W
+            given = {"oreg3d": w} if args.workload == "oregonator_3d" else {}
+            pools = serving.make_pools(given=given)
+            sizes = {k: v["w"].n for k, v in pools.items()}
+            reqs = W.serving_stream(args.serving_requests, pool_sizes=sizes)
+            budget = 2 << 30
+            with rd.Session(budget, n_streams=4, precision=rd.MIXED) as sess:
+                recs, wall, _ = serving.replay(sess, reqs, pools, 1.0)
+            summ = serving.summarize(recs, wall)
+            summ.update({"budget_bytes": budget, "precision": "mixed", "streams": 4,
+                         "offered_cells_per_s": sum(len(r.idx) for r in reqs) / reqs[-1].t_arrival})
+            compare["serving"] = summ
+            del pools
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -274,13 +376,7 @@ def main():
                    "atol": w.atol, "precision": args.precision, "schedule": args.schedule,
                    "kernel": kname, "graph": bool(args.graph),
                    "failed_cells": int(nfail)},
-        "roofline": {"bound": "alu", "achieved": achieved,
-                     "peak": roofline.PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / roofline.PEAK_FP64_VECTOR_TFLOPS,
-                     "traffic": traffic,
-                     "flops_per_launch": flops, "avg_kernel_ms": kernel_ms,
-                     "avg_step_ms_events": main_run["avg_launch_ms"],
-                     "algorithmic_bytes_per_launch": w.n * roofline.bytes_per_cell(w.m)},
+        "roofline": roof,
         "cpu_baseline": cpu,
         "compare": compare,
         "autotune_ms": tuning,

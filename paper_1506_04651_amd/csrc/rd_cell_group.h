@@ -76,6 +76,8 @@ struct GroupCell {
     static constexpr int M = NC; /* loops run over NC columns; rows and columns >= m are zero */
     static constexpr bool HAS_G = Model::HAS_G;
     static constexpr bool kFused = FUSE;
+    /* FP32 inverses: every solve is refined once against the FP64 matrices */
+    static constexpr bool kRefine = sizeof(LT) < sizeof(double);
     int m;           /* species (run time, 1..16) */
     double inv3m, invm;
 
@@ -97,9 +99,10 @@ struct GroupCell {
     __device__ __forceinline__ bool has(unsigned f) const { return (flags & f) != 0u; }
     __device__ __forceinline__ void set(unsigned f, bool v) { flags = v ? (flags | f) : (flags & ~f); }
 
-    /* f_q(u) and (G u)_q; every lane of the group must be active */
-    __device__ __forceinline__ double rhs(double u, double& gu) const {
-        double lin = 0.0, loss = 0.0;
+    /* lin = (K u)_q and loss = (G u)_q; every lane of the group must be active */
+    __device__ __forceinline__ void rows(double u, double& lin, double& loss) const {
+        lin = 0.0;
+        loss = 0.0;
         if constexpr (kFused) {
             if constexpr (HAS_G) {
                 fused_row4<0>(u, kg, kg + kGroup, lin, loss);
@@ -124,8 +127,21 @@ struct GroupCell {
                 if (HAS_G) loss += kg[kGroup + j] * uj;
             }
         }
+    }
+
+    /* f_q(u) and (G u)_q; every lane of the group must be active */
+    __device__ __forceinline__ double rhs(double u, double& gu) const {
+        double lin, loss;
+        rows(u, lin, loss);
         gu = loss;
         return HAS_G ? lin - u * loss : lin;
+    }
+
+    /* (J x)_q at the stored Jacobian point: (K x)_q - uJ (G x)_q - gJ x_q */
+    __device__ __forceinline__ double jmul(double x) const {
+        double lin, loss;
+        rows(x, lin, loss);
+        return HAS_G ? lin - uJ * loss - gJ * x : lin;
     }
 
     __device__ __forceinline__ void load(const StepParams& P, const double* __restrict__ states,
@@ -436,11 +452,23 @@ struct GroupCell {
         }
         nfev += 3;
         const double g = radau::GAMMA * ih, al = radau::ALPHA * ih, be = radau::BETA * ih;
-        const LT r1 = solve_real((LT)(G1 - g * w1));
-        LT r2 = (LT)(G2 - al * w2 + be * w3), r3 = (LT)(G3 - be * w2 - al * w3);
+        const double b1 = G1 - g * w1, b2 = G2 - al * w2 + be * w3, b3 = G3 - be * w2 - al * w3;
+        const LT r1 = solve_real((LT)b1);
+        LT r2 = (LT)b2, r3 = (LT)b3;
         solve_cplx(r2, r3);
         ++nsol;
-        const double d1 = (double)r1, d2 = (double)r2, d3 = (double)r3;
+        double d1 = (double)r1, d2 = (double)r2, d3 = (double)r3;
+        if constexpr (kRefine) {
+            /* one step of iterative refinement against the FP64 matrices
+             * E1 = g I - J, E2 = (al + i be) I - J: x += E32^{-1} (b - E x) */
+            const double j1 = jmul(d1), j2 = jmul(d2), j3 = jmul(d3);
+            const LT c1 = solve_real((LT)(b1 - g * d1 + j1));
+            LT c2 = (LT)(b2 - al * d2 + be * d3 + j2), c3 = (LT)(b3 - be * d2 - al * d3 + j3);
+            solve_cplx(c2, c3);
+            d1 += (double)c1;
+            d2 += (double)c2;
+            d3 += (double)c3;
+        }
         w1 += d1;
         w2 += d2;
         w3 += d3;
@@ -473,9 +501,14 @@ struct GroupCell {
         constexpr double DW1 = radau::D1 * radau::T11 + radau::D2 * radau::T21 + radau::D3;
         constexpr double DW2 = radau::D1 * radau::T12 + radau::D2 * radau::T22 + radau::D3;
         constexpr double DW3 = radau::D1 * radau::T13 + radau::D2 * radau::T23;
-        const LT v = solve_real((LT)(fb + (DW1 * w1 + DW2 * w2 + DW3 * w3) * ih));
+        const double b = fb + (DW1 * w1 + DW2 * w2 + DW3 * w3) * ih;
+        const LT v = solve_real((LT)b);
         ++nsol;
         e = (double)v;
+        if constexpr (kRefine) {
+            const LT c = solve_real((LT)(b - (radau::GAMMA * ih) * e + jmul(e)));
+            e += (double)c;
+        }
         const double s = e * isc;
         return sqrt_f(grp_sum(s * s) * invm);
     }

@@ -25,7 +25,8 @@
  *
  * LT is the type of the LU factors and triangular solves: double for the FP64
  * path, float for the mixed path (f, residuals, W, error estimate and control
- * stay double).
+ * stay double, and every FP32 solve is refined once against the FP64
+ * iteration matrix, so the mixed path takes the FP64 path's decisions).
  */
 #pragma once
 #include <hip/hip_runtime.h>
@@ -265,6 +266,8 @@ template <class Model, typename LT, int BLOCK>
 struct SmallCell {
     static constexpr int M = Model::M;
     using L = SmallLds<M>;
+    /* FP32 factors: every solve is refined once against the FP64 matrices */
+    static constexpr bool kRefine = sizeof(LT) < sizeof(double);
 
     /* state */
     double y[M], f0[M], isc[M];
@@ -465,20 +468,33 @@ struct SmallCell {
         }
         nfev += 3;
         const double g = radau::GAMMA * ih, al = radau::ALPHA * ih, be = radau::BETA * ih;
+        /* right-hand sides of the real and the complex system */
+        double b1[M], b2[M], b3[M];
         LT r1[M], r2[M], r3[M];
 #pragma unroll
         for (int q = 0; q < M; ++q) {
-            r1[q] = (LT)(G[0][q] - g * w[0][q]);
-            r2[q] = (LT)(G[1][q] - al * w[1][q] + be * w[2][q]);
-            r3[q] = (LT)(G[2][q] - be * w[1][q] - al * w[2][q]);
+            b1[q] = G[0][q] - g * w[0][q];
+            b2[q] = G[1][q] - al * w[1][q] + be * w[2][q];
+            b3[q] = G[2][q] - be * w[1][q] - al * w[2][q];
+            r1[q] = (LT)b1[q];
+            r2[q] = (LT)b2[q];
+            r3[q] = (LT)b3[q];
         }
         lu_solve_real<M, LT>(e1, p1, r1);
         lu_solve_cplx<M, LT>(e2r, e2i, p2, r2, r3);
+        double x1[M], x2[M], x3[M];
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            x1[q] = (double)r1[q];
+            x2[q] = (double)r2[q];
+            x3[q] = (double)r3[q];
+        }
+        if constexpr (kRefine) refine_newton(b1, b2, b3, x1, x2, x3);
         ++nsol;
         double acc = 0.0;
 #pragma unroll
         for (int q = 0; q < M; ++q) {
-            const double d1 = (double)r1[q], d2 = (double)r2[q], d3 = (double)r3[q];
+            const double d1 = x1[q], d2 = x2[q], d3 = x3[q];
             w[0][q] += d1;
             w[1][q] += d2;
             w[2][q] += d3;
@@ -513,22 +529,77 @@ struct SmallCell {
         return k >= P.kmax ? NW_FAILED : NW_CONTINUE;
     }
 
+    /* Mixed precision: one step of iterative refinement of the FP32-factored
+     * solves, with the residual of the FP64 systems E1 = (gamma/h) I - J and
+     * E2 = ((alpha + i beta)/h) I - J (J from the LDS column, the same J the
+     * factors were rounded from): x += LU32^{-1} (b - E x).  The solve error
+     * drops from about cond * 2^-24 to its square, so the Newton iterates are
+     * those of the FP64 iteration to rounding and the same control decisions
+     * follow. */
+    __device__ __forceinline__ void refine_newton(const double (&b1)[M], const double (&b2)[M],
+                                                  const double (&b3)[M], double (&x1)[M],
+                                                  double (&x2)[M], double (&x3)[M]) {
+        const double g = radau::GAMMA * ih, al = radau::ALPHA * ih, be = radau::BETA * ih;
+        LT c1[M], c2[M], c3[M];
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            double j1 = 0.0, j2 = 0.0, j3 = 0.0;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                const double a = lds[L::J0 + i * M + j];
+                j1 += a * x1[j];
+                j2 += a * x2[j];
+                j3 += a * x3[j];
+            }
+            c1[i] = (LT)(b1[i] - g * x1[i] + j1);
+            c2[i] = (LT)(b2[i] - al * x2[i] + be * x3[i] + j2);
+            c3[i] = (LT)(b3[i] - be * x2[i] - al * x3[i] + j3);
+        }
+        lu_solve_real<M, LT>(e1, p1, c1);
+        lu_solve_cplx<M, LT>(e2r, e2i, p2, c2, c3);
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            x1[q] += (double)c1[q];
+            x2[q] += (double)c2[q];
+            x3[q] += (double)c3[q];
+        }
+    }
+
     /* e = E1^{-1} [fb + (d1 z1 + d2 z2 + d3 z3)/h]; returns RMS(e/sc). */
     __device__ __forceinline__ double estimate(const double (&fb)[M], double (&e)[M]) {
         /* d.Z = (d^T T) W */
         constexpr double DW1 = radau::D1 * radau::T11 + radau::D2 * radau::T21 + radau::D3;
         constexpr double DW2 = radau::D1 * radau::T12 + radau::D2 * radau::T22 + radau::D3;
         constexpr double DW3 = radau::D1 * radau::T13 + radau::D2 * radau::T23;
+        double b[M];
         LT v[M];
 #pragma unroll
-        for (int q = 0; q < M; ++q)
-            v[q] = (LT)(fb[q] + (DW1 * w[0][q] + DW2 * w[1][q] + DW3 * w[2][q]) * ih);
+        for (int q = 0; q < M; ++q) {
+            b[q] = fb[q] + (DW1 * w[0][q] + DW2 * w[1][q] + DW3 * w[2][q]) * ih;
+            v[q] = (LT)b[q];
+        }
         lu_solve_real<M, LT>(e1, p1, v);
+#pragma unroll
+        for (int q = 0; q < M; ++q) e[q] = (double)v[q];
+        if constexpr (kRefine) {
+            /* one refinement step against E1 in FP64, as in refine_newton */
+            const double g = radau::GAMMA * ih;
+            LT c[M];
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                double jx = 0.0;
+#pragma unroll
+                for (int j = 0; j < M; ++j) jx += lds[L::J0 + i * M + j] * e[j];
+                c[i] = (LT)(b[i] - g * e[i] + jx);
+            }
+            lu_solve_real<M, LT>(e1, p1, c);
+#pragma unroll
+            for (int q = 0; q < M; ++q) e[q] += (double)c[q];
+        }
         ++nsol;
         double acc = 0.0;
 #pragma unroll
         for (int q = 0; q < M; ++q) {
-            e[q] = (double)v[q];
             const double s = e[q] * isc[q];
             acc += s * s;
         }

@@ -24,13 +24,16 @@ from . import workloads as W
 from ._lib import MIXED, PERSISTENT
 
 
-def make_pools(small: bool = False):
+def make_pools(small: bool = False, given=None):
     """Device-resident cell pools.  small=True uses reduced 3D / m=16 pools
-    (for tests); the full pools are the benchmark's 2D, 3D and m=16 fields."""
+    (for tests); the full pools are the benchmark's 2D, 3D and m=16 fields.
+    given: already generated workloads to reuse, by pool name."""
     import torch
-    o2 = W.oregonator_2d()
-    o3 = W.oregonator_3d(side=64, n_total=64 ** 3, check=False) if small else W.oregonator_3d()
-    k16 = W.kinetics16(n=1 << 16) if small else W.kinetics16()
+    given = given or {}
+    o2 = given.get("oreg2d") or W.oregonator_2d()
+    o3 = given.get("oreg3d") or (W.oregonator_3d(side=64, n_total=64 ** 3, check=False)
+                                 if small else W.oregonator_3d())
+    k16 = given.get("kin16") or (W.kinetics16(n=1 << 16) if small else W.kinetics16())
     pools = {}
     for name, w in (("oreg2d", o2), ("oreg3d", o3), ("kin16", k16)):
         pools[name] = {"w": w, "states": torch.tensor(w.states, dtype=torch.float64, device="cuda")}

@@ -57,10 +57,7 @@ def test_fd_jacobian_oregonator(rd, orc, schedule, precision):
     yo, sto, reto = run_oracle(orc, w, jacobian=1)
     assert ret == reto == 0
     rep = compare(y, st, yo, sto, w.atol, label=f"fd s{schedule} p{precision}")
-    if precision == 0:
-        check(rep, w.n, w.rtol)
-    else:
-        assert rep["max_err"] <= 10 * w.rtol
+    check(rep, w.n, w.rtol)
 
 
 def test_bytecode_oregonator_2d(rd, orc):

@@ -229,10 +229,10 @@ def test_claim_order_does_not_change_results(rd):
 
 
 def test_oregonator_3d_fp64_and_mixed_vs_oracle(rd, orc):
-    """The 4 194 304-cell scroll-wave batch, FP64 and mixed (FP32 LU) on the
-    GPU; the oracle on the fixed 65 536-cell sample (seed 33).  FP64 is held to
-    1e-8 per cell; for mixed the per-cell error is reported and held to the
-    tolerance scale."""
+    """The 4 194 304-cell scroll-wave batch, FP64 and mixed (FP32 factors,
+    refined solves) on the GPU; the oracle on the fixed 65 536-cell sample
+    (seed 33).  Both paths are held to 1e-8 per cell with identical control
+    decisions."""
     w = W.oregonator_3d()
     idx = W.sample_indices(w.n, 65536, 33)
     s = w.subset(idx)
@@ -248,8 +248,22 @@ def test_oregonator_3d_fp64_and_mixed_vs_oracle(rd, orc):
     ym, stm, retm = run_gpu(rd, w, precision=1)
     assert retm == 0
     repm = compare(ym[:, idx], stm[:, idx], yo, sto, w.atol, label="3d mixed sampled")
-    assert repm["max_err"] <= 10 * w.rtol
-    assert repm["frac_within_tol"] >= 0.9
+    assert repm["max_err"] <= 1e-8
+    assert repm["trace_divergent"] == 0
+
+
+def test_oregonator_2d_mixed_every_cell_vs_oracle(rd, orc):
+    """Mixed precision (FP32 factors, every solve refined once against the FP64
+    matrices) on every cell of the 512 x 512 field: within 1e-8 of the FP64
+    oracle per cell, with the oracle's control decisions in every cell."""
+    w = W.oregonator_2d()
+    say("oregonator_2d mixed every cell, n", w.n)
+    y, st, ret = run_gpu(rd, w, precision=1)
+    yo, sto, reto = run_oracle(orc, w)
+    assert ret == reto == 0
+    rep = compare(y, st, yo, sto, w.atol, label="2d mixed every cell")
+    assert rep["max_err"] <= 1e-8
+    assert rep["trace_divergent"] == 0
 
 
 def test_oregonator_3d_every_cell_vs_oracle(rd, orc):

@@ -98,8 +98,7 @@ def test_mix_queues_for_memory_equals_alone_and_oracle(rd, orc, pools, precision
         assert reto == 0
         err = cell_rel_err(outs[j].cpu().numpy(), yo, w.atol)
         worst = max(worst, float(err.max()))
-        if precision == 0:
-            assert err.max() <= 1e-8, (j, r.pool, float(err.max()))
+        assert err.max() <= 1e-8, (j, r.pool, float(err.max()))
     say("in-mix results vs oracle, max rel err", worst)
 
 

@@ -135,3 +135,40 @@ def test_step_histogram():
     assert sum(h["cells"]) == n.size
     assert h["cells"][:4] == [2, 2, 2, 2] and h["max"] == 600
     assert h["p50"] == 7.0
+
+
+def test_reference_flops_by_hand():
+    """The reference per-event counts applied to known counters: one cell
+    with nstep 10, nfev 40, njac 3, ndec 6, nnewt 12 gives
+    40 f + 3 J + 6 factor + 12 Newton + 10 (estimate + step)."""
+    st = np.zeros((9, 1), dtype=np.int64)
+    st[1, 0], st[4, 0], st[5, 0], st[6, 0], st[8, 0] = 10, 40, 3, 6, 12
+    ref = R.reference_counts(R.KIND_OREGONATOR, 3)
+    assert R.reference_flops(st, ref) == 40 * 12 + 3 * 10 + 6 * 100 + 12 * 255 + 10 * (45 + 100)
+    # FP32 share of the mixed path: factorizations, the Newton solves, the
+    # estimate's solve
+    assert R.reference_fp32_flops(st, R.KIND_OREGONATOR, 3) == 6 * 100 + 12 * 90 + 10 * 18
+
+
+def test_reference_counts_by_nonzeros():
+    K = np.zeros((16, 16))
+    G = np.zeros((16, 16))
+    K[0, 1] = K[1, 0] = K[0, 0] = 1.0      # 3 nonzeros
+    G[2, 3] = 1.0                           # 1 nonzero
+    ref = R.reference_counts(R.KIND_KINETICS, 16, K, G)
+    assert ref["f"] == 2 * 3 + 2 * 1 + 2 * 16
+    assert ref["jac"] == 4 * 1 + 256
+    dense = R.reference_counts(R.KIND_KINETICS, 16)
+    assert dense["f"] == 4 * 256 + 32 and dense["jac"] == 3 * 256
+    assert R.reference_counts(R.KIND_NAGUMO, 1) is None
+
+
+def test_blended_bound_and_mixed_counts():
+    # 78.6 TFLOP of FP64 and 157.3 TFLOP of FP32 take one second each
+    assert R.blended_bound_s(78.6e12, 157.3e12) == pytest.approx(2.0)
+    # the mixed kernels add one refinement per solve: more FLOPs per Newton
+    # iteration and estimate, nothing else changes
+    a, b = R.event_flops(R.KIND_OREGONATOR, 3), R.event_flops(R.KIND_OREGONATOR, 3, mixed=True)
+    assert b["newton"] > a["newton"] and b["estimate"] > a["estimate"]
+    assert {k: a[k] for k in ("f", "jac", "factor", "step")} == \
+        {k: b[k] for k in ("f", "jac", "factor", "step")}
