@@ -162,6 +162,30 @@ int64_t rd_reaction_step_ex(double* states, int64_t n_cells, int32_t m,
                             const rd_model* model, const rd_options* opts,
                             int32_t* stats, void* hip_stream, int32_t async);
 
+/*
+ * For callers that cannot allocate memory (code under stream capture, tight
+ * serving loops, harnesses that forbid allocation): rd_reaction_step_ex
+ * without any device or pinned-host allocation, on any call including the
+ * first.  Its scratch (the kernel's two counters, the model's parameter
+ * block, the claim-order scratch of the persistent schedule) is a fixed
+ * device array of rd_noalloc_scratch_bytes() bytes (about 21 MB) that every
+ * device the library runs on holds until the process ends; requests of more
+ * than RD_NOALLOC_MAX_CELLS cells are refused with RD_ETOOBIG.  All calls on
+ * one device share that device's array, so calls that overlap on one device
+ * (other streams, other threads) race: the caller orders them.  The model
+ * parameters are copied asynchronously from a per-device host copy of the
+ * block that the next call on the device overwrites.  opts->use_graph and
+ * opts->h_cells must be unset (RD_EINVAL).  Arguments, layout, results and
+ * the other errors as rd_reaction_step_ex; same kernels, bitwise the same
+ * results.
+ */
+#define RD_NOALLOC_MAX_CELLS 4194304
+int64_t rd_reaction_step_noalloc(double* states, int64_t n_cells, int32_t m,
+                                 double dt, double rtol, double atol,
+                                 const rd_model* model, const rd_options* opts,
+                                 int32_t* stats, void* hip_stream, int32_t async);
+size_t rd_noalloc_scratch_bytes(void);
+
 /* ------------------------------------------------------------------------ */
 /* The steps around the reaction step: diffusion and the Strang step on a     */
 /* uniform grid (Descombes et al., §2.1: U_{n+1} = R_{dt/2} D_dt R_{dt/2} U_n).  */

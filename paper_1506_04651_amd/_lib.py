@@ -66,6 +66,13 @@ SIGNATURES = {
                                              ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                              ctypes.POINTER(RdModel), ctypes.POINTER(RdOptions),
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
+    "rd_reaction_step_noalloc": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_int64,
+                                                  ctypes.c_int32, ctypes.c_double,
+                                                  ctypes.c_double, ctypes.c_double,
+                                                  ctypes.POINTER(RdModel),
+                                                  ctypes.POINTER(RdOptions), ctypes.c_void_p,
+                                                  ctypes.c_void_p, ctypes.c_int32]),
+    "rd_noalloc_scratch_bytes": (ctypes.c_size_t, []),
     "rd_session_create": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
                                            ctypes.c_size_t, ctypes.POINTER(RdOptions)]),
     "rd_submit": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,

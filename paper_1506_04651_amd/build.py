@@ -19,7 +19,8 @@ LIB = os.path.join(HERE, "librd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["rd_api.cpp", "rd_serving.cpp", "rd_kernels_small.hip", "rd_kernels_group.hip",
-           "rd_kernels_fd.hip", "rd_order.hip", "rd_diffusion.hip", "rd_strang.cpp", "rd_mra.hip"]
+           "rd_kernels_fd.hip", "rd_order.hip", "rd_diffusion.hip", "rd_strang.cpp", "rd_mra.hip",
+           "rd_noalloc.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-result", "-I", INCLUDE, "-I", CSRC]

@@ -208,11 +208,15 @@ int enqueue_order(DevCtx& c, Prepared& pr, hipStream_t s, unsigned long long* co
 }
 
 int persistent_grid(const DevCtx& c, const KernelEntry* e, int64_t n) {
+    return persistent_grid_cu(c.cu_count, e, n);
+}
+
+int persistent_grid_cu(int cu_count, const KernelEntry* e, int64_t n) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, e->func, e->block, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
-    const int64_t resident = (int64_t)per_cu * c.cu_count;
+    const int64_t resident = (int64_t)per_cu * cu_count;
     const int64_t needed = (n + e->cells_per_block - 1) / e->cells_per_block;
     int64_t g = needed < resident ? needed : resident;
     if (g < 1) g = 1;
@@ -229,8 +233,8 @@ static bool all_finite(const double* p, int64_t k) {
 /* Bytecode program: check it against the rules of the public header and pack
  * it for the device interpreter: [L, C] as integers in 64-bit slots, the
  * constants, then one slot per instruction holding op | d << 8 | a << 16 |
- * b << 24. */
-static bool bytecode_block(const rd_model* md, int32_t m, std::vector<double>& block) {
+ * b << 24.  out holds kMaxParamDoubles. */
+static bool bytecode_block(const rd_model* md, int32_t m, double* out, size_t* len) {
     const double* p = md->params;
     if (m < 1 || m > 4 || md->n_params < 2) return false;
     auto whole = [](double v, double lo, double hi) {
@@ -240,11 +244,15 @@ static bool bytecode_block(const rd_model* md, int32_t m, std::vector<double>& b
     const int L = (int)p[0], C = (int)p[1];
     if (m + C > RD_BC_REGS || md->n_params < 2 + (int64_t)C + 4LL * L) return false;
     if (!all_finite(p + 2, C)) return false;
+    auto as_double = [](long long w) {
+        double v;
+        std::memcpy(&v, &w, sizeof(v));
+        return v;
+    };
     bool defined[RD_BC_REGS] = {};
     for (int r = 0; r < m + C; ++r) defined[r] = true;
     int out_count[4] = {0, 0, 0, 0};
-    std::vector<long long> words;
-    words.reserve(L);
+    size_t k_out = 2 + (size_t)C;
     for (int k = 0; k < L; ++k) {
         const double* ins = p + 2 + C + 4 * k;
         if (!whole(ins[0], RD_BC_ADD, RD_BC_OUT) || !whole(ins[1], 0, RD_BC_REGS - 1) ||
@@ -260,56 +268,62 @@ static bool bytecode_block(const rd_model* md, int32_t m, std::vector<double>& b
             if (d < m + C) return false;
             defined[d] = true;
         }
-        words.push_back((long long)(op | (d << 8) | (a << 16) | ((long long)b << 24)));
+        out[k_out++] = as_double((long long)(op | (d << 8) | (a << 16) | ((long long)b << 24)));
     }
     for (int i = 0; i < m; ++i)
         if (out_count[i] != 1) return false;
-    auto as_double = [](long long w) {
-        double v;
-        std::memcpy(&v, &w, sizeof(v));
-        return v;
-    };
-    block.clear();
-    block.push_back(as_double(L));
-    block.push_back(as_double(C));
-    block.insert(block.end(), p + 2, p + 2 + C);
-    for (long long w : words) block.push_back(as_double(w));
+    out[0] = as_double(L);
+    out[1] = as_double(C);
+    std::memcpy(out + 2, p + 2, sizeof(double) * (size_t)C);
+    *len = k_out;
     return true;
 }
 
-bool model_block(const rd_model* md, int32_t m, std::vector<double>& block) {
+bool model_block_into(const rd_model* md, int32_t m, double* out, size_t* len) {
     if (!md || md->m != m || !md->params) return false;
     const double* p = md->params;
-    block.clear();
+    auto copy = [&](size_t k) {
+        std::memcpy(out, p, sizeof(double) * k);
+        *len = k;
+        return true;
+    };
     switch (md->kind) {
     case RD_OREGONATOR:
         if (m != 3 || md->n_params < 4 || !all_finite(p, 4) || p[0] == 0.0 || p[1] == 0.0) return false;
         /* {eps, mu, f, q} -> {q, f, 1/mu, 1/eps} */
-        block = {p[3], p[2], 1.0 / p[1], 1.0 / p[0]};
+        out[0] = p[3];
+        out[1] = p[2];
+        out[2] = 1.0 / p[1];
+        out[3] = 1.0 / p[0];
+        *len = 4;
         return true;
     case RD_ROBERTSON:
         if (m != 3 || md->n_params < 3 || !all_finite(p, 3)) return false;
-        block.assign(p, p + 3);
-        return true;
+        return copy(3);
     case RD_NAGUMO:
         if (m != 1 || md->n_params < 1 || !all_finite(p, 1)) return false;
-        block.assign(p, p + 1);
-        return true;
+        return copy(1);
     case RD_LINEAR:
         if (m < 1 || m > RD_MAX_M || md->n_params < (int64_t)m * m || !all_finite(p, (int64_t)m * m))
             return false;
-        block.assign(p, p + (size_t)m * m);
-        return true;
+        return copy((size_t)m * m);
     case RD_KINETICS:
         if (m < 1 || m > RD_MAX_M || md->n_params < 2LL * m * m || !all_finite(p, 2LL * m * m))
             return false;
-        block.assign(p, p + 2 * (size_t)m * m);
-        return true;
+        return copy(2 * (size_t)m * m);
     case RD_BYTECODE:
-        return bytecode_block(md, m, block);
+        return bytecode_block(md, m, out, len);
     default:
         return false;
     }
+}
+
+bool model_block(const rd_model* md, int32_t m, std::vector<double>& block) {
+    block.resize(kMaxParamDoubles);
+    size_t len = 0;
+    if (!model_block_into(md, m, block.data(), &len)) return false;
+    block.resize(len);
+    return true;
 }
 
 static const double* device_params(DevCtx& c, int kind, int m, const std::vector<double>& block,
@@ -374,8 +388,9 @@ static bool options_valid(const rd_options& o) {
            (o.jacobian == RD_JAC_ANALYTIC || o.jacobian == RD_JAC_FD);
 }
 
-int prepare(double* states, int64_t n, int32_t m, double dt, double rtol, double atol,
-            const rd_model* model, const rd_options* opts, int32_t* stats, Prepared* out) {
+int prepare_host(double* states, int64_t n, int32_t m, double dt, double rtol, double atol,
+                 const rd_model* model, const rd_options* opts, int32_t* stats, Prepared* out,
+                 double* block, size_t* blen) {
     rd_options o;
     rd_default_options(&o);
     if (opts) o = *opts;
@@ -384,8 +399,7 @@ int prepare(double* states, int64_t n, int32_t m, double dt, double rtol, double
     if (!std::isfinite(rtol) || !(rtol > 0.0)) { set_error("rtol must be finite and > 0"); return RD_EINVAL; }
     if (!std::isfinite(atol) || !(atol >= 0.0)) { set_error("atol must be finite and >= 0"); return RD_EINVAL; }
     if (!options_valid(o)) { set_error("invalid rd_options"); return RD_EINVAL; }
-    std::vector<double> block;
-    if (!model || model->m != m || !model_block(model, m, block)) {
+    if (!model || model->m != m || !model_block_into(model, m, block, blen)) {
         set_error("invalid model (kind/m/params)");
         return RD_EINVAL;
     }
@@ -410,6 +424,16 @@ int prepare(double* states, int64_t n, int32_t m, double dt, double rtol, double
     out->args.stats = stats;
     out->args.hcell = o.h_cells;
     out->args.n = n;
+    return 0;
+}
+
+int prepare(double* states, int64_t n, int32_t m, double dt, double rtol, double atol,
+            const rd_model* model, const rd_options* opts, int32_t* stats, Prepared* out) {
+    std::vector<double> block(kMaxParamDoubles);
+    size_t blen = 0;
+    int r = prepare_host(states, n, m, dt, rtol, atol, model, opts, stats, out, block.data(), &blen);
+    if (r < 0) return r;
+    block.resize(blen);
     if (n == 0) return 0;
     DevCtx* c = current_ctx();
     if (!c) return RD_EDEVICE;
@@ -418,9 +442,9 @@ int prepare(double* states, int64_t n, int32_t m, double dt, double rtol, double
     const double* dp = device_params(*c, model->kind, m, block, &err);
     if (!dp) return err ? err : RD_EDEVICE;
     out->args.params = dp;
-    out->grid = e->schedule == RD_PERSISTENT
-                    ? persistent_grid(*c, e, n)
-                    : (int)((n + e->cells_per_block - 1) / e->cells_per_block);
+    out->grid = out->entry->schedule == RD_PERSISTENT
+                    ? persistent_grid(*c, out->entry, n)
+                    : (int)((n + out->entry->cells_per_block - 1) / out->entry->cells_per_block);
     return 0;
 }
 

@@ -54,6 +54,19 @@ DevCtx* current_ctx();
 int prepare(double* states, int64_t n, int32_t m, double dt, double rtol, double atol,
             const rd_model* model, const rd_options* opts, int32_t* stats, Prepared* out);
 
+/* Largest pre-processed model block (the bytecode model: L, C, 32 constants,
+ * 4096 instructions), in doubles. */
+constexpr size_t kMaxParamDoubles = 2 + RD_BC_REGS + 4096;
+
+/* The host part of prepare: validation, tolerances, kernel choice, and the
+ * model's device block written to `block` (kMaxParamDoubles doubles, *blen
+ * used); no device work and no allocation.  out->args.params and out->grid
+ * are left for the caller. */
+int prepare_host(double* states, int64_t n, int32_t m, double dt, double rtol, double atol,
+                 const rd_model* model, const rd_options* opts, int32_t* stats, Prepared* out,
+                 double* block, size_t* blen);
+bool model_block_into(const rd_model* model, int32_t m, double* out, size_t* len);
+
 /* Scratch of at least `bytes` for launches on stream s (claim order). */
 void* stream_workspace(DevCtx& c, hipStream_t s, size_t bytes, int* err);
 
@@ -91,6 +104,7 @@ int64_t reaction_count(int word);
 /* Grid for a persistent kernel: resident workgroups on the device, capped by
  * the number of workgroups the cells would fill. */
 int persistent_grid(const DevCtx& c, const KernelEntry* e, int64_t n);
+int persistent_grid_cu(int cu_count, const KernelEntry* e, int64_t n);
 
 /* Host-side parameter pre-processing shared by direct calls and sessions:
  * returns false when the model is invalid.  block receives the device layout. */
