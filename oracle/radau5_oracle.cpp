@@ -230,7 +230,7 @@ struct Model {
 /* Validation of a bytecode program against the rules stated in rdo.h. */
 bool bytecode_from_abi(const rdo_model* mm, Model& out) {
     const int m = mm->m;
-    if (m < 1 || m > 4 || !mm->params || mm->n_params < 2) return false;
+    if (m < 1 || m > 16 || !mm->params || mm->n_params < 2) return false;
     const double* p = mm->params;
     auto is_int = [](double v, double lo, double hi) {
         return std::isfinite(v) && v == std::floor(v) && v >= lo && v <= hi;

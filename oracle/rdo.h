@@ -31,13 +31,13 @@ enum {
     RDO_NAGUMO     = 3, /* m=1, params {k}                                      */
     RDO_LINEAR     = 4, /* any m, params {K[m*m] row-major}: f(u) = K u          */
     RDO_ROBERTSON  = 5, /* m=3, params {k1, k2, k3}                             */
-    RDO_BYTECODE   = 6  /* m=1..4, f given as a register program, see below      */
+    RDO_BYTECODE   = 6  /* m=1..16, f given as a register program, see below     */
 };
 
 /*
  * Bytecode model (a user-supplied f without compiled code).  params =
  *   [L, C, c_0 .. c_{C-1}, then L instructions of 4 doubles (op, d, a, b)]
- * over 32 FP64 registers r[0..32): r[0..m) hold u (read only), r[m..m+C) the
+ * over 64 FP64 registers r[0..64): r[0..m) hold u (read only), r[m..m+C) the
  * constants, the rest are temporaries.  Ops:
  *   1 ADD r[d] = r[a] + r[b]    2 SUB r[d] = r[a] - r[b]   3 MUL r[d] = r[a] * r[b]
  *   4 DIV r[d] = r[a] / r[b]    5 NEG r[d] = -r[a]         6 EXP r[d] = exp(r[a])
@@ -47,7 +47,7 @@ enum {
  * of f_0 .. f_{m-1} exactly once.  Its Jacobian is always taken by finite
  * differences.
  */
-#define RDO_BC_REGS 32
+#define RDO_BC_REGS 64
 enum { RDO_BC_ADD = 1, RDO_BC_SUB, RDO_BC_MUL, RDO_BC_DIV, RDO_BC_NEG, RDO_BC_EXP,
        RDO_BC_LOG, RDO_BC_POW, RDO_BC_OUT };
 
