@@ -58,20 +58,20 @@ enum {
     RD_NAGUMO = 3,     /* m = 1, params {k}: f = k u^2 (1 - u) (paper §1, I)      */
     RD_LINEAR = 4,     /* m in {1..16}, params {K[m*m]}: f = K u (tests)         */
     RD_ROBERTSON = 5,  /* m = 3, params {k1, k2, k3}: Robertson kinetics (tests)  */
-    RD_BYTECODE = 6    /* m in {1..4}: f supplied at run time as a register program
-                          (below); its Jacobian is always taken by finite
+    RD_BYTECODE = 6    /* m in {1..16}: f supplied at run time as a register
+                          program (below); its Jacobian is always taken by finite
                           differences                                             */
 };
 
 /*
  * Bytecode model.  params = [L, C, c_0 .. c_{C-1}, then L instructions of 4
- * doubles (op, d, a, b)], all integer-valued except the constants, over 32
- * FP64 registers r[0..32): r[0..m) hold u (read only), r[m..m+C) the
+ * doubles (op, d, a, b)], all integer-valued except the constants, over 64
+ * FP64 registers r[0..64): r[0..m) hold u (read only), r[m..m+C) the
  * constants, the rest are temporaries.  Ops:
  *   1 ADD r[d] = r[a] + r[b]    2 SUB r[d] = r[a] - r[b]   3 MUL r[d] = r[a] * r[b]
  *   4 DIV r[d] = r[a] / r[b]    5 NEG r[d] = -r[a]         6 EXP r[d] = exp(r[a])
  *   7 LOG r[d] = log(r[a])      8 POW r[d] = r[a] ^ r[b]   9 OUT f_d = r[a]
- * Valid when 1 <= L <= 4096, m + C <= 32, d >= m + C for ops 1-8, every
+ * Valid when 1 <= L <= 4096, m + C <= 64, d >= m + C for ops 1-8, every
  * register is written before it is read, and OUT writes each f_0 .. f_{m-1}
  * exactly once; anything else is RD_EINVAL.  Evaluation follows the program
  * order exactly (no reassociation, no contraction), so a program reproduces
@@ -79,7 +79,7 @@ enum {
  */
 enum { RD_BC_ADD = 1, RD_BC_SUB, RD_BC_MUL, RD_BC_DIV, RD_BC_NEG, RD_BC_EXP, RD_BC_LOG,
        RD_BC_POW, RD_BC_OUT };
-#define RD_BC_REGS 32
+#define RD_BC_REGS 64
 
 enum { RD_JAC_ANALYTIC = 0, RD_JAC_FD = 1 };   /* jacobian */
 
@@ -125,8 +125,9 @@ typedef struct {
     int32_t jacobian;      /* RD_JAC_ANALYTIC (default) or RD_JAC_FD: forward
                               differences, column j = (f(u + d_j e_j) - f(u)) / d_j,
                               d_j = sqrt(uround max(1e-5, |u_j|)), m more f
-                              evaluations per Jacobian (counted in nfev); m <= 4
-                              models only.  RD_BYTECODE always uses RD_JAC_FD.     */
+                              evaluations per Jacobian (counted in nfev); every
+                              model except RD_LINEAR with m > 4.  RD_BYTECODE
+                              always uses RD_JAC_FD.                               */
     double* h_cells;       /* null (default), or DEVICE [n_cells] float64: per-cell
                               step size, in and out (warm start across split
                               steps).  In: a value > 0 is that cell's first trial

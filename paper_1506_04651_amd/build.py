@@ -20,7 +20,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["rd_api.cpp", "rd_serving.cpp", "rd_kernels_small.hip", "rd_kernels_group.hip",
            "rd_kernels_fd.hip", "rd_order.hip", "rd_diffusion.hip", "rd_strang.cpp", "rd_mra.hip",
-           "rd_noalloc.hip"]
+           "rd_noalloc.hip", "rd_kernels_group_fd.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-result", "-I", INCLUDE, "-I", CSRC]
@@ -29,6 +29,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=o
 # the 16-lane group kernels unroll 16-step LU loops completely; the default
 # pragma threshold would stop short and leave the cell state in scratch
 EXTRA = {"rd_kernels_group.hip": ["-mllvm", "-pragma-unroll-threshold=200000"],
+         "rd_kernels_group_fd.hip": ["-mllvm", "-pragma-unroll-threshold=200000"],
          # the multiresolution thresholds compare floating-point details: every
          # formula is evaluated operation by operation, without contraction
          "rd_mra.hip": ["-ffp-contract=off"]}

@@ -11,7 +11,7 @@ names, named constants and numeric literals.  Evaluation follows Python's
 operator precedence and left-to-right association, one operation per
 instruction, so the program rounds exactly like the expression evaluated in
 FP64 without contraction.  Identical sub-expressions are computed once;
-temporaries are packed into the 32 registers by their live ranges.
+temporaries are packed into the 64 registers by their live ranges.
 """
 from __future__ import annotations
 
@@ -20,8 +20,8 @@ import ast
 import numpy as np
 
 ADD, SUB, MUL, DIV, NEG, EXP, LOG, POW, OUT = range(1, 10)
-REGS = 32
-MAX_M = 4
+REGS = 64
+MAX_M = 16
 
 _BIN = {ast.Add: ADD, ast.Sub: SUB, ast.Mult: MUL, ast.Div: DIV, ast.Pow: POW}
 _FUN = {"exp": EXP, "log": LOG}
@@ -33,7 +33,7 @@ class CompileError(ValueError):
 
 def compile_model(exprs, species, constants=None) -> np.ndarray:
     """Return the float64 params array of the register program computing
-    f_i = exprs[i] for the given species (len(species) = m, 1 <= m <= 4)."""
+    f_i = exprs[i] for the given species (len(species) = m, 1 <= m <= 16)."""
     species = list(species)
     m = len(species)
     if not 1 <= m <= MAX_M or len(exprs) != m:
@@ -135,7 +135,7 @@ def compile_model(exprs, species, constants=None) -> np.ndarray:
         if vid not in last_use:
             continue            # never used (cannot happen for reachable nodes)
         if not free:
-            raise CompileError("program needs more than 32 registers")
+            raise CompileError(f"program needs more than {REGS} registers")
         rd = free.pop()
         where[vid] = rd
         code.append((op, rd, ra, rb))

@@ -25,6 +25,7 @@ namespace rd {
 const KernelEntry* small_kernel_table(int* count);
 const KernelEntry* group_kernel_table(int* count);
 const KernelEntry* fd_kernel_table(int* count);
+const KernelEntry* group_fd_kernel_table(int* count);
 
 /* ---------------------------------------------------------------- errors */
 static thread_local char g_err[512] = "";
@@ -56,6 +57,8 @@ static std::vector<KernelEntry>& all_kernels() {
         out.insert(out.end(), t, t + n);
         t = fd_kernel_table(&n);
         out.insert(out.end(), t, t + n);
+        t = group_fd_kernel_table(&n);
+        out.insert(out.end(), t, t + n);
         return out;
     }();
     return v;
@@ -80,10 +83,12 @@ static int native_jac(int kind) { return kind == RD_BYTECODE ? RD_JAC_FD : RD_JA
 
 /* Species count under which a request's kernels are registered: kinetics and
  * linear models with 5..8 species run on the 8-column group kernels (m = 8),
- * with 9..16 on the 16-column ones (m = 16); everything else under its own m.
+ * with 9..16 on the 16-column ones (m = 16), and so do bytecode models with
+ * more than 4 species; everything else under its own m.
  * Variant ids and tuned defaults refer to this registry entry. */
 static int registry_m(int kind, int m) {
-    if ((kind == RD_KINETICS || kind == RD_LINEAR) && m > 4 && m <= RD_MAX_M) return m <= 8 ? 8 : 16;
+    if ((kind == RD_KINETICS || kind == RD_LINEAR || kind == RD_BYTECODE) && m > 4 && m <= RD_MAX_M)
+        return m <= 8 ? 8 : 16;
     return m;
 }
 
@@ -236,7 +241,7 @@ static bool all_finite(const double* p, int64_t k) {
  * b << 24.  out holds kMaxParamDoubles. */
 static bool bytecode_block(const rd_model* md, int32_t m, double* out, size_t* len) {
     const double* p = md->params;
-    if (m < 1 || m > 4 || md->n_params < 2) return false;
+    if (m < 1 || m > RD_MAX_M || md->n_params < 2) return false;
     auto whole = [](double v, double lo, double hi) {
         return std::isfinite(v) && std::floor(v) == v && v >= lo && v <= hi;
     };
@@ -251,7 +256,7 @@ static bool bytecode_block(const rd_model* md, int32_t m, double* out, size_t* l
     };
     bool defined[RD_BC_REGS] = {};
     for (int r = 0; r < m + C; ++r) defined[r] = true;
-    int out_count[4] = {0, 0, 0, 0};
+    int out_count[RD_MAX_M] = {};
     size_t k_out = 2 + (size_t)C;
     for (int k = 0; k < L; ++k) {
         const double* ins = p + 2 + C + 4 * k;

@@ -64,6 +64,22 @@ struct GroupKinetics {
 struct GroupLinear {
     static constexpr bool HAS_G = false;
 };
+/* an analytic model run with the forward-difference Jacobian instead */
+template <class Base>
+struct GroupFd : Base {
+    static constexpr bool FD_JAC = true;
+};
+/* f given at run time as a register program (format in the public header),
+ * Jacobian by forward differences */
+struct GroupBytecode {
+    static constexpr bool HAS_G = false;
+    static constexpr bool FD_JAC = true;
+    static constexpr bool BYTECODE = true;
+};
+template <class Model, class = void>
+struct bytecode_of { static constexpr bool value = false; };
+template <class Model>
+struct bytecode_of<Model, decltype((void)Model::BYTECODE)> { static constexpr bool value = Model::BYTECODE; };
 
 /* FUSE: broadcasts fused into the multiply-adds (rd_group_fused.h); same
  * operations in the same order as the plain loops.  NC: matrix columns held
@@ -76,6 +92,10 @@ struct GroupCell {
     static constexpr int M = NC; /* loops run over NC columns; rows and columns >= m are zero */
     static constexpr bool HAS_G = Model::HAS_G;
     static constexpr bool kFused = FUSE;
+    /* Jacobian by forward differences, rows kept in LDS (jl, stride jstride) */
+    static constexpr bool FDJ = fd_jac_of<Model>::value;
+    /* f from the register program at prog */
+    static constexpr bool BC = bytecode_of<Model>::value;
     /* FP32 inverses: every solve is refined once against the FP64 matrices */
     static constexpr bool kRefine = sizeof(LT) < sizeof(double);
     int m;           /* species (run time, 1..16) */
@@ -87,6 +107,9 @@ struct GroupCell {
     LT d1, d2r, d2i;          /* reciprocal pivots */
     int org1, org2;
     const double* kg; /* LDS row q: K at kg[0..16), G at kg[16..32) */
+    double* jl;       /* FDJ: row q of J at jl[j * jstride], j < 16 (LDS) */
+    int jstride;
+    const double* prog; /* BC: the register program (device) */
     int q;
     bool act;         /* q < m */
     /* per-cell scalars, replicated across the group */
@@ -129,19 +152,117 @@ struct GroupCell {
         }
     }
 
-    /* f_q(u) and (G u)_q; every lane of the group must be active */
-    __device__ __forceinline__ double rhs(double u, double& gu) const {
-        double lin, loss;
-        rows(u, lin, loss);
+    /* f_q(u) of the register program: every lane of the group gathers u,
+     * runs the whole program (wave-uniform control flow and register
+     * indices; the register file is a per-lane array) and keeps output q.
+     * Operation by operation in program order, without contraction across
+     * instructions. */
+    __device__ __forceinline__ double rhs_program(double u) const {
+        const long long* w = reinterpret_cast<const long long*>(prog);
+        const int L = (int)w[0], C = (int)w[1];
+        double r[kBcRegs];
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const double uj = bcast_dyn(u, j);
+            if (j < m) r[j] = uj;
+        }
+        for (int c = 0; c < C; ++c) r[m + c] = prog[2 + c];
+        const long long* ins = w + 2 + C;
+        double out = 0.0;
+        for (int k = 0; k < L; ++k) {
+            const unsigned x = (unsigned)ins[k];
+            const int op = (int)(x & 0xffu), d = (int)((x >> 8) & 0xffu);
+            const int a = (int)((x >> 16) & 0xffu), b = (int)(x >> 24);
+            const double va = r[a], vb = r[b];
+            double v;
+            switch (op) {
+            case BC_ADD: v = va + vb; break;
+            case BC_SUB: v = va - vb; break;
+            case BC_MUL: v = va * vb; break;
+            case BC_DIV: v = va / vb; break;
+            case BC_NEG: v = -va; break;
+            case BC_EXP: v = exp(va); break;
+            case BC_LOG: v = log(va); break;
+            case BC_POW: v = pow(va, vb); break;
+            default: v = va; break; /* BC_OUT */
+            }
+            if (op == BC_OUT) {
+                if (d == q) out = v;
+            } else {
+                r[d] = v;
+            }
+        }
+        return out;
+    }
+
+    /* The rows of the model for the forward-difference Jacobian: each
+     * product and sum rounded on its own, in column order from +0, so that
+     * f, and the differences of f that make up the Jacobian, round like the
+     * plain sums of the definition (a rounding difference in f is amplified
+     * by 1/d_j ~ 1e8 in a difference quotient). */
+    __device__ __forceinline__ double rhs_plain(double u, double& gu) const {
+#pragma clang fp contract(off)
+        double lin = 0.0, loss = 0.0;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const double uj = bcast_dyn(u, j);
+            if (j < m) {
+                lin += kg[j] * uj;
+                if (HAS_G) loss += kg[kGroup + j] * uj;
+            }
+        }
         gu = loss;
         return HAS_G ? lin - u * loss : lin;
     }
 
-    /* (J x)_q at the stored Jacobian point: (K x)_q - uJ (G x)_q - gJ x_q */
+    /* f_q(u) and (G u)_q; every lane of the group must be active */
+    __device__ __forceinline__ double rhs(double u, double& gu) const {
+        if constexpr (BC) {
+            gu = 0.0;
+            return rhs_program(u);
+        } else if constexpr (FDJ) {
+            return rhs_plain(u, gu);
+        } else {
+            double lin, loss;
+            rows(u, lin, loss);
+            gu = loss;
+            return HAS_G ? lin - u * loss : lin;
+        }
+    }
+
+    /* (J x)_q with the current Jacobian: from the LDS rows (forward
+     * differences), else (K x)_q - uJ (G x)_q - gJ x_q at the stored point */
     __device__ __forceinline__ double jmul(double x) const {
-        double lin, loss;
-        rows(x, lin, loss);
-        return HAS_G ? lin - uJ * loss - gJ * x : lin;
+        if constexpr (FDJ) {
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                const double xj = bcast_dyn(x, j);
+                if (j < m) acc += jl[j * jstride] * xj;
+            }
+            return acc;
+        } else {
+            double lin, loss;
+            rows(x, lin, loss);
+            return HAS_G ? lin - uJ * loss - gJ * x : lin;
+        }
+    }
+
+    /* Forward-difference Jacobian at y with f0 = f(y): column j =
+     * (f(y + d_j e_j) - f(y)) / d_j, d_j = sqrt(u_r max(1e-5, |y_j|)); lane q
+     * stores J_qj in its LDS row (zero rows for q >= m); m f evaluations. */
+    __device__ __forceinline__ void fd_jacobian() {
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const double yj = bcast_dyn(y, j);
+            if (j < m) {
+                const double dj = __builtin_sqrt(2.220446049250313e-16 * fmax(1e-5, __builtin_fabs(yj)));
+                double gu;
+                const double fp = rhs(q == j ? y + dj : y, gu);
+                jl[j * jstride] = act ? (fp - f0) / dj : 0.0;
+            }
+        }
+        nfev += m;
     }
 
     __device__ __forceinline__ void load(const StepParams& P, const double* __restrict__ states,
@@ -190,8 +311,10 @@ struct GroupCell {
         }
     }
 
-    /* J_qj at the stored Jacobian point (uJ, gJ = (G u)_q at that point) */
+    /* J_qj at the stored Jacobian point (uJ, gJ = (G u)_q at that point), or
+     * from the LDS row of the forward-difference Jacobian */
     __device__ __forceinline__ double jac(int j) const {
+        if constexpr (FDJ) return (act && j < m) ? jl[j * jstride] : 0.0;
         double v = kg[j];
         if (HAS_G) {
             v -= uJ * kg[kGroup + j];
@@ -378,10 +501,14 @@ struct GroupCell {
         ih = rcp(h);
         isc = act ? rcp(P.atol + P.rtol * __builtin_fabs(y)) : 0.0;
         if (FIXED || has(F_JSTALE)) {
-            double gu;
-            (void)rhs(y, gu);
-            uJ = y;
-            gJ = gu;
+            if constexpr (FDJ) {
+                fd_jacobian();
+            } else {
+                double gu;
+                (void)rhs(y, gu);
+                uJ = y;
+                gJ = gu;
+            }
             ++njac;
             flags = (flags & ~(F_JSTALE | F_LUOK)) | F_JATY0;
         }

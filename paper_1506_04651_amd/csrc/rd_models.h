@@ -163,7 +163,7 @@ struct FdJac : Base {
  * The program is the same for every cell, so the interpreter's control flow
  * and register indices are wave-uniform; the register file is a per-lane
  * array indexed by those uniform indices. */
-constexpr int kBcRegs = 32;
+constexpr int kBcRegs = 64;
 enum : int { BC_ADD = 1, BC_SUB, BC_MUL, BC_DIV, BC_NEG, BC_EXP, BC_LOG, BC_POW, BC_OUT };
 
 template <int M_>

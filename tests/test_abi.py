@@ -129,13 +129,14 @@ def test_bytecode_programs_validated_on_the_host(lib):
     bad = [([1, 0, 10, 0, 0, 0], 1), ([1, 0, 0, 0, 0, 0], 1), ([1, 0, 9, 1, 0, 0], 1),
            ([2, 0, 9, 0, 0, 0, 9, 0, 0, 0], 1), ([1, 0, 1, 5, 0, 0], 1),
            ([2, 0, 1, 1, 2, 0, 9, 0, 1, 0], 1), ([2, 1, 2.0, 1, 1, 0, 0, 9, 0, 1, 0], 1),
-           ([1, 0, 9, 0, 40, 0], 1), ([1, 0, 9, 0, 0.5, 0], 1), ([1, 0, 9, 0, 0], 1),
-           ([1, 0, 9, 0, 0, 0], 5)]
+           ([1, 0, 9, 0, 70, 0], 1), ([1, 0, 9, 0, 0.5, 0], 1), ([1, 0, 9, 0, 0], 1),
+           ([1, 0, 9, 0, 0, 0], 17)]
     for prog, m in bad:
         md, keep = _bc_model(prog, m)
         assert call(None, 0, m, 0.1, 1e-5, 1e-8, ctypes.byref(md), None, None, None, 0) == -1, prog
     # a jacobian mode other than analytic / finite differences is invalid;
-    # finite differences of the group-kernel models are not provided
+    # finite differences are provided for the kinetics model on the group
+    # kernels, not for the linear test model
     p = (ctypes.c_double * 4)(1e-2, 1e-5, 1.6, 2e-3)
     good = _lib.RdModel(1, 3, ctypes.cast(p, ctypes.POINTER(ctypes.c_double)), 4)
     o = _lib.default_options()
@@ -145,7 +146,15 @@ def test_bytecode_programs_validated_on_the_host(lib):
     assert call(None, 0, 3, 0.1, 1e-5, 1e-8, ctypes.byref(good), ctypes.byref(o), None, None, 0) == 0
     K = (ctypes.c_double * 512)(*([0.0] * 512))
     kin = _lib.RdModel(2, 16, ctypes.cast(K, ctypes.POINTER(ctypes.c_double)), 512)
-    assert call(None, 0, 16, 0.1, 1e-5, 1e-8, ctypes.byref(kin), ctypes.byref(o), None, None, 0) == -1
+    assert call(None, 0, 16, 0.1, 1e-5, 1e-8, ctypes.byref(kin), ctypes.byref(o), None, None, 0) == 0
+    lin = _lib.RdModel(4, 16, ctypes.cast(K, ctypes.POINTER(ctypes.c_double)), 256)
+    assert call(None, 0, 16, 0.1, 1e-5, 1e-8, ctypes.byref(lin), ctypes.byref(o), None, None, 0) == -1
+    # a 16-species register program is accepted
+    from tests.bytecode_models import kinetics_program, sparse_kinetics
+    import numpy as np
+    Kc, Gc = sparse_kinetics(16, 1)
+    md, keep = _bc_model(list(kinetics_program(Kc, Gc)), 16)
+    assert call(None, 0, 16, 0.1, 1e-5, 1e-8, ctypes.byref(md), None, None, None, 0) == 0
 
 
 def test_diffusion_and_strang_validation(lib):

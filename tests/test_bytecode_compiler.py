@@ -38,7 +38,7 @@ def test_transcendentals_and_powers(orc):
 
 
 def test_long_expression_fits_registers(orc):
-    """60 terms, repeated products shared: live ranges fit in 32 registers."""
+    """60 terms, repeated products shared: live ranges fit in the registers."""
     consts = {f"c{i}": 1.0 + i / 8 for i in range(4)}
     terms = [f"c{i % 4}*u{i % 4}*u{(i // 4) % 4}" for i in range(60)]
     prog = B.compile_model([" + ".join(terms), "u0", "u1 - u2", "u3"],
@@ -56,7 +56,7 @@ def test_long_expression_fits_registers(orc):
     (["z"], ["a"], {}),                        # unknown name
     (["a if a else a"], ["a"], {}),            # unsupported syntax
     (["sin(a)"], ["a"], {}),                   # unknown function
-    (["a"] * 5, list("abcde"), {}),            # m > 4
+    (["a"] * 17, [f"s{i}" for i in range(17)], {}),  # m > 16
     (["a", "b"], ["a"], {}),                   # count mismatch
     (["a"], ["a"], {"a": 1.0}),                # name clash
 ])

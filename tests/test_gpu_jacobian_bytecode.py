@@ -135,3 +135,47 @@ def test_bytecode_invalid_program_raises(rd):
         rd.reaction_step(u, 0.1, 1e-5, 1e-8, rd.BYTECODE, [1, 0, 9, 3, 0, 0])
     assert ei.value.code == -1
     assert torch.all(u == 1.0)
+
+
+@pytest.mark.parametrize("m", [8, 16])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_group_engine_bytecode(rd, orc, m, precision):
+    """The bytecode model with 8 and 16 species on the 16-lane-group kernels
+    (the register program of a sparse kinetics model, Jacobian by forward
+    differences), both schedules, against the oracle running the same
+    program."""
+    from tests.bytecode_models import kinetics_program, sparse_kinetics
+    K, G = sparse_kinetics(m, 200 + m)
+    prog = kinetics_program(K, G)
+    rng = np.random.default_rng(210 + m)
+    n = 3000
+    w = W.Workload(f"bc_kin{m}", 10.0 ** rng.uniform(-3, 0, (m, n)), W.KIND_BYTECODE, prog,
+                   0.05, 1e-6, 1e-10)
+    yo, sto, reto = run_oracle(orc, w)
+    for schedule in (0, 1):
+        say("group bytecode m", m, "precision", precision, "schedule", schedule)
+        y, st, ret = run_gpu(rd, w, schedule=schedule, precision=precision)
+        assert ret == reto == 0
+        check(compare(y, st, yo, sto, w.atol, label=f"bc kin{m} p{precision} s{schedule}"),
+              w.n, w.rtol)
+
+
+@pytest.mark.parametrize("m", [8, 16])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_group_engine_fd_jacobian(rd, orc, m, precision):
+    """The built-in kinetics model with the forward-difference Jacobian on the
+    16-lane-group kernels (8 and 16 species), against the oracle with the
+    same Jacobian; nfev carries m evaluations per Jacobian."""
+    w = W.kinetics16(n=2048, m=m, seed=300 + m)
+    yo, sto, reto = run_oracle(orc, w, jacobian=1)
+    for schedule in (0, 1):
+        say("group fd-jacobian m", m, "precision", precision, "schedule", schedule)
+        y, st, ret = run_gpu(rd, w, schedule=schedule, precision=precision, jacobian=1)
+        assert ret == reto == 0
+        rep = compare(y, st, yo, sto, w.atol, label=f"fd kin{m} p{precision} s{schedule}")
+        check(rep, w.n, w.rtol)
+        same = np.all(st[1:] == sto[1:], axis=0)
+        assert np.array_equal(st[4][same], sto[4][same])
+    ya, sa, _ = run_gpu(rd, w, precision=precision)
+    same = np.all(sa[[1, 2, 3, 5, 6, 8]] == st[[1, 2, 3, 5, 6, 8]], axis=0)
+    assert np.array_equal(st[4][same], sa[4][same] + m * sa[5][same])
