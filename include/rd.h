@@ -390,6 +390,13 @@ int32_t rd_variant_count(int32_t kind, int32_t m, int32_t precision,
 const char* rd_variant_name(int32_t kind, int32_t m, int32_t precision,
                             int32_t schedule, int32_t variant);
 
+/* Lanes of a wave that integrate one cell in variant v (1-based; 0 = the
+ * default): 1 for the one-lane kernels (64 cells per wave), 16 for the
+ * 16-lane-group kernels (4 cells per wave; also offered for the kinetics and
+ * linear models with m <= 4).  RD_EINVAL when there is no such variant. */
+int32_t rd_variant_lanes(int32_t kind, int32_t m, int32_t precision, int32_t schedule,
+                         int32_t variant);
+
 /* Make variant v (1-based) the default for (kind, m, precision, schedule):
  * the autotuner's result.  0 or RD_EINVAL. */
 int32_t rd_set_default_variant(int32_t kind, int32_t m, int32_t precision,

@@ -15,7 +15,8 @@ from ._lib import (BYTECODE, FP64, JAC_ANALYTIC, JAC_FD, KINETICS, LINEAR, MIXED
                    last_error)
 from .api import (RdError, Session, diffusion_step, last_kernel_ms, mra_adapt, mra_leaves,
                   mra_reconstruct, persistent_grid, reaction_step, request_bytes,
-                  set_default_variant, strang_step, variant_count, variant_name)
+                  set_default_variant, strang_step, variant_count, variant_lanes,
+                  variant_name)
 
 __all__ = ["FP64", "MIXED", "PERSISTENT", "ONE_LAUNCH", "OREGONATOR", "KINETICS",
            "NAGUMO", "LINEAR", "ROBERTSON", "BYTECODE", "JAC_ANALYTIC", "JAC_FD",
@@ -23,4 +24,4 @@ __all__ = ["FP64", "MIXED", "PERSISTENT", "ONE_LAUNCH", "OREGONATOR", "KINETICS"
            "last_error", "RdError", "Session", "reaction_step", "diffusion_step",
            "strang_step", "mra_leaves", "mra_reconstruct", "mra_adapt", "last_kernel_ms",
            "persistent_grid", "request_bytes", "variant_count", "variant_name",
-           "set_default_variant"]
+           "variant_lanes", "set_default_variant"]

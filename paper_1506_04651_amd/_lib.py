@@ -93,6 +93,7 @@ SIGNATURES = {
     "rd_variant_count": (ctypes.c_int32, [ctypes.c_int32] * 4),
     "rd_variant_name": (ctypes.c_char_p, [ctypes.c_int32] * 5),
     "rd_set_default_variant": (ctypes.c_int32, [ctypes.c_int32] * 5),
+    "rd_variant_lanes": (ctypes.c_int32, [ctypes.c_int32] * 5),
     "rd_persistent_grid": (ctypes.c_int32, [ctypes.c_int32] * 4 + [ctypes.c_int64]),
     "rd_last_kernel_ms": (ctypes.c_double, []),
     "rd_diffusion_step": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_int32,

@@ -245,6 +245,11 @@ def variant_name(kind, m, precision=FP64, schedule=PERSISTENT, variant=0) -> str
     return r.decode() if r else None
 
 
+def variant_lanes(kind, m, precision=FP64, schedule=PERSISTENT, variant=0) -> int:
+    """Lanes per cell of a kernel variant (1 or 16)."""
+    return _check(_lib.load().rd_variant_lanes(kind, m, precision, schedule, variant))
+
+
 def set_default_variant(kind, m, precision, schedule, variant) -> None:
     _check(_lib.load().rd_set_default_variant(kind, m, precision, schedule, variant))
 

@@ -4,9 +4,16 @@ The library compiles several variants of each kernel: work-group size, the
 waves-per-SIMD target the register allocator is held to (higher occupancy at
 the price of spills), how many lanes must wait before the step-end block runs
 (batching), whether the step parameters are staged in LDS or kept in scalar
-registers, the wave issue priorities of the persistent schedule and, for the
-16-lane kernels, fused or separate broadcasts.  Every variant computes the same
-per-cell arithmetic.  Which one is fastest depends on the model, m, the
+registers, the layout of the per-lane LDS slots (lane columns or lane rows),
+the wave issue priorities of the persistent schedule and, for the 16-lane
+kernels, fused or separate broadcasts and 8 or 16 matrix columns per lane;
+for the kinetics and linear models with m <= 4 also the number of lanes per
+cell (one lane, 64 cells per wave, or a 16-lane group, 4 cells per wave).
+Variants of one engine compute the same per-cell arithmetic and must give
+bitwise the same states; a variant with another number of lanes per cell
+runs other arithmetic (Gauss-Jordan inverses instead of LU) and is accepted
+when every cell has the same counters (the same control decisions) and its
+states agree to 1e-10 relative (floored at atol).  Which one is fastest depends on the model, m, the
 precision and on the distribution of per-cell cost in the batch, so the choice
 is measured: every
 variant is timed on the caller's own batch (HIP events on the launch stream),
@@ -65,21 +72,33 @@ def tune(states0, dt, rtol, atol, kind, params, precision=FP64, schedule=PERSIST
     differs bitwise from variant 1's are rejected (they must run the same
     per-cell arithmetic)."""
     import torch
-    m = int(states0.shape[0])
+    m, n = int(states0.shape[0]), int(states0.shape[1])
     nv = api.variant_count(kind, m, precision, schedule)
-    res = {"ms": {}, "names": {}, "rejected": []}
-    # correctness first: one launch of each variant, compared with variant 1
-    ref = None
+    res = {"ms": {}, "names": {}, "rejected": [], "lanes": {}}
+    # correctness first: one launch of each variant with counters, compared
+    # with variant 1
+    ref = ref_st = None
+    lanes1 = api.variant_lanes(kind, m, precision, schedule, 1)
     u = torch.empty_like(states0)
+    st = torch.zeros((9, n), dtype=torch.int32, device=states0.device)
     ok = []
     for v in range(1, nv + 1):
         name = api.variant_name(kind, m, precision, schedule, v)
         if name is None:
             continue
-        _launch_ms(u, states0, dt, rtol, atol, kind, params, precision, schedule, v)
+        u.copy_(states0)
+        api.reaction_step(u, dt, rtol, atol, kind, params, stats=st, precision=precision,
+                          schedule=schedule, variant=v)
+        lanes = api.variant_lanes(kind, m, precision, schedule, v)
         if ref is None:
-            ref = u.clone()
-        elif not torch.equal(u, ref):
+            ref, ref_st = u.clone(), st.clone()
+            same = True
+        elif lanes == lanes1:
+            same = torch.equal(u, ref) and torch.equal(st, ref_st)
+        else:
+            rel = (u - ref).abs() / torch.clamp(ref.abs(), min=max(atol, 1e-300))
+            same = torch.equal(st, ref_st) and float(rel.max()) <= 1e-10
+        if not same:
             res["rejected"].append(v)
             if verbose:
                 print(f"  variant {v} {name}: output differs from variant 1, rejected",
@@ -87,6 +106,7 @@ def tune(states0, dt, rtol, atol, kind, params, precision=FP64, schedule=PERSIST
             continue
         ok.append(v)
         res["names"][v] = name
+        res["lanes"][v] = lanes
     # then `reps` rounds over all variants, so that clock and cache drift
     # falls on every variant alike; the median per variant
     times = {v: [] for v in ok}

@@ -709,6 +709,14 @@ const char* rd_variant_name(int32_t kind, int32_t m, int32_t precision, int32_t 
     return e ? e->name : nullptr;
 }
 
+int32_t rd_variant_lanes(int32_t kind, int32_t m, int32_t precision, int32_t schedule,
+                         int32_t variant) {
+    const KernelEntry* e =
+        find_kernel(kind, m, precision, schedule, 0, variant <= 0 ? 0 : variant, -1);
+    if (!e) { set_error("no such variant"); return RD_EINVAL; }
+    return e->block / e->cells_per_block;
+}
+
 int32_t rd_set_default_variant(int32_t kind, int32_t m, int32_t precision, int32_t schedule,
                                int32_t variant) {
     if (variant < 1 || variant > rd_variant_count(kind, m, precision, schedule)) {

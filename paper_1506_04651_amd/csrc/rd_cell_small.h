@@ -238,11 +238,14 @@ __device__ __forceinline__ void lu_solve_cplx(const T (&ar)[M][M], const T (&ai)
     }
 }
 
-/* Per-lane LDS slots: a [ROWS][BLOCK] array, lane column `tid`. */
-template <int BLOCK, typename V = double>
+/* Per-lane LDS slots with row stride STRIDE: a [ROWS][BLOCK] array read by
+ * lane column (STRIDE = BLOCK, base &arr[0][tid]: consecutive lanes hit
+ * consecutive words), or a [BLOCK][ROWS'] array read by lane row (STRIDE = 1,
+ * base &arr[tid][0], ROWS' odd). */
+template <int STRIDE, typename V = double>
 struct LdsCol {
-    V* base; /* &arr[0][tid] */
-    __device__ __forceinline__ V& operator[](int row) const { return base[row * BLOCK]; }
+    V* base;
+    __device__ __forceinline__ V& operator[](int row) const { return base[row * STRIDE]; }
 };
 
 /* Rows of the per-lane LDS column: Jacobian (M*M), Z of the last accepted
@@ -259,9 +262,12 @@ struct SmallLds {
     static constexpr int ROWS = HPRE + 1;
     static constexpr int NSTEP = 0, NACCEPT = 1, NREJECT = 2, NJAC = 3, NDEC = 4;
     static constexpr int IROWS = 5;
+    /* odd row counts of the lane-row layout */
+    static constexpr int ROWS_AOS = ROWS | 1, IROWS_AOS = IROWS | 1;
 };
 
 /* ---------------- the per-cell engine ----------------------------------- */
+/* BLOCK: the row stride of the cell's LDS slots (LdsCol) */
 template <class Model, typename LT, int BLOCK>
 struct SmallCell {
     static constexpr int M = Model::M;

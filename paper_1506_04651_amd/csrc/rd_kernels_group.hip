@@ -9,7 +9,30 @@
 
 namespace rd {
 
+/* The 8-column kernels registered for 1 <= m <= 4 as well, as further
+ * variants beside the one-lane kernels (variant 1): the same models with
+ * sixteen lanes per cell instead of one, four cells per wave instead of 64.
+ * Their arithmetic differs from the one-lane engine's (Gauss-Jordan inverses,
+ * pivot choice R25), so they agree with it to rounding, not bitwise. */
+#define RD_G16_SMALL(KIND, MODEL, TAG, M)                                                          \
+    {KIND, 0, M, 0, 0, false, 2, 256, 256 / kGroup, TAG ".lanes16.g16c8.fp64.persistent.b256.w3.fs4", \
+     &launch_group_pers<MODEL, double, false, 256, 3, 4, true, 8>,                                 \
+     (const void*)&k_group_persistent<MODEL, double, false, 256, 3, 4, true, 8>},                  \
+    {KIND, 0, M, 1, 0, false, 2, 256, 256 / kGroup, TAG ".lanes16.g16c8.mixed.persistent.b256.w4.fs4", \
+     &launch_group_pers<MODEL, float, false, 256, 4, 4, true, 8>,                                  \
+     (const void*)&k_group_persistent<MODEL, float, false, 256, 4, 4, true, 8>},                   \
+    {KIND, 0, M, 0, 1, false, 2, 256, 256 / kGroup, TAG ".lanes16.g16c8.fp64.onelaunch.b256",       \
+     &launch_group_one<MODEL, double, false, 256, 1, 1, true, 8>,                                  \
+     (const void*)&k_group_onelaunch<MODEL, double, false, 256, 1, 1, true, 8>},                   \
+    {KIND, 0, M, 1, 1, false, 2, 256, 256 / kGroup, TAG ".lanes16.g16c8.mixed.onelaunch.b256",      \
+     &launch_group_one<MODEL, float, false, 256, 1, 1, true, 8>,                                   \
+     (const void*)&k_group_onelaunch<MODEL, float, false, 256, 1, 1, true, 8>}
+
 static const KernelEntry g_group_table[] = {
+    RD_G16_SMALL(2, GroupKinetics, "kinetics", 1), RD_G16_SMALL(2, GroupKinetics, "kinetics", 2),
+    RD_G16_SMALL(2, GroupKinetics, "kinetics", 3), RD_G16_SMALL(2, GroupKinetics, "kinetics", 4),
+    RD_G16_SMALL(4, GroupLinear, "linear", 1), RD_G16_SMALL(4, GroupLinear, "linear", 2),
+    RD_G16_SMALL(4, GroupLinear, "linear", 3), RD_G16_SMALL(4, GroupLinear, "linear", 4),
     RD_GONE(2, GroupKinetics, 0, double, false, 1, 256, 1, 1, "kinetics.g16.fp64.onelaunch.b256"),
     RD_GONE(2, GroupKinetics, 1, float, false, 1, 256, 1, 1, "kinetics.g16.mixed.onelaunch.b256"),
     RD_GPERS(2, GroupKinetics, 0, double, false, 1, 256, 2, 4, "kinetics.g16.fp64.persistent.b256.w2.fs4"),

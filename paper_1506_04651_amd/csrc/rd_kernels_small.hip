@@ -66,6 +66,7 @@ hipError_t launch_reset(unsigned long long* p, int n, hipStream_t s) {
     RD_PERS_U(KIND, MODEL, M, PREC, LT, 30, 128, 3, 40, 2, 64, 40, TAG ".persistent.b128.w3.fs40.p2.u64"), \
     RD_PERS_U(KIND, MODEL, M, PREC, LT, 31, 128, 3, 40, 2, 40, 64, TAG ".persistent.b128.w3.fs40.p2.l64"), \
     RD_PERS_U(KIND, MODEL, M, PREC, LT, 32, 128, 3, 40, 2, 64, 64, TAG ".persistent.b128.w3.fs40.p2.u64.l64"), \
+    RD_PERS_A(KIND, MODEL, M, PREC, LT, 33, 128, 3, 48, 2, 64, 64, TAG ".persistent.b128.w3.fs48.p2.u64.l64.aos"), \
     RD_ONE(KIND, MODEL, M, PREC, LT, false, 2, 256, 1, 16, TAG ".onelaunch.b256.fs16"),       \
     RD_ONE(KIND, MODEL, M, PREC, LT, false, 3, 256, 1, 1, TAG ".onelaunch.b256.fs1")
 

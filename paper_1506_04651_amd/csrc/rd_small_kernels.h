@@ -98,19 +98,22 @@ __device__ __forceinline__ int claim_priority(unsigned long long held, unsigned 
  * for all of them costs little), then FSU while the wave holds cells at the
  * top priority, else FSMIN. */
 template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool PLDS = true,
-          int PDIV = 0, int FSU = FSMIN, int FSL = FSMIN>
+          int PDIV = 0, int FSU = FSMIN, int FSL = FSMIN, bool AOS = false>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_persistent(LaunchArgs a) {
     using L = SmallLds<Model::M>;
-    __shared__ double sh[L::ROWS * BLOCK];
-    __shared__ int shi[L::IROWS * BLOCK];
+    /* LDS layout of the per-lane slots: [rows][lanes] (lane columns), or
+     * with AOS [lanes][rows] (lane rows, odd row count) */
+    constexpr int RS = AOS ? 1 : BLOCK;
+    __shared__ double sh[(AOS ? L::ROWS_AOS : L::ROWS) * BLOCK];
+    __shared__ int shi[(AOS ? L::IROWS_AOS : L::IROWS) * BLOCK];
     __shared__ StepParams sPl;
     if (PLDS) stage_params(sPl, a.P);
     const StepParams& sP = PLDS ? sPl : a.P;
     const Model md(a.params);
-    SmallCell<Model, LT, BLOCK> cell;
-    cell.lds.base = sh + threadIdx.x;
-    cell.ilds.base = shi + threadIdx.x;
+    SmallCell<Model, LT, RS> cell;
+    cell.lds.base = sh + (AOS ? threadIdx.x * L::ROWS_AOS : threadIdx.x);
+    cell.ilds.base = shi + (AOS ? threadIdx.x * L::IROWS_AOS : threadIdx.x);
     cell.phase = PH_IDLE;
     cell.status = ST_OK;
     int64_t c = -1;
@@ -167,7 +170,7 @@ k_persistent(LaunchArgs a) {
         }
         if (__ballot(alive) == 0ull) break;
         if (PLDS) __asm__ volatile("" ::: "memory"); /* re-read sP from LDS each pass */
-        advance<Model, LT, FIXED, BLOCK, FSMIN>(cell, md, sP, fs);
+        advance<Model, LT, FIXED, RS, FSMIN>(cell, md, sP, fs);
     }
 }
 
@@ -180,9 +183,9 @@ hipError_t launch_one(const LaunchArgs& a, int grid, hipStream_t s) {
 }
 
 template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool PLDS = true,
-          int PDIV = 0, int FSU = FSMIN, int FSL = FSMIN>
+          int PDIV = 0, int FSU = FSMIN, int FSL = FSMIN, bool AOS = false>
 hipError_t launch_pers(const LaunchArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_persistent<Model, LT, FIXED, BLOCK, WPE, FSMIN, PLDS, PDIV, FSU, FSL>),
+    hipLaunchKernelGGL((k_persistent<Model, LT, FIXED, BLOCK, WPE, FSMIN, PLDS, PDIV, FSU, FSL, AOS>),
                        dim3(grid), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
@@ -203,6 +206,10 @@ hipError_t launch_pers(const LaunchArgs& a, int grid, hipStream_t s) {
     {KIND, fd_jac_of<MODEL>::value ? 1 : 0, M, PREC, 0, false, VAR, BLOCK, BLOCK, NAME,           \
      &launch_pers<MODEL, LT, false, BLOCK, WPE, FS, true, PDIV, FSU, FSL>,                      \
      (const void*)&k_persistent<MODEL, LT, false, BLOCK, WPE, FS, true, PDIV, FSU, FSL>}
+#define RD_PERS_A(KIND, MODEL, M, PREC, LT, VAR, BLOCK, WPE, FS, PDIV, FSU, FSL, NAME)          \
+    {KIND, fd_jac_of<MODEL>::value ? 1 : 0, M, PREC, 0, false, VAR, BLOCK, BLOCK, NAME,           \
+     &launch_pers<MODEL, LT, false, BLOCK, WPE, FS, true, PDIV, FSU, FSL, true>,                \
+     (const void*)&k_persistent<MODEL, LT, false, BLOCK, WPE, FS, true, PDIV, FSU, FSL, true>}
 #define RD_PERS(KIND, MODEL, M, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, NAME)                      \
     {KIND, fd_jac_of<MODEL>::value ? 1 : 0, M, PREC, 0, FIXED, VAR, BLOCK, BLOCK, NAME,                                          \
      &launch_pers<MODEL, LT, FIXED, BLOCK, WPE, FS>,                                            \
