@@ -54,6 +54,10 @@ static const KernelEntry g_group_table[] = {
     RD_GPERS(2, GroupKinetics, 1, float, false, 8, 128, 3, 4, "kinetics.g16.mixed.persistent.b128.w3.fs4"),
     RD_GPERS_X(2, GroupKinetics, 1, float, false, 9, 256, 3, 4, false, 16,
                "kinetics.g16.mixed.persistent.b256.w3.fs4.unfused"),
+    RD_GPERS(2, GroupKinetics, 1, float, false, 10, 256, 4, 4, "kinetics.g16.mixed.persistent.b256.w4.fs4"),
+    RD_GPERS(2, GroupKinetics, 1, float, false, 11, 256, 4, 3, "kinetics.g16.mixed.persistent.b256.w4.fs3"),
+    RD_GPERS(2, GroupKinetics, 0, double, false, 8, 256, 3, 4, "kinetics.g16.fp64.persistent.b256.w3.fs4"),
+    RD_GPERS(2, GroupKinetics, 0, double, false, 9, 128, 2, 4, "kinetics.g16.fp64.persistent.b128.w2.fs4"),
     RD_GONE(2, GroupKinetics, 0, double, true, 1, 256, 1, 1, "kinetics.g16.fp64.onelaunch.fixed"),
     RD_GPERS(2, GroupKinetics, 0, double, true, 1, 256, 1, 1, "kinetics.g16.fp64.persistent.fixed"),
     /* 8 columns (m = 5..8) */
