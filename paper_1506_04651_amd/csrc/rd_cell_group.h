@@ -86,7 +86,10 @@ struct bytecode_of<Model, decltype((void)Model::BYTECODE)> { static constexpr bo
  * per lane, 16, or 8 for m <= 8 (lanes 8..15 of the group then hold zero
  * rows, as lanes m..15 do in either form; halving the columns halves the
  * matrices' registers and the elimination work). */
-template <class Model, typename LT, bool FUSE = false, int NC = kGroup>
+/* COLD: the per-cell values touched once per step or less (Z of the last
+ * accepted step, the step-control scalars, the Jacobian point) live in LDS
+ * slots instead of registers, which leaves more registers to the hot loop */
+template <class Model, typename LT, bool FUSE = false, int NC = kGroup, bool COLD = false>
 struct GroupCell {
     static_assert(NC == 8 || NC == kGroup, "8 or 16 columns");
     static constexpr int M = NC; /* loops run over NC columns; rows and columns >= m are zero */
@@ -102,7 +105,20 @@ struct GroupCell {
     double inv3m, invm;
 
     /* lane-q components */
-    double y, f0, isc, w1, w2, w3, z1o, z2o, z3o, uJ, gJ;
+    double y, f0, isc, w1, w2, w3;
+    /* cold values: Z of the last accepted step, lane q's component of the
+     * Jacobian point and (G u)_q there, the step-control scalars */
+    enum : int { C_Z1 = 0, C_Z2, C_Z3, C_UJ, C_GJ, C_HOLD, C_IHACC, C_QACC, C_HPRE, C_N };
+    double creg[C_N];
+    double* cl; /* COLD: slot i at cl[i * jstride] (LDS) */
+    __device__ __forceinline__ double& cv(int i) {
+        if constexpr (COLD) return cl[i * jstride];
+        else return creg[i];
+    }
+    __device__ __forceinline__ double cv(int i) const {
+        if constexpr (COLD) return cl[i * jstride];
+        else return creg[i];
+    }
     LT e1[M], e2r[M], e2i[M]; /* rows of the Gauss-Jordan inverses (see gj_real) */
     LT d1, d2r, d2i;          /* reciprocal pivots */
     int org1, org2;
@@ -112,9 +128,9 @@ struct GroupCell {
     const double* prog; /* BC: the register program (device) */
     int q;
     bool act;         /* q < m */
-    /* per-cell scalars, replicated across the group */
-    double t, h, ih, h_old, ih_acc, qerr_acc, eta, inprev;
-    double h_pre; /* step size before the last-step shortening (warm start out) */
+    /* per-cell scalars, replicated across the group (the step-control ones
+     * that change once per step are cold values, cv) */
+    double t, h, ih, eta, inprev;
     unsigned flags;
     int phase, status, k, nsing, outcome;
     int nstep, naccept, nreject, nfev, njac, ndec, nsol, nnewt;
@@ -244,7 +260,7 @@ struct GroupCell {
         } else {
             double lin, loss;
             rows(x, lin, loss);
-            return HAS_G ? lin - uJ * loss - gJ * x : lin;
+            return HAS_G ? lin - cv(C_UJ) * loss - cv(C_GJ) * x : lin;
         }
     }
 
@@ -278,8 +294,8 @@ struct GroupCell {
         const double hw = hcell ? hcell[c] : 0.0;
         h = P.fixed_steps > 0 ? P.dt / P.fixed_steps
                               : fmin(hw > 0.0 ? hw : (P.h0 > 0.0 ? P.h0 : P.dt), P.dt);
-        h_pre = fin ? h : 0.0;
-        h_old = ih_acc = qerr_acc = inprev = 0.0;
+        cv(C_HPRE) = fin ? h : 0.0;
+        cv(C_HOLD) = cv(C_IHACC) = cv(C_QACC) = inprev = 0.0;
         eta = 1.0;
         k = 0;
         nsing = 0;
@@ -287,9 +303,9 @@ struct GroupCell {
         w1 = 0.0;
         w2 = 0.0;
         w3 = 0.0;
-        z1o = 0.0;
-        z2o = 0.0;
-        z3o = 0.0;
+        cv(C_Z1) = 0.0;
+        cv(C_Z2) = 0.0;
+        cv(C_Z3) = 0.0;
         phase = fin ? PH_START : PH_IDLE;
         if (!fin) status = ST_NONFINITE;
     }
@@ -297,7 +313,7 @@ struct GroupCell {
     __device__ __forceinline__ void store(double* __restrict__ states, int32_t* __restrict__ stats,
                                           int64_t n, int64_t c, double* __restrict__ hcell) const {
         if (act) states[(int64_t)q * n + c] = y;
-        if (hcell && q == 0) hcell[c] = h_pre;
+        if (hcell && q == 0) hcell[c] = cv(C_HPRE);
         if (stats && q == 0) {
             stats[0 * n + c] = status;
             stats[1 * n + c] = nstep;
@@ -317,8 +333,8 @@ struct GroupCell {
         if constexpr (FDJ) return (act && j < m) ? jl[j * jstride] : 0.0;
         double v = kg[j];
         if (HAS_G) {
-            v -= uJ * kg[kGroup + j];
-            if (j == q) v -= gJ;
+            v -= cv(C_UJ) * kg[kGroup + j];
+            if (j == q) v -= cv(C_GJ);
         }
         return act ? v : 0.0;
     }
@@ -487,7 +503,7 @@ struct GroupCell {
     template <bool FIXED>
     __device__ __forceinline__ void start(const StepParams& P) {
         if (!FIXED) {
-            h_pre = h;
+            cv(C_HPRE) = h;
             if (nstep >= P.max_steps) { status = ST_MAXSTEPS; phase = PH_IDLE; return; }
             if (h < P.h_min) { status = ST_HSMALL; phase = PH_IDLE; return; }
             const bool last = t + 1.0001 * h >= P.dt;
@@ -506,8 +522,8 @@ struct GroupCell {
             } else {
                 double gu;
                 (void)rhs(y, gu);
-                uJ = y;
-                gJ = gu;
+                cv(C_UJ) = y;
+                cv(C_GJ) = gu;
             }
             ++njac;
             flags = (flags & ~(F_JSTALE | F_LUOK)) | F_JATY0;
@@ -527,7 +543,7 @@ struct GroupCell {
          * the same single assignment of w1, w2, w3 */
         double za = 0.0, zb = 0.0, zc = 0.0;
         if (has(F_OLD)) {
-            const double r = h * rcp(h_old);
+            const double r = h * rcp(cv(C_HOLD));
             const double s1 = -1.0, s2 = radau::C1 - 1.0, s3 = radau::C2 - 1.0;
             const double cs[3] = {radau::C1 * r, radau::C2 * r, r};
             double Lw[3][3];
@@ -539,7 +555,7 @@ struct GroupCell {
                 Lw[i][1] = d1 * d3 * d4 * radau::LAG_INV1;
                 Lw[i][2] = d1 * d2 * d4 * radau::LAG_INV2;
             }
-            const double v0 = -z3o, v1 = z1o - z3o, v2 = z2o - z3o;
+            const double v0 = -cv(C_Z3), v1 = cv(C_Z1) - cv(C_Z3), v2 = cv(C_Z2) - cv(C_Z3);
             za = Lw[0][0] * v0 + Lw[0][1] * v1 + Lw[0][2] * v2;
             zb = Lw[1][0] * v0 + Lw[1][1] * v1 + Lw[1][2] * v2;
             zc = Lw[2][0] * v0 + Lw[2][1] * v1 + Lw[2][2] * v2;
@@ -646,16 +662,16 @@ struct GroupCell {
             if (oc == NW_FAILED) { status = ST_NEWTON; phase = PH_IDLE; return; }
             ++nstep;
             ++naccept;
-            z1o = radau::T11 * w1 + radau::T12 * w2 + radau::T13 * w3;
-            z2o = radau::T21 * w1 + radau::T22 * w2 + radau::T23 * w3;
-            z3o = w1 + w2;
-            y += z3o;
+            cv(C_Z1) = radau::T11 * w1 + radau::T12 * w2 + radau::T13 * w3;
+            cv(C_Z2) = radau::T21 * w1 + radau::T22 * w2 + radau::T23 * w3;
+            cv(C_Z3) = w1 + w2;
+            y += cv(C_Z3);
             double gu;
             f0 = rhs(y, gu);
             ++nfev;
             flags |= F_OLD;
             if (grp_bits(finite_d(y)) != 0xFFFFu) { status = ST_NONFINITE; phase = PH_IDLE; return; }
-            h_old = h;
+            cv(C_HOLD) = h;
             eta = pow08(fmax(eta, UROUND));
             phase = (naccept >= P.fixed_steps) ? PH_IDLE : PH_START;
             return;
@@ -691,7 +707,7 @@ struct GroupCell {
                 /* predictive: fac (h / h_acc) err_acc^(1/4) / err^(1/2) */
                 const double r2 = (err == 0.0)
                     ? 8.0
-                    : fmin(8.0, fmax(0.2, fac * (h * ih_acc) * qerr_acc * (s * s)));
+                    : fmin(8.0, fmax(0.2, fac * (h * cv(C_IHACC)) * cv(C_QACC) * (s * s)));
                 h_new = fmin(h_new, h * r2);
             }
             const double zz1 = radau::T11 * w1 + radau::T12 * w2 + radau::T13 * w3;
@@ -706,16 +722,16 @@ struct GroupCell {
                 phase = PH_IDLE;
                 return;
             }
-            ih_acc = ih;
+            cv(C_IHACC) = ih;
             /* max(err, 1e-2)^(1/4); (1e-2)^(1/4) = sqrt(0.1) */
-            qerr_acc = err >= 1e-2 ? rcp_nr(s) : 0.31622776601683794;
+            cv(C_QACC) = err >= 1e-2 ? rcp_nr(s) : 0.31622776601683794;
             y = y1;
             f0 = f1;
-            z1o = zz1;
-            z2o = zz2;
-            z3o = zz3;
+            cv(C_Z1) = zz1;
+            cv(C_Z2) = zz2;
+            cv(C_Z3) = zz3;
             t = has(F_LAST) ? P.dt : t + h;
-            h_old = h;
+            cv(C_HOLD) = h;
             eta = pow08(fmax(eta, UROUND));
             ++naccept;
             if (has(F_REJECT)) h_new = fmin(h_new, h);

@@ -42,10 +42,11 @@ __device__ __forceinline__ void load_table(double* tab, const double* __restrict
 /* jfd: the block's LDS for forward-difference Jacobian rows, [16][BLOCK]
  * (lane t's row at column j is jfd[j * BLOCK + t]); unused otherwise. */
 template <int BLOCK, class Cell>
-__device__ __forceinline__ void init_cell(Cell& cell, const double* tab, double* jfd,
+__device__ __forceinline__ void init_cell(Cell& cell, const double* tab, double* jfd, double* cold,
                                           const double* params, int m) {
     cell.q = (int)grp_lane();
     cell.jl = jfd + threadIdx.x;
+    cell.cl = cold + threadIdx.x;
     cell.jstride = BLOCK;
     cell.prog = params;
     cell.m = m;
@@ -55,7 +56,7 @@ __device__ __forceinline__ void init_cell(Cell& cell, const double* tab, double*
     cell.kg = tab + cell.q * GroupTable::STRIDE;
     cell.phase = PH_IDLE;
     cell.status = ST_OK;
-    cell.uJ = cell.gJ = 0.0;
+    cell.cv(Cell::C_UJ) = cell.cv(Cell::C_GJ) = 0.0;
 }
 
 template <bool FIXED, int FSMIN, class Cell>
@@ -82,34 +83,38 @@ __device__ __forceinline__ void advance_group(Cell& cell, const StepParams& P) {
     if (cell.phase == PH_START) cell.template start<FIXED>(P);
 }
 
-template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool FUSE, int NC>
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool FUSE, int NC,
+          bool COLD = false>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_group_onelaunch(LaunchArgs a, int m) {
     __shared__ double tab[GroupTable::DOUBLES];
     __shared__ double jfd[fd_jac_of<Model>::value ? NC * BLOCK : 1];
+    __shared__ double gcold[COLD ? GroupCell<Model, LT, FUSE, NC, COLD>::C_N * BLOCK : 1];
     __shared__ StepParams sP;
     stage_params(sP, a.P);
     load_table<Model>(tab, a.params, m, BLOCK);
     const int64_t c = (int64_t)blockIdx.x * (BLOCK / kGroup) + threadIdx.x / kGroup;
     if (c >= a.n) return;
-    GroupCell<Model, LT, FUSE, NC> cell;
-    init_cell<BLOCK>(cell, tab, jfd, a.params, m);
+    GroupCell<Model, LT, FUSE, NC, COLD> cell;
+    init_cell<BLOCK>(cell, tab, jfd, gcold, a.params, m);
     cell.load(sP, a.states, a.n, c, a.hcell);
     while (cell.phase != PH_IDLE) advance_group<FIXED, FSMIN>(cell, sP);
     cell.store(a.states, a.stats, a.n, c, a.hcell);
     if (cell.status != ST_OK && cell.q == 0) atomicAdd(a.nfail, 1ull);
 }
 
-template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool FUSE, int NC>
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool FUSE, int NC,
+          bool COLD = false>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_group_persistent(LaunchArgs a, int m) {
     __shared__ double tab[GroupTable::DOUBLES];
     __shared__ double jfd[fd_jac_of<Model>::value ? NC * BLOCK : 1];
+    __shared__ double gcold[COLD ? GroupCell<Model, LT, FUSE, NC, COLD>::C_N * BLOCK : 1];
     __shared__ StepParams sP;
     stage_params(sP, a.P);
     load_table<Model>(tab, a.params, m, BLOCK);
-    GroupCell<Model, LT, FUSE, NC> cell;
-    init_cell<BLOCK>(cell, tab, jfd, a.params, m);
+    GroupCell<Model, LT, FUSE, NC, COLD> cell;
+    init_cell<BLOCK>(cell, tab, jfd, gcold, a.params, m);
     int64_t c = -1;
     bool alive = true;
     const unsigned lane = __lane_id();
@@ -166,10 +171,11 @@ hipError_t launch_group_one(const LaunchArgs& a, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool FUSE, int NC>
+template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool FUSE, int NC,
+          bool COLD = false>
 hipError_t launch_group_pers(const LaunchArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_group_persistent<Model, LT, FIXED, BLOCK, WPE, FSMIN, FUSE, NC>), dim3(grid),
-                       dim3(BLOCK), 0, s, a, (int)a.P.m);
+    hipLaunchKernelGGL((k_group_persistent<Model, LT, FIXED, BLOCK, WPE, FSMIN, FUSE, NC, COLD>),
+                       dim3(grid), dim3(BLOCK), 0, s, a, (int)a.P.m);
     return hipGetLastError();
 }
 
@@ -185,6 +191,10 @@ hipError_t launch_group_pers(const LaunchArgs& a, int grid, hipStream_t s) {
     {KIND, fd_jac_of<MODEL>::value ? 1 : 0, NC, PREC, 0, FIXED, VAR, BLOCK, BLOCK / kGroup, NAME,                                 \
      &launch_group_pers<MODEL, LT, FIXED, BLOCK, WPE, FS, FUSE, NC>,                             \
      (const void*)&k_group_persistent<MODEL, LT, FIXED, BLOCK, WPE, FS, FUSE, NC>}
+#define RD_GPERS_C(KIND, MODEL, PREC, LT, VAR, BLOCK, WPE, FS, NC, NAME)                          \
+    {KIND, fd_jac_of<MODEL>::value ? 1 : 0, NC, PREC, 0, false, VAR, BLOCK, BLOCK / kGroup, NAME,     \
+     &launch_group_pers<MODEL, LT, false, BLOCK, WPE, FS, true, NC, true>,                          \
+     (const void*)&k_group_persistent<MODEL, LT, false, BLOCK, WPE, FS, true, NC, true>}
 #define RD_GONE(KIND, MODEL, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, NAME)                          \
     RD_GONE_X(KIND, MODEL, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, 16, NAME)
 #define RD_GPERS(KIND, MODEL, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, NAME)                         \

@@ -35,7 +35,7 @@ static const KernelEntry g_group_table[] = {
     RD_G16_SMALL(4, GroupLinear, "linear", 3), RD_G16_SMALL(4, GroupLinear, "linear", 4),
     RD_GONE(2, GroupKinetics, 0, double, false, 1, 256, 1, 1, "kinetics.g16.fp64.onelaunch.b256"),
     RD_GONE(2, GroupKinetics, 1, float, false, 1, 256, 1, 1, "kinetics.g16.mixed.onelaunch.b256"),
-    RD_GPERS(2, GroupKinetics, 0, double, false, 1, 256, 2, 4, "kinetics.g16.fp64.persistent.b256.w2.fs4"),
+    RD_GPERS_C(2, GroupKinetics, 0, double, 1, 256, 3, 4, 16, "kinetics.g16.fp64.persistent.b256.w3.fs4.cold"),
     RD_GPERS(2, GroupKinetics, 1, float, false, 1, 256, 3, 4, "kinetics.g16.mixed.persistent.b256.w3.fs4"),
     RD_GPERS(2, GroupKinetics, 0, double, false, 2, 256, 1, 2, "kinetics.g16.fp64.persistent.b256.fs2"),
     RD_GPERS(2, GroupKinetics, 1, float, false, 2, 256, 1, 2, "kinetics.g16.mixed.persistent.b256.fs2"),
@@ -58,6 +58,11 @@ static const KernelEntry g_group_table[] = {
     RD_GPERS(2, GroupKinetics, 1, float, false, 11, 256, 4, 3, "kinetics.g16.mixed.persistent.b256.w4.fs3"),
     RD_GPERS(2, GroupKinetics, 0, double, false, 8, 256, 3, 4, "kinetics.g16.fp64.persistent.b256.w3.fs4"),
     RD_GPERS(2, GroupKinetics, 0, double, false, 9, 128, 2, 4, "kinetics.g16.fp64.persistent.b128.w2.fs4"),
+    /* cold per-cell values in LDS */
+    RD_GPERS_C(2, GroupKinetics, 1, float, 12, 256, 3, 4, 16, "kinetics.g16.mixed.persistent.b256.w3.fs4.cold"),
+    RD_GPERS_C(2, GroupKinetics, 1, float, 13, 256, 3, 3, 16, "kinetics.g16.mixed.persistent.b256.w3.fs3.cold"),
+    RD_GPERS(2, GroupKinetics, 0, double, false, 10, 256, 2, 4, "kinetics.g16.fp64.persistent.b256.w2.fs4"),
+    RD_GPERS_C(2, GroupKinetics, 0, double, 11, 256, 2, 4, 16, "kinetics.g16.fp64.persistent.b256.w2.fs4.cold"),
     RD_GONE(2, GroupKinetics, 0, double, true, 1, 256, 1, 1, "kinetics.g16.fp64.onelaunch.fixed"),
     RD_GPERS(2, GroupKinetics, 0, double, true, 1, 256, 1, 1, "kinetics.g16.fp64.persistent.fixed"),
     /* 8 columns (m = 5..8) */
@@ -69,6 +74,9 @@ static const KernelEntry g_group_table[] = {
     RD_GPERS8(2, GroupKinetics, 1, float, 2, 3, 4, "kinetics.g16c8.mixed.persistent.b256.w3.fs4"),
     RD_GPERS8(2, GroupKinetics, 0, double, 3, 4, 4, "kinetics.g16c8.fp64.persistent.b256.w4.fs4"),
     RD_GPERS8(2, GroupKinetics, 1, float, 3, 3, 2, "kinetics.g16c8.mixed.persistent.b256.w3.fs2"),
+    RD_GPERS_C(2, GroupKinetics, 0, double, 6, 256, 3, 4, 8, "kinetics.g16c8.fp64.persistent.b256.w3.fs4.cold"),
+    RD_GPERS_C(2, GroupKinetics, 0, double, 7, 256, 4, 4, 8, "kinetics.g16c8.fp64.persistent.b256.w4.fs4.cold"),
+    RD_GPERS_C(2, GroupKinetics, 1, float, 5, 256, 4, 4, 8, "kinetics.g16c8.mixed.persistent.b256.w4.fs4.cold"),
     RD_GPERS8(2, GroupKinetics, 0, double, 4, 3, 2, "kinetics.g16c8.fp64.persistent.b256.w3.fs2"),
     RD_GPERS_X(2, GroupKinetics, 0, double, false, 5, 256, 3, 4, false, 8,
                "kinetics.g16c8.fp64.persistent.b256.w3.fs4.unfused"),
