@@ -17,6 +17,14 @@
 namespace rd {
 
 constexpr double kFastLo = 1e-280, kFastHi = 1e280; /* refined forms valid inside */
+
+/* The library operations of the out-of-range branches, kept out of line: they
+ * run almost never, and inlined (pow especially) their constants would be
+ * hoisted into registers of the kernels' main loops and spilled. */
+__device__ __noinline__ double slow_rcp(double a) { return 1.0 / a; }
+__device__ __noinline__ double slow_sqrt(double x) { return __builtin_sqrt(x); }
+__device__ __noinline__ double slow_rroot4(double x) { return 1.0 / __builtin_sqrt(__builtin_sqrt(x)); }
+__device__ __noinline__ double slow_pow08(double x) { return pow(x, 0.8); }
 constexpr float kSeedLo = 1e-30f, kSeedHi = 1e30f;  /* FP32 seeds valid inside */
 
 /* 1/a for |a| in [kFastLo, kFastHi]: v_rcp_f64 and two Newton steps
@@ -32,7 +40,7 @@ __device__ __forceinline__ double rcp(double a) {
     double r = rcp_nr(a);
     const double aa = __builtin_fabs(a);
     const bool ok = aa >= kFastLo && aa <= kFastHi;
-    if (__ballot(!ok) != 0ull) r = ok ? r : 1.0 / a;
+    if (__ballot(!ok) != 0ull) r = ok ? r : slow_rcp(a);
     return r;
 }
 /* FP32: v_rcp_f32 and one Newton step, IEEE division outside [1e-36, 1e36]. */
@@ -59,7 +67,7 @@ __device__ __forceinline__ double sqrt_nr(double x) {
 __device__ __forceinline__ double sqrt_f(double x) {
     double s = sqrt_nr(x);
     const bool ok = x >= kFastLo && x <= kFastHi;
-    if (__ballot(!ok) != 0ull) s = ok ? s : __builtin_sqrt(x);
+    if (__ballot(!ok) != 0ull) s = ok ? s : slow_sqrt(x);
     return s;
 }
 
@@ -75,7 +83,7 @@ __device__ __forceinline__ double rroot4(double x) {
         y = __builtin_fma(0.25 * y, e, y);
     }
     const bool ok = x >= (double)kSeedLo && x <= (double)kSeedHi;
-    if (__ballot(!ok) != 0ull) y = ok ? y : 1.0 / __builtin_sqrt(__builtin_sqrt(x));
+    if (__ballot(!ok) != 0ull) y = ok ? y : slow_rroot4(x);
     return y;
 }
 
@@ -94,7 +102,7 @@ __device__ __forceinline__ double pow08(double x) {
     }
     y = __builtin_fma(y, kDeltaLn2 * (double)lg, y);
     const bool ok = x >= (double)kSeedLo && x <= (double)kSeedHi;
-    if (__ballot(!ok) != 0ull) y = ok ? y : pow(x, 0.8);
+    if (__ballot(!ok) != 0ull) y = ok ? y : slow_pow08(x);
     return y;
 }
 
