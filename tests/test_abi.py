@@ -217,3 +217,18 @@ def test_product_path_does_not_reference_the_oracle():
                 txt = open(os.path.join(dp, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "rdo_" not in txt and "liboracle" not in txt, f
+
+
+def test_variant_lanes_per_cell(lib):
+    """The variant table's lanes per cell: one lane for the one-lane kernels,
+    16 for the 16-lane-group kernels, both offered for kinetics with m <= 4."""
+    import paper_1506_04651_amd as rd
+    assert rd.variant_lanes(rd.OREGONATOR, 3, rd.FP64, rd.PERSISTENT, 1) == 1
+    assert rd.variant_lanes(rd.KINETICS, 16, rd.FP64, rd.PERSISTENT, 1) == 16
+    for m in (1, 2, 3, 4):
+        for prec in (rd.FP64, rd.MIXED):
+            n = rd.variant_count(rd.KINETICS, m, prec, rd.PERSISTENT)
+            lanes = {rd.variant_lanes(rd.KINETICS, m, prec, rd.PERSISTENT, v) for v in range(1, n + 1)}
+            assert lanes == {1, 16}, (m, prec, lanes)
+    with pytest.raises(rd.RdError):
+        rd.variant_lanes(rd.OREGONATOR, 3, rd.FP64, rd.PERSISTENT, 999)
