@@ -46,6 +46,19 @@ namespace rd {
 __device__ __forceinline__ float absv(float x) { return __builtin_fabsf(x); }
 __device__ __forceinline__ double absv(double x) { return __builtin_fabs(x); }
 __device__ __forceinline__ float fmaf_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+/* v, opaque to the optimizer at this point: comparisons derived from it are
+ * formed where they are used instead of being hoisted out of the kernel's
+ * loop as lane masks (which would be kept in, and spilled from, scalar
+ * registers) */
+__device__ __forceinline__ int opaque_int(int v) {
+    __asm__ volatile("" : "+v"(v));
+    return v;
+}
+/* the same for a wave-uniform value (kept in a scalar register) */
+__device__ __forceinline__ int opaque_uniform(int v) {
+    __asm__ volatile("" : "+s"(v));
+    return v;
+}
 __device__ __forceinline__ double fmaf_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 /* LDS table of the model, zero padded to 16 x 16: row q holds K[q][0..16)
@@ -329,15 +342,16 @@ struct GroupCell {
 
     /* J_qj at the stored Jacobian point (uJ, gJ = (G u)_q at that point), or
      * from the LDS row of the forward-difference Jacobian */
-    __device__ __forceinline__ double jac(int j) const {
-        if constexpr (FDJ) return (act && j < m) ? jl[j * jstride] : 0.0;
+    __device__ __forceinline__ double jac(int j, int qv, bool av) const {
+        if constexpr (FDJ) return (av && j < m) ? jl[j * jstride] : 0.0;
         double v = kg[j];
         if (HAS_G) {
             v -= cv(C_UJ) * kg[kGroup + j];
-            if (j == q) v -= cv(C_GJ);
+            if (j == qv) v -= cv(C_GJ);
         }
-        return act ? v : 0.0;
+        return av ? v : 0.0;
     }
+    __device__ __forceinline__ double jac(int j) const { return jac(j, q, act); }
 
     /* ---- inverse of E1 (real) by Gauss-Jordan with partial pivoting ----
      * Step kk: the pivot row (after the exchange, lane kk) is left unscaled;
@@ -347,9 +361,18 @@ struct GroupCell {
      * keeps d = 1 / p_kk.  At the end lane q holds row q of R with
      * (P E)^{-1} = diag(d) R, P the row exchanges (org: source row of lane q).
      * The pivots, and so the singularity test, are those of the LU
-     * factorization with the same pivoting. */
+     * factorization with the same pivoting.
+     * SAFE: reciprocal pivots by rcp (library division outside its fast
+     * range); returns false for a zero pivot.  Otherwise by rcp_nr alone,
+     * and false as soon as a pivot lies outside rcp_nr's range (the caller
+     * then repeats the inversion with SAFE; inside the range both give the
+     * same bits). */
+    template <bool SAFE>
     __device__ __forceinline__ bool gj_real(LT (&a)[M], LT& d, int& org) {
         bool ok = true;
+        const int q = opaque_int(this->q);
+        const int m = opaque_uniform(this->m);
+        const bool act = q < m;
         org = q;
         d = LT(0);
 #pragma unroll
@@ -357,10 +380,14 @@ struct GroupCell {
             if (kk < m) {
                 const bool below = act && q > kk;
                 const unsigned key = below ? mag_key(absv(a[kk])) : 0u;
-                const unsigned kmax = grp_max_u(key);
                 LT akk = bcast_dyn(a[kk], kk);
-                const bool need = kmax > mag_key(absv(akk));
-                if (__ballot(need) != 0ull) {
+                const unsigned kd = mag_key(absv(akk));
+                /* an exchange is needed in a group iff one of its lanes
+                 * below the diagonal holds a larger key than the diagonal;
+                 * the group maximum is formed only then (rarely) */
+                if (__ballot(key > kd) != 0ull) {
+                    const unsigned kmax = grp_max_u(key);
+                    const bool need = kmax > kd;
                     const unsigned cand = grp_bits(below && key == kmax);
                     const int p = (need && cand) ? __ffs(cand) - 1 : kk;
                     const int src = (q == kk) ? p : (q == p ? kk : q);
@@ -369,8 +396,14 @@ struct GroupCell {
                     org = grp_shfl(org, src);
                     akk = bcast_dyn(a[kk], kk);
                 }
-                ok = ok && (akk != LT(0));
-                const LT inv = rcp(akk);
+                LT inv;
+                if constexpr (SAFE) {
+                    ok = ok && (akk != LT(0));
+                    inv = rcp(akk);
+                } else {
+                    ok = ok && rcp_nr_ok(akk);
+                    inv = rcp_nr(akk);
+                }
                 const bool piv = q == kk;
                 const LT f = piv ? LT(0) : a[kk] * inv;
                 if constexpr (kFused) {
@@ -388,8 +421,12 @@ struct GroupCell {
     }
 
     /* ---- inverse of E2 (complex), same scheme in complex arithmetic ---- */
+    template <bool SAFE>
     __device__ __forceinline__ bool gj_cplx(LT (&ar)[M], LT (&ai)[M], LT& dr, LT& di, int& org) {
         bool ok = true;
+        const int q = opaque_int(this->q);
+        const int m = opaque_uniform(this->m);
+        const bool act = q < m;
         org = q;
         dr = di = LT(0);
 #pragma unroll
@@ -397,10 +434,11 @@ struct GroupCell {
             if (kk < m) {
                 const bool below = act && q > kk;
                 const unsigned key = below ? mag_key(ar[kk] * ar[kk] + ai[kk] * ai[kk]) : 0u;
-                const unsigned kmax = grp_max_u(key);
                 LT pr = bcast_dyn(ar[kk], kk), pi = bcast_dyn(ai[kk], kk);
-                const bool need = kmax > mag_key(pr * pr + pi * pi);
-                if (__ballot(need) != 0ull) {
+                const unsigned kd = mag_key(pr * pr + pi * pi);
+                if (__ballot(key > kd) != 0ull) {
+                    const unsigned kmax = grp_max_u(key);
+                    const bool need = kmax > kd;
                     const unsigned cand = grp_bits(below && key == kmax);
                     const int p = (need && cand) ? __ffs(cand) - 1 : kk;
                     const int src = (q == kk) ? p : (q == p ? kk : q);
@@ -413,8 +451,15 @@ struct GroupCell {
                     pr = bcast_dyn(ar[kk], kk);
                     pi = bcast_dyn(ai[kk], kk);
                 }
-                ok = ok && !(pr == LT(0) && pi == LT(0));
-                const LT rn = rcp(pr * pr + pi * pi);
+                const LT nn = pr * pr + pi * pi;
+                LT rn;
+                if constexpr (SAFE) {
+                    ok = ok && !(pr == LT(0) && pi == LT(0));
+                    rn = rcp(nn);
+                } else {
+                    ok = ok && rcp_nr_ok(nn);
+                    rn = rcp_nr(nn);
+                }
                 const LT ir = pr * rn, ii = -pi * rn; /* 1 / (pr + i pi) */
                 const bool piv = q == kk;
                 const LT xr = ar[kk], xi = ai[kk];
@@ -485,18 +530,37 @@ struct GroupCell {
         bi = sr * d2i + si * d2r;
     }
 
-    __device__ __forceinline__ bool factor() {
+    /* rows q of E1 = (gamma/h) I - J and E2 = ((alpha + i beta)/h) I - J */
+    __device__ __forceinline__ void form_e() {
         const double g = radau::GAMMA * ih, ar = radau::ALPHA * ih, bi = radau::BETA * ih;
+        const int qv = opaque_int(q);
+        const bool av = qv < m;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-            const double mj = -jac(j);
-            const bool d = act && j == q;
+            const double mj = -jac(j, qv, av);
+            const bool d = av && j == qv;
             e1[j] = (LT)(d ? g + mj : mj);
             e2r[j] = (LT)(d ? ar + mj : mj);
             e2i[j] = (LT)(d ? bi : 0.0);
         }
-        const bool ok1 = gj_real(e1, d1, org1);
-        const bool ok2 = gj_cplx(e2r, e2i, d2r, d2i, org2);
+    }
+
+    /* Both inverses; false if E1 or E2 is singular.  A group whose pivots
+     * leave the fast reciprocal's range (rare: near-singular or badly scaled
+     * matrices) inverts again with the safe reciprocal, so every group ends
+     * with the bits of the safe inversion. */
+    __device__ __forceinline__ bool factor() {
+        form_e();
+        bool ok1 = gj_real<false>(e1, d1, org1);
+        bool ok2 = gj_cplx<false>(e2r, e2i, d2r, d2i, org2);
+        const bool redo = !(ok1 && ok2); /* group-uniform */
+        if (__ballot(redo) != 0ull) {
+            if (redo) {
+                form_e();
+                ok1 = gj_real<true>(e1, d1, org1);
+                ok2 = gj_cplx<true>(e2r, e2i, d2r, d2i, org2);
+            }
+        }
         return ok1 && ok2;
     }
 

@@ -36,19 +36,31 @@ __device__ __forceinline__ double rcp_nr(double a) {
     return r;
 }
 
+/* a inside the range where rcp_nr is valid (false for zero, denormals,
+ * huge and non-finite values) */
+__device__ __forceinline__ bool rcp_nr_ok(double a) {
+    const double aa = __builtin_fabs(a);
+    return aa >= kFastLo && aa <= kFastHi;
+}
+
 __device__ __forceinline__ double rcp(double a) {
     double r = rcp_nr(a);
-    const double aa = __builtin_fabs(a);
-    const bool ok = aa >= kFastLo && aa <= kFastHi;
+    const bool ok = rcp_nr_ok(a);
     if (__ballot(!ok) != 0ull) r = ok ? r : slow_rcp(a);
     return r;
 }
 /* FP32: v_rcp_f32 and one Newton step, IEEE division outside [1e-36, 1e36]. */
-__device__ __forceinline__ float rcp(float a) {
-    float r = __builtin_amdgcn_rcpf(a);
-    r = __builtin_fmaf(__builtin_fmaf(-a, r, 1.0f), r, r);
+__device__ __forceinline__ float rcp_nr(float a) {
+    const float r = __builtin_amdgcn_rcpf(a);
+    return __builtin_fmaf(__builtin_fmaf(-a, r, 1.0f), r, r);
+}
+__device__ __forceinline__ bool rcp_nr_ok(float a) {
     const float aa = __builtin_fabsf(a);
-    const bool ok = aa >= 1e-36f && aa <= 1e36f;
+    return aa >= 1e-36f && aa <= 1e36f;
+}
+__device__ __forceinline__ float rcp(float a) {
+    float r = rcp_nr(a);
+    const bool ok = rcp_nr_ok(a);
     if (__ballot(!ok) != 0ull) r = ok ? r : 1.0f / a;
     return r;
 }
