@@ -67,6 +67,12 @@ hipError_t launch_reset(unsigned long long* p, int n, hipStream_t s) {
     RD_PERS_U(KIND, MODEL, M, PREC, LT, 31, 128, 3, 40, 2, 40, 64, TAG ".persistent.b128.w3.fs40.p2.l64"), \
     RD_PERS_U(KIND, MODEL, M, PREC, LT, 32, 128, 3, 40, 2, 64, 64, TAG ".persistent.b128.w3.fs40.p2.u64.l64"), \
     RD_PERS_A(KIND, MODEL, M, PREC, LT, 33, 128, 3, 48, 2, 64, 64, TAG ".persistent.b128.w3.fs48.p2.u64.l64.aos"), \
+    RD_PERS_U(KIND, MODEL, M, PREC, LT, 34, 128, 3, 48, 2, 64, 64, TAG ".persistent.b128.w3.fs48.p2.u64.l64"), \
+    RD_PERS_C(KIND, MODEL, M, PREC, LT, 35, 128, 3, 48, 2, 64, 64, 16, TAG ".persistent.b128.w3.fs48.p2.u64.l64.c16"), \
+    RD_PERS_C(KIND, MODEL, M, PREC, LT, 36, 128, 3, 48, 2, 64, 64, 24, TAG ".persistent.b128.w3.fs48.p2.u64.l64.c24"), \
+    RD_PERS_C(KIND, MODEL, M, PREC, LT, 37, 128, 3, 48, 2, 64, 64, 36, TAG ".persistent.b128.w3.fs48.p2.u64.l64.c36"), \
+    RD_PERS_C(KIND, MODEL, M, PREC, LT, 38, 128, 3, 56, 2, 64, 64, 28, TAG ".persistent.b128.w3.fs56.p2.u64.l64.c28"), \
+    RD_PERS_C(KIND, MODEL, M, PREC, LT, 39, 128, 3, 64, 2, 64, 64, 28, TAG ".persistent.b128.w3.fs64.p2.u64.l64.c28"), \
     RD_ONE(KIND, MODEL, M, PREC, LT, false, 2, 256, 1, 16, TAG ".onelaunch.b256.fs16"),       \
     RD_ONE(KIND, MODEL, M, PREC, LT, false, 3, 256, 1, 1, TAG ".onelaunch.b256.fs1")
 

@@ -88,7 +88,11 @@ __device__ __forceinline__ int claim_priority(unsigned long long held, unsigned 
     return 0;
 }
 
-/* PLDS: the step parameters are staged in LDS and re-read each pass (true),
+/* CMIN > 1: a wave claims new cells only once at least CMIN of its lanes are
+ * idle, or none is left working; each claim round waits for the loads of the
+ * claimed cells, so fewer, larger rounds trade that latency against the
+ * passes an idle lane waits.  Changes when a cell starts, never its result.
+ * PLDS: the step parameters are staged in LDS and re-read each pass (true),
  * or read from the kernel arguments, where the compiler keeps them in scalar
  * registers across the loop (false).  Same arithmetic either way.  PDIV > 0:
  * wave issue priorities from claim positions (claim_priority).  Step-end
@@ -98,7 +102,7 @@ __device__ __forceinline__ int claim_priority(unsigned long long held, unsigned 
  * for all of them costs little), then FSU while the wave holds cells at the
  * top priority, else FSMIN. */
 template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool PLDS = true,
-          int PDIV = 0, int FSU = FSMIN, int FSL = FSMIN, bool AOS = false>
+          int PDIV = 0, int FSU = FSMIN, int FSL = FSMIN, bool AOS = false, int CMIN = 1>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_persistent(LaunchArgs a) {
     using L = SmallLds<Model::M>;
@@ -133,7 +137,10 @@ k_persistent(LaunchArgs a) {
             held = ~0ull;
         }
         const unsigned long long mask = __ballot(need);
-        if (mask) {
+        bool claim = mask != 0ull;
+        if (CMIN > 1 && claim && (unsigned)__popcll(mask) < (unsigned)CMIN)
+            claim = __ballot(alive && cell.phase != PH_IDLE) == 0ull;
+        if (claim) {
             const unsigned cnt = (unsigned)__popcll(mask);
             const unsigned rank = (unsigned)__popcll(mask & below);
             const unsigned long long avail = qend - qnext;
@@ -183,9 +190,9 @@ hipError_t launch_one(const LaunchArgs& a, int grid, hipStream_t s) {
 }
 
 template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool PLDS = true,
-          int PDIV = 0, int FSU = FSMIN, int FSL = FSMIN, bool AOS = false>
+          int PDIV = 0, int FSU = FSMIN, int FSL = FSMIN, bool AOS = false, int CMIN = 1>
 hipError_t launch_pers(const LaunchArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_persistent<Model, LT, FIXED, BLOCK, WPE, FSMIN, PLDS, PDIV, FSU, FSL, AOS>),
+    hipLaunchKernelGGL((k_persistent<Model, LT, FIXED, BLOCK, WPE, FSMIN, PLDS, PDIV, FSU, FSL, AOS, CMIN>),
                        dim3(grid), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
@@ -210,6 +217,10 @@ hipError_t launch_pers(const LaunchArgs& a, int grid, hipStream_t s) {
     {KIND, fd_jac_of<MODEL>::value ? 1 : 0, M, PREC, 0, false, VAR, BLOCK, BLOCK, NAME,           \
      &launch_pers<MODEL, LT, false, BLOCK, WPE, FS, true, PDIV, FSU, FSL, true>,                \
      (const void*)&k_persistent<MODEL, LT, false, BLOCK, WPE, FS, true, PDIV, FSU, FSL, true>}
+#define RD_PERS_C(KIND, MODEL, M, PREC, LT, VAR, BLOCK, WPE, FS, PDIV, FSU, FSL, CMIN, NAME)   \
+    {KIND, fd_jac_of<MODEL>::value ? 1 : 0, M, PREC, 0, false, VAR, BLOCK, BLOCK, NAME,           \
+     &launch_pers<MODEL, LT, false, BLOCK, WPE, FS, true, PDIV, FSU, FSL, false, CMIN>,         \
+     (const void*)&k_persistent<MODEL, LT, false, BLOCK, WPE, FS, true, PDIV, FSU, FSL, false, CMIN>}
 #define RD_PERS(KIND, MODEL, M, PREC, LT, FIXED, VAR, BLOCK, WPE, FS, NAME)                      \
     {KIND, fd_jac_of<MODEL>::value ? 1 : 0, M, PREC, 0, FIXED, VAR, BLOCK, BLOCK, NAME,                                          \
      &launch_pers<MODEL, LT, FIXED, BLOCK, WPE, FS>,                                            \
@@ -224,16 +235,17 @@ enum { K_OREG = 1, K_KIN = 2, K_NAG = 3, K_LIN = 4, K_ROB = 5, K_BC = 6 };
  * kernels (3 where the engine fits 168 registers with few spills, else 1);
  * the persistent kernels give waves that hold early claim positions (the
  * costliest cells under the longest-first order) a higher issue priority
- * (claim_priority with PDIV = 2), and batch step ends at 48 waiting lanes,
+ * (claim_priority with PDIV = 2), batch step ends at 48 waiting lanes,
  * or at all lanes while a wave still holds its first claims (its lanes then
- * started together on cells of similar cost) or holds the costliest cells */
+ * started together on cells of similar cost) or holds the costliest cells,
+ * and claim new cells in rounds of at least 28 idle lanes (CMIN) */
 #define RD_MODEL_SET_W(KIND, MODEL, M, TAG, WPE)                                                      \
     RD_ONE(KIND, MODEL, M, 0, double, false, 1, 256, 1, 32, TAG ".fp64.onelaunch.b256.fs32"),        \
     RD_ONE(KIND, MODEL, M, 1, float, false, 1, 256, 1, 32, TAG ".mixed.onelaunch.b256.fs32"),         \
-    RD_PERS_U(KIND, MODEL, M, 0, double, 1, 128, WPE, 48, 2, 64, 64,                                \
-              TAG ".fp64.persistent.b128.w" RD_STR(WPE) ".fs48.p2.u64.l64"),                        \
-    RD_PERS_U(KIND, MODEL, M, 1, float, 1, 128, WPE, 48, 2, 64, 64,                                 \
-              TAG ".mixed.persistent.b128.w" RD_STR(WPE) ".fs48.p2.u64.l64"),                       \
+    RD_PERS_C(KIND, MODEL, M, 0, double, 1, 128, WPE, 48, 2, 64, 64, 28,                            \
+              TAG ".fp64.persistent.b128.w" RD_STR(WPE) ".fs48.p2.u64.l64.c28"),                    \
+    RD_PERS_C(KIND, MODEL, M, 1, float, 1, 128, WPE, 48, 2, 64, 64, 28,                             \
+              TAG ".mixed.persistent.b128.w" RD_STR(WPE) ".fs48.p2.u64.l64.c28"),                   \
     RD_ONE(KIND, MODEL, M, 0, double, true, 1, 256, 1, 1, TAG ".fp64.onelaunch.fixed"),             \
     RD_PERS(KIND, MODEL, M, 0, double, true, 1, 256, 1, 1, TAG ".fp64.persistent.fixed")
 #define RD_MODEL_SET(KIND, MODEL, M, TAG) RD_MODEL_SET_W(KIND, MODEL, M, TAG, 3)
