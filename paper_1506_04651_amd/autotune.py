@@ -3,7 +3,8 @@
 The library compiles several variants of each kernel: work-group size, the
 waves-per-SIMD target the register allocator is held to (higher occupancy at
 the price of spills), how many lanes must wait before the step-end block runs
-(batching), whether the step parameters are staged in LDS or kept in scalar
+(batching), how many lanes must be idle before a wave claims new cells (claim
+rounds), whether the step parameters are staged in LDS or kept in scalar
 registers, the layout of the per-lane LDS slots (lane columns or lane rows),
 the wave issue priorities of the persistent schedule and, for the 16-lane
 kernels, fused or separate broadcasts and 8 or 16 matrix columns per lane;

@@ -8,8 +8,9 @@
  * error of a few units in the last place, the size of the rounding
  * differences that already separate any two orderings of the same arithmetic.
  * Arguments outside the range where the estimate is safe (zero, denormal,
- * huge, non-finite) take the library operation instead; that branch runs only
- * when some lane of the wave needs it.
+ * huge, non-finite) take the library operation instead, in an out-of-line
+ * call that runs only in the lanes that need it (and is skipped when no lane
+ * of the wave does).
  */
 #pragma once
 #include <hip/hip_runtime.h>
@@ -25,6 +26,7 @@ __device__ __noinline__ double slow_rcp(double a) { return 1.0 / a; }
 __device__ __noinline__ double slow_sqrt(double x) { return __builtin_sqrt(x); }
 __device__ __noinline__ double slow_rroot4(double x) { return 1.0 / __builtin_sqrt(__builtin_sqrt(x)); }
 __device__ __noinline__ double slow_pow08(double x) { return pow(x, 0.8); }
+__device__ __noinline__ float slow_rcpf(float a) { return 1.0f / a; }
 constexpr float kSeedLo = 1e-30f, kSeedHi = 1e30f;  /* FP32 seeds valid inside */
 
 /* 1/a for |a| in [kFastLo, kFastHi]: v_rcp_f64 and two Newton steps
@@ -46,7 +48,7 @@ __device__ __forceinline__ bool rcp_nr_ok(double a) {
 __device__ __forceinline__ double rcp(double a) {
     double r = rcp_nr(a);
     const bool ok = rcp_nr_ok(a);
-    if (__ballot(!ok) != 0ull) r = ok ? r : slow_rcp(a);
+    if (!ok) r = slow_rcp(a);
     return r;
 }
 /* FP32: v_rcp_f32 and one Newton step, IEEE division outside [1e-36, 1e36]. */
@@ -61,7 +63,7 @@ __device__ __forceinline__ bool rcp_nr_ok(float a) {
 __device__ __forceinline__ float rcp(float a) {
     float r = rcp_nr(a);
     const bool ok = rcp_nr_ok(a);
-    if (__ballot(!ok) != 0ull) r = ok ? r : 1.0f / a;
+    if (!ok) r = slow_rcpf(a);
     return r;
 }
 
@@ -79,7 +81,7 @@ __device__ __forceinline__ double sqrt_nr(double x) {
 __device__ __forceinline__ double sqrt_f(double x) {
     double s = sqrt_nr(x);
     const bool ok = x >= kFastLo && x <= kFastHi;
-    if (__ballot(!ok) != 0ull) s = ok ? s : slow_sqrt(x);
+    if (!ok) s = slow_sqrt(x);
     return s;
 }
 
@@ -95,7 +97,7 @@ __device__ __forceinline__ double rroot4(double x) {
         y = __builtin_fma(0.25 * y, e, y);
     }
     const bool ok = x >= (double)kSeedLo && x <= (double)kSeedHi;
-    if (__ballot(!ok) != 0ull) y = ok ? y : slow_rroot4(x);
+    if (!ok) y = slow_rroot4(x);
     return y;
 }
 
@@ -114,7 +116,7 @@ __device__ __forceinline__ double pow08(double x) {
     }
     y = __builtin_fma(y, kDeltaLn2 * (double)lg, y);
     const bool ok = x >= (double)kSeedLo && x <= (double)kSeedHi;
-    if (__ballot(!ok) != 0ull) y = ok ? y : slow_pow08(x);
+    if (!ok) y = slow_pow08(x);
     return y;
 }
 
