@@ -488,7 +488,8 @@ struct GroupCell {
 
     /* x = E1^{-1} b = diag(d) R (P b); lane q holds b_q on entry, x_q on return */
     __device__ __forceinline__ LT solve_real(LT b) const {
-        if (__ballot(org1 != q) != 0ull) b = grp_shfl(b, org1);
+        /* the lane's row index from the lane id (cheaper than keeping q live) */
+        if (__ballot(org1 != grp_lane_here()) != 0ull) b = grp_shfl(b, org1);
         if constexpr (kFused) {
             if (m == M) {
                 if constexpr (NC == 16) return fused_mv16(e1, b) * d1;
@@ -503,7 +504,7 @@ struct GroupCell {
     }
 
     __device__ __forceinline__ void solve_cplx(LT& br, LT& bi) const {
-        if (__ballot(org2 != q) != 0ull) {
+        if (__ballot(org2 != grp_lane_here()) != 0ull) {
             br = grp_shfl(br, org2);
             bi = grp_shfl(bi, org2);
         }

@@ -12,6 +12,13 @@ namespace rd {
 constexpr int kGroup = 16;
 
 __device__ __forceinline__ unsigned grp_lane() { return __lane_id() & 15u; }
+/* The same, read from the hardware at this point: the compiler can neither
+ * hoist it out of a loop nor keep it live (and spill it) across one. */
+__device__ __forceinline__ int grp_lane_here() {
+    int v;
+    __asm__ volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(v));
+    return v & 15;
+}
 __device__ __forceinline__ unsigned grp_base() { return __lane_id() & 48u; }
 
 /* The 16 ballot bits of this lane's group. */
