@@ -46,15 +46,10 @@ namespace rd {
 __device__ __forceinline__ float absv(float x) { return __builtin_fabsf(x); }
 __device__ __forceinline__ double absv(double x) { return __builtin_fabs(x); }
 __device__ __forceinline__ float fmaf_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-/* v, opaque to the optimizer at this point: comparisons derived from it are
- * formed where they are used instead of being hoisted out of the kernel's
- * loop as lane masks (which would be kept in, and spilled from, scalar
- * registers) */
-__device__ __forceinline__ int opaque_int(int v) {
-    __asm__ volatile("" : "+v"(v));
-    return v;
-}
-/* the same for a wave-uniform value (kept in a scalar register) */
+/* v (wave-uniform, kept in a scalar register), opaque to the optimizer at
+ * this point: comparisons derived from it are formed where they are used
+ * instead of being hoisted out of the kernel's loop as lane masks (which
+ * would be kept in, and spilled from, scalar registers) */
 __device__ __forceinline__ int opaque_uniform(int v) {
     __asm__ volatile("" : "+s"(v));
     return v;
@@ -67,6 +62,8 @@ __device__ __forceinline__ double fmaf_t(double a, double b, double c) { return 
 struct GroupTable {
     static constexpr int STRIDE = 2 * kGroup + 2;
     static constexpr int DOUBLES = kGroup * STRIDE;
+    /* the two padding columns of every row hold 1/m and 1/(3m) */
+    static constexpr int INVM = 2 * kGroup, INV3M = 2 * kGroup + 1;
 };
 
 /* f_i = sum_j K_ij u_j - u_i sum_k G_ik u_k; J_ij = K_ij - u_i G_ij - d_ij (G u)_i */
@@ -115,7 +112,6 @@ struct GroupCell {
     /* FP32 inverses: every solve is refined once against the FP64 matrices */
     static constexpr bool kRefine = sizeof(LT) < sizeof(double);
     int m;           /* species (run time, 1..16) */
-    double inv3m, invm;
 
     /* lane-q components */
     double y, f0, isc, w1, w2, w3;
@@ -132,6 +128,20 @@ struct GroupCell {
         if constexpr (COLD) return cl[i * jstride];
         else return creg[i];
     }
+    /* the counters that change once per step or less (the step count is
+     * the sum of accepted and rejected steps); COLD: in further LDS slots,
+     * the low word of slot C_N + i */
+    enum : int { K_NACC = 0, K_NREJ, K_NJAC, K_NDEC, K_N };
+    static constexpr int COLD_SLOTS = C_N + K_N; /* LDS slots per lane (COLD) */
+    int kreg[K_N];
+    __device__ __forceinline__ int& kc(int i) {
+        if constexpr (COLD) return *reinterpret_cast<int*>(cl + (C_N + i) * jstride);
+        else return kreg[i];
+    }
+    __device__ __forceinline__ int kc(int i) const {
+        if constexpr (COLD) return *reinterpret_cast<const int*>(cl + (C_N + i) * jstride);
+        else return kreg[i];
+    }
     LT e1[M], e2r[M], e2i[M]; /* rows of the Gauss-Jordan inverses (see gj_real) */
     LT d1, d2r, d2i;          /* reciprocal pivots */
     int org1, org2;
@@ -146,7 +156,7 @@ struct GroupCell {
     double t, h, ih, eta, inprev;
     unsigned flags;
     int phase, status, k, nsing, outcome;
-    int nstep, naccept, nreject, nfev, njac, ndec, nsol, nnewt;
+    int nfev, nsol, nnewt;
 
     __device__ __forceinline__ bool has(unsigned f) const { return (flags & f) != 0u; }
     __device__ __forceinline__ void set(unsigned f, bool v) { flags = v ? (flags | f) : (flags & ~f); }
@@ -297,7 +307,8 @@ struct GroupCell {
     __device__ __forceinline__ void load(const StepParams& P, const double* __restrict__ states,
                                          int64_t n, int64_t c, const double* __restrict__ hcell) {
         y = act ? states[(int64_t)q * n + c] : 0.0;
-        nstep = naccept = nreject = njac = ndec = nsol = nnewt = 0;
+        kc(K_NACC) = kc(K_NREJ) = kc(K_NJAC) = kc(K_NDEC) = 0;
+        nsol = nnewt = 0;
         nfev = 1;
         double gu;
         f0 = rhs(y, gu);
@@ -329,12 +340,12 @@ struct GroupCell {
         if (hcell && q == 0) hcell[c] = cv(C_HPRE);
         if (stats && q == 0) {
             stats[0 * n + c] = status;
-            stats[1 * n + c] = nstep;
-            stats[2 * n + c] = naccept;
-            stats[3 * n + c] = nreject;
+            stats[1 * n + c] = kc(K_NACC) + kc(K_NREJ);
+            stats[2 * n + c] = kc(K_NACC);
+            stats[3 * n + c] = kc(K_NREJ);
             stats[4 * n + c] = nfev;
-            stats[5 * n + c] = njac;
-            stats[6 * n + c] = ndec;
+            stats[5 * n + c] = kc(K_NJAC);
+            stats[6 * n + c] = kc(K_NDEC);
             stats[7 * n + c] = nsol;
             stats[8 * n + c] = nnewt;
         }
@@ -370,7 +381,7 @@ struct GroupCell {
     template <bool SAFE>
     __device__ __forceinline__ bool gj_real(LT (&a)[M], LT& d, int& org) {
         bool ok = true;
-        const int q = opaque_int(this->q);
+        const int q = grp_lane_here();
         const int m = opaque_uniform(this->m);
         const bool act = q < m;
         org = q;
@@ -424,7 +435,7 @@ struct GroupCell {
     template <bool SAFE>
     __device__ __forceinline__ bool gj_cplx(LT (&ar)[M], LT (&ai)[M], LT& dr, LT& di, int& org) {
         bool ok = true;
-        const int q = opaque_int(this->q);
+        const int q = grp_lane_here();
         const int m = opaque_uniform(this->m);
         const bool act = q < m;
         org = q;
@@ -534,7 +545,7 @@ struct GroupCell {
     /* rows q of E1 = (gamma/h) I - J and E2 = ((alpha + i beta)/h) I - J */
     __device__ __forceinline__ void form_e() {
         const double g = radau::GAMMA * ih, ar = radau::ALPHA * ih, bi = radau::BETA * ih;
-        const int qv = opaque_int(q);
+        const int qv = grp_lane_here();
         const bool av = qv < m;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
@@ -569,7 +580,7 @@ struct GroupCell {
     __device__ __forceinline__ void start(const StepParams& P) {
         if (!FIXED) {
             cv(C_HPRE) = h;
-            if (nstep >= P.max_steps) { status = ST_MAXSTEPS; phase = PH_IDLE; return; }
+            if (kc(K_NACC) + kc(K_NREJ) >= P.max_steps) { status = ST_MAXSTEPS; phase = PH_IDLE; return; }
             if (h < P.h_min) { status = ST_HSMALL; phase = PH_IDLE; return; }
             const bool last = t + 1.0001 * h >= P.dt;
             if (last) {
@@ -590,11 +601,11 @@ struct GroupCell {
                 cv(C_UJ) = y;
                 cv(C_GJ) = gu;
             }
-            ++njac;
+            ++kc(K_NJAC);
             flags = (flags & ~(F_JSTALE | F_LUOK)) | F_JATY0;
         }
         if (FIXED || !has(F_LUOK)) {
-            ++ndec;
+            ++kc(K_NDEC);
             if (!factor()) {
                 if (FIXED || ++nsing >= 5) { status = ST_SINGULAR; phase = PH_IDLE; return; }
                 h *= 0.5;
@@ -685,7 +696,7 @@ struct GroupCell {
         const double dz3 = d1 + d2;
         const double s1 = dz1 * isc, s2 = dz2 * isc, s3 = dz3 * isc;
         const double acc = grp_sum(s1 * s1 + s2 * s2 + s3 * s3);
-        const double nk = sqrt_f(acc * inv3m);
+        const double nk = sqrt_f(acc * kg[GroupTable::INV3M]);
         if (!finite_d(nk)) return NW_FAILED;
         const double tol = P.newton_tol;
         if (k >= 2) {
@@ -718,15 +729,14 @@ struct GroupCell {
             e += (double)c;
         }
         const double s = e * isc;
-        return sqrt_f(grp_sum(s * s) * invm);
+        return sqrt_f(grp_sum(s * s) * kg[GroupTable::INVM]);
     }
 
     template <bool FIXED>
     __device__ __forceinline__ void finish(const StepParams& P, int oc) {
         if (FIXED) {
             if (oc == NW_FAILED) { status = ST_NEWTON; phase = PH_IDLE; return; }
-            ++nstep;
-            ++naccept;
+            ++kc(K_NACC);
             cv(C_Z1) = radau::T11 * w1 + radau::T12 * w2 + radau::T13 * w3;
             cv(C_Z2) = radau::T21 * w1 + radau::T22 * w2 + radau::T23 * w3;
             cv(C_Z3) = w1 + w2;
@@ -738,12 +748,11 @@ struct GroupCell {
             if (grp_bits(finite_d(y)) != 0xFFFFu) { status = ST_NONFINITE; phase = PH_IDLE; return; }
             cv(C_HOLD) = h;
             eta = pow08(fmax(eta, UROUND));
-            phase = (naccept >= P.fixed_steps) ? PH_IDLE : PH_START;
+            phase = (kc(K_NACC) >= P.fixed_steps) ? PH_IDLE : PH_START;
             return;
         }
         if (oc == NW_FAILED) {
-            ++nstep;
-            ++nreject;
+            ++kc(K_NREJ);
             h *= 0.5;
             flags = (flags | F_REJECT) & ~F_LUOK;
             if (!has(F_JATY0)) flags |= F_JSTALE;
@@ -759,7 +768,6 @@ struct GroupCell {
             err = estimate(fe, e);
         }
         if (!finite_d(err)) { status = ST_NONFINITE; phase = PH_IDLE; return; }
-        ++nstep;
         const double fac = k <= kMaxFacTable
                                ? P.fac[k]
                                : 0.9 * (2.0 * P.kmax + 1.0) / (2.0 * P.kmax + (double)k);
@@ -798,7 +806,7 @@ struct GroupCell {
             t = has(F_LAST) ? P.dt : t + h;
             cv(C_HOLD) = h;
             eta = pow08(fmax(eta, UROUND));
-            ++naccept;
+            ++kc(K_NACC);
             if (has(F_REJECT)) h_new = fmin(h_new, h);
             const bool keep_j = has(F_KEEPJ);
             flags = (flags & ~(F_FIRST | F_REJECT | F_JATY0 | F_JSTALE)) | F_OLD | F_ACC |
@@ -812,7 +820,7 @@ struct GroupCell {
             h = hn;
             phase = (t < P.dt) ? PH_START : PH_IDLE;
         } else {
-            ++nreject;
+            ++kc(K_NREJ);
             const double hn = has(F_FIRST) ? 0.1 * h : h_new;
             if (hn != h) flags &= ~F_LUOK;
             h = hn;

@@ -22,15 +22,19 @@ namespace rd {
 
 constexpr unsigned kGroupClaimChunk = 4; /* cells */
 
-/* Model rows into LDS, zero padded to 16 x 16 (K then G per row); the
- * bytecode model has no rows (its program is read from the parameter block). */
+/* Model rows into LDS, zero padded to 16 x 16 (K then G per row), and 1/m,
+ * 1/(3m) in the padding columns of every row; the bytecode model has no rows
+ * (its program is read from the parameter block). */
 template <class Model>
 __device__ __forceinline__ void load_table(double* tab, const double* __restrict__ p, int m, int block) {
-    if (bytecode_of<Model>::value) return;
     for (int i = threadIdx.x; i < GroupTable::DOUBLES; i += block) {
         const int row = i / GroupTable::STRIDE, col = i % GroupTable::STRIDE;
         double v = 0.0;
-        if (row < m) {
+        if (col == GroupTable::INVM) {
+            v = 1.0 / m;
+        } else if (col == GroupTable::INV3M) {
+            v = 1.0 / (3.0 * m);
+        } else if (!bytecode_of<Model>::value && row < m) {
             if (col < m) v = p[row * m + col];
             else if (Model::HAS_G && col >= kGroup && col < kGroup + m) v = p[m * m + row * m + (col - kGroup)];
         }
@@ -51,8 +55,6 @@ __device__ __forceinline__ void init_cell(Cell& cell, const double* tab, double*
     cell.prog = params;
     cell.m = m;
     cell.act = cell.q < m;
-    cell.inv3m = 1.0 / (3.0 * m);
-    cell.invm = 1.0 / m;
     cell.kg = tab + cell.q * GroupTable::STRIDE;
     cell.phase = PH_IDLE;
     cell.status = ST_OK;
@@ -89,7 +91,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE,
 k_group_onelaunch(LaunchArgs a, int m) {
     __shared__ double tab[GroupTable::DOUBLES];
     __shared__ double jfd[fd_jac_of<Model>::value ? NC * BLOCK : 1];
-    __shared__ double gcold[COLD ? GroupCell<Model, LT, FUSE, NC, COLD>::C_N * BLOCK : 1];
+    __shared__ double gcold[COLD ? GroupCell<Model, LT, FUSE, NC, COLD>::COLD_SLOTS * BLOCK : 1];
     __shared__ StepParams sP;
     stage_params(sP, a.P);
     load_table<Model>(tab, a.params, m, BLOCK);
@@ -109,7 +111,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE,
 k_group_persistent(LaunchArgs a, int m) {
     __shared__ double tab[GroupTable::DOUBLES];
     __shared__ double jfd[fd_jac_of<Model>::value ? NC * BLOCK : 1];
-    __shared__ double gcold[COLD ? GroupCell<Model, LT, FUSE, NC, COLD>::C_N * BLOCK : 1];
+    __shared__ double gcold[COLD ? GroupCell<Model, LT, FUSE, NC, COLD>::COLD_SLOTS * BLOCK : 1];
     __shared__ StepParams sP;
     stage_params(sP, a.P);
     load_table<Model>(tab, a.params, m, BLOCK);

@@ -73,6 +73,10 @@ hipError_t launch_reset(unsigned long long* p, int n, hipStream_t s) {
     RD_PERS_C(KIND, MODEL, M, PREC, LT, 37, 128, 3, 48, 2, 64, 64, 36, TAG ".persistent.b128.w3.fs48.p2.u64.l64.c36"), \
     RD_PERS_C(KIND, MODEL, M, PREC, LT, 38, 128, 3, 56, 2, 64, 64, 28, TAG ".persistent.b128.w3.fs56.p2.u64.l64.c28"), \
     RD_PERS_C(KIND, MODEL, M, PREC, LT, 39, 128, 3, 64, 2, 64, 64, 28, TAG ".persistent.b128.w3.fs64.p2.u64.l64.c28"), \
+    RD_PERS_C(KIND, MODEL, M, PREC, LT, 40, 256, 3, 48, 2, 64, 64, 28, TAG ".persistent.b256.w3.fs48.p2.u64.l64.c28"), \
+    RD_PERS_C(KIND, MODEL, M, PREC, LT, 41, 128, 3, 48, 0, 48, 48, 28, TAG ".persistent.b128.w3.fs48.c28"), \
+    RD_PERS_C(KIND, MODEL, M, PREC, LT, 42, 128, 3, 48, 2, 48, 48, 28, TAG ".persistent.b128.w3.fs48.p2.c28"), \
+    RD_PERS_C(KIND, MODEL, M, PREC, LT, 43, 64, 3, 48, 2, 64, 64, 28, TAG ".persistent.b64.w3.fs48.p2.u64.l64.c28"), \
     RD_ONE(KIND, MODEL, M, PREC, LT, false, 2, 256, 1, 16, TAG ".onelaunch.b256.fs16"),       \
     RD_ONE(KIND, MODEL, M, PREC, LT, false, 3, 256, 1, 1, TAG ".onelaunch.b256.fs1")
 
