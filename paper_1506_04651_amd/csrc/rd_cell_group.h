@@ -128,10 +128,11 @@ struct GroupCell {
         if constexpr (COLD) return cl[i * jstride];
         else return creg[i];
     }
-    /* the counters that change once per step or less (the step count is
-     * the sum of accepted and rejected steps); COLD: in further LDS slots,
-     * the low word of slot C_N + i */
-    enum : int { K_NACC = 0, K_NREJ, K_NJAC, K_NDEC, K_N };
+    /* the counters, updated once per step or less: the step count is the
+     * sum of accepted and rejected steps, and a step's Newton iterations
+     * (k of them: 3 k f evaluations, k solves) are added when it ends;
+     * COLD: in further LDS slots, the low word of slot C_N + i */
+    enum : int { K_NACC = 0, K_NREJ, K_NJAC, K_NDEC, K_NFEV, K_NSOL, K_NNEWT, K_N };
     static constexpr int COLD_SLOTS = C_N + K_N; /* LDS slots per lane (COLD) */
     int kreg[K_N];
     __device__ __forceinline__ int& kc(int i) {
@@ -156,7 +157,6 @@ struct GroupCell {
     double t, h, ih, eta, inprev;
     unsigned flags;
     int phase, status, k, nsing, outcome;
-    int nfev, nsol, nnewt;
 
     __device__ __forceinline__ bool has(unsigned f) const { return (flags & f) != 0u; }
     __device__ __forceinline__ void set(unsigned f, bool v) { flags = v ? (flags | f) : (flags & ~f); }
@@ -301,15 +301,15 @@ struct GroupCell {
                 jl[j * jstride] = act ? (fp - f0) / dj : 0.0;
             }
         }
-        nfev += m;
+        kc(K_NFEV) += m;
     }
 
     __device__ __forceinline__ void load(const StepParams& P, const double* __restrict__ states,
                                          int64_t n, int64_t c, const double* __restrict__ hcell) {
         y = act ? states[(int64_t)q * n + c] : 0.0;
         kc(K_NACC) = kc(K_NREJ) = kc(K_NJAC) = kc(K_NDEC) = 0;
-        nsol = nnewt = 0;
-        nfev = 1;
+        kc(K_NSOL) = kc(K_NNEWT) = 0;
+        kc(K_NFEV) = 1;
         double gu;
         f0 = rhs(y, gu);
         status = ST_OK;
@@ -343,11 +343,11 @@ struct GroupCell {
             stats[1 * n + c] = kc(K_NACC) + kc(K_NREJ);
             stats[2 * n + c] = kc(K_NACC);
             stats[3 * n + c] = kc(K_NREJ);
-            stats[4 * n + c] = nfev;
+            stats[4 * n + c] = kc(K_NFEV);
             stats[5 * n + c] = kc(K_NJAC);
             stats[6 * n + c] = kc(K_NDEC);
-            stats[7 * n + c] = nsol;
-            stats[8 * n + c] = nnewt;
+            stats[7 * n + c] = kc(K_NSOL);
+            stats[8 * n + c] = kc(K_NNEWT);
         }
     }
 
@@ -646,7 +646,6 @@ struct GroupCell {
 
     __device__ __forceinline__ int newton(const StepParams& P) {
         ++k;
-        ++nnewt;
         double G1, G2, G3, gu;
         {
             const double z = radau::T11 * w1 + radau::T12 * w2 + radau::T13 * w3;
@@ -669,13 +668,11 @@ struct GroupCell {
             G2 += radau::TI23 * F;
             G3 += radau::TI33 * F;
         }
-        nfev += 3;
         const double g = radau::GAMMA * ih, al = radau::ALPHA * ih, be = radau::BETA * ih;
         const double b1 = G1 - g * w1, b2 = G2 - al * w2 + be * w3, b3 = G3 - be * w2 - al * w3;
         const LT r1 = solve_real((LT)b1);
         LT r2 = (LT)b2, r3 = (LT)b3;
         solve_cplx(r2, r3);
-        ++nsol;
         double d1 = (double)r1, d2 = (double)r2, d3 = (double)r3;
         if constexpr (kRefine) {
             /* one step of iterative refinement against the FP64 matrices
@@ -722,7 +719,7 @@ struct GroupCell {
         constexpr double DW3 = radau::D1 * radau::T13 + radau::D2 * radau::T23;
         const double b = fb + (DW1 * w1 + DW2 * w2 + DW3 * w3) * ih;
         const LT v = solve_real((LT)b);
-        ++nsol;
+        ++kc(K_NSOL);
         e = (double)v;
         if constexpr (kRefine) {
             const LT c = solve_real((LT)(b - (radau::GAMMA * ih) * e + jmul(e)));
@@ -734,6 +731,9 @@ struct GroupCell {
 
     template <bool FIXED>
     __device__ __forceinline__ void finish(const StepParams& P, int oc) {
+        kc(K_NNEWT) += k;
+        kc(K_NSOL) += k;
+        kc(K_NFEV) += 3 * k;
         if (FIXED) {
             if (oc == NW_FAILED) { status = ST_NEWTON; phase = PH_IDLE; return; }
             ++kc(K_NACC);
@@ -743,7 +743,7 @@ struct GroupCell {
             y += cv(C_Z3);
             double gu;
             f0 = rhs(y, gu);
-            ++nfev;
+            ++kc(K_NFEV);
             flags |= F_OLD;
             if (grp_bits(finite_d(y)) != 0xFFFFu) { status = ST_NONFINITE; phase = PH_IDLE; return; }
             cv(C_HOLD) = h;
@@ -764,7 +764,7 @@ struct GroupCell {
         if (err >= 1.0 && (flags & (F_FIRST | F_REJECT))) {
             double gu;
             const double fe = rhs(y + e, gu);
-            ++nfev;
+            ++kc(K_NFEV);
             err = estimate(fe, e);
         }
         if (!finite_d(err)) { status = ST_NONFINITE; phase = PH_IDLE; return; }
@@ -789,7 +789,7 @@ struct GroupCell {
             const double y1 = y + zz3;
             double gu;
             const double f1 = rhs(y1, gu);
-            ++nfev;
+            ++kc(K_NFEV);
             if (grp_bits(finite_d(y1) && finite_d(f1)) != 0xFFFFu) {
                 status = ST_NONFINITE;
                 phase = PH_IDLE;
