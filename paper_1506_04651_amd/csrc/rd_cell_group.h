@@ -116,8 +116,9 @@ struct GroupCell {
     /* lane-q components */
     double y, f0, isc, w1, w2, w3;
     /* cold values: Z of the last accepted step, lane q's component of the
-     * Jacobian point and (G u)_q there, the step-control scalars */
-    enum : int { C_Z1 = 0, C_Z2, C_Z3, C_UJ, C_GJ, C_HOLD, C_IHACC, C_QACC, C_HPRE, C_N };
+     * Jacobian point and (G u)_q there, the step-control scalars and the
+     * Newton rate estimates (eta, 1/norm of the last increment) */
+    enum : int { C_Z1 = 0, C_Z2, C_Z3, C_UJ, C_GJ, C_HOLD, C_IHACC, C_QACC, C_HPRE, C_ETA, C_INPREV, C_N };
     double creg[C_N];
     double* cl; /* COLD: slot i at cl[i * jstride] (LDS) */
     __device__ __forceinline__ double& cv(int i) {
@@ -154,7 +155,7 @@ struct GroupCell {
     bool act;         /* q < m */
     /* per-cell scalars, replicated across the group (the step-control ones
      * that change once per step are cold values, cv) */
-    double t, h, ih, eta, inprev;
+    double t, h, ih;
     unsigned flags;
     int phase, status, k, nsing, outcome;
 
@@ -319,8 +320,8 @@ struct GroupCell {
         h = P.fixed_steps > 0 ? P.dt / P.fixed_steps
                               : fmin(hw > 0.0 ? hw : (P.h0 > 0.0 ? P.h0 : P.dt), P.dt);
         cv(C_HPRE) = fin ? h : 0.0;
-        cv(C_HOLD) = cv(C_IHACC) = cv(C_QACC) = inprev = 0.0;
-        eta = 1.0;
+        cv(C_HOLD) = cv(C_IHACC) = cv(C_QACC) = cv(C_INPREV) = 0.0;
+        cv(C_ETA) = 1.0;
         k = 0;
         nsing = 0;
         flags = F_FIRST | F_JSTALE;
@@ -640,7 +641,7 @@ struct GroupCell {
         w2 = radau::TI21 * za + radau::TI22 * zb + radau::TI23 * zc;
         w3 = radau::TI31 * za + radau::TI32 * zb + radau::TI33 * zc;
         k = 0;
-        inprev = 0.0;
+        cv(C_INPREV) = 0.0;
         phase = PH_NEWTON;
     }
 
@@ -697,10 +698,10 @@ struct GroupCell {
         if (!finite_d(nk)) return NW_FAILED;
         const double tol = P.newton_tol;
         if (k >= 2) {
-            const double th = nk * inprev;
+            const double th = nk * cv(C_INPREV);
             if (th >= 0.99) return NW_FAILED;
             const double om = 1.0 - th;
-            eta = th * rcp_nr(om);
+            cv(C_ETA) = th * rcp_nr(om);
             double tp = 1.0;
             for (int j = 0; j < P.kmax - k; ++j) tp *= th;
             if (tp * nk > tol * om) return NW_FAILED;
@@ -708,8 +709,8 @@ struct GroupCell {
         } else {
             set(F_KEEPJ, true);
         }
-        if (eta * nk <= tol) return NW_CONVERGED;
-        inprev = rcp(nk); /* nk > 0: nk == 0 converges above */
+        if (cv(C_ETA) * nk <= tol) return NW_CONVERGED;
+        cv(C_INPREV) = rcp(nk); /* nk > 0: nk == 0 converges above */
         return k >= P.kmax ? NW_FAILED : NW_CONTINUE;
     }
 
@@ -747,7 +748,7 @@ struct GroupCell {
             flags |= F_OLD;
             if (grp_bits(finite_d(y)) != 0xFFFFu) { status = ST_NONFINITE; phase = PH_IDLE; return; }
             cv(C_HOLD) = h;
-            eta = pow08(fmax(eta, UROUND));
+            cv(C_ETA) = pow08(fmax(cv(C_ETA), UROUND));
             phase = (kc(K_NACC) >= P.fixed_steps) ? PH_IDLE : PH_START;
             return;
         }
@@ -805,7 +806,7 @@ struct GroupCell {
             cv(C_Z3) = zz3;
             t = has(F_LAST) ? P.dt : t + h;
             cv(C_HOLD) = h;
-            eta = pow08(fmax(eta, UROUND));
+            cv(C_ETA) = pow08(fmax(cv(C_ETA), UROUND));
             ++kc(K_NACC);
             if (has(F_REJECT)) h_new = fmin(h_new, h);
             const bool keep_j = has(F_KEEPJ);
