@@ -463,16 +463,26 @@ struct GroupCell {
                     pr = bcast_dyn(ar[kk], kk);
                     pi = bcast_dyn(ai[kk], kk);
                 }
+                /* 1 / (pr + i pi) = (pr - i pi) / (pr^2 + pi^2) */
                 const LT nn = pr * pr + pi * pi;
-                LT rn;
+                LT ir, ii;
                 if constexpr (SAFE) {
                     ok = ok && !(pr == LT(0) && pi == LT(0));
-                    rn = rcp(nn);
+                    if (rcp_nr_ok(nn)) {
+                        const LT rn = rcp_nr(nn);
+                        ir = pr * rn;
+                        ii = -pi * rn;
+                    } else {
+                        const auto z = slow_crcp(pr, pi);
+                        ir = z.x;
+                        ii = z.y;
+                    }
                 } else {
                     ok = ok && rcp_nr_ok(nn);
-                    rn = rcp_nr(nn);
+                    const LT rn = rcp_nr(nn);
+                    ir = pr * rn;
+                    ii = -pi * rn;
                 }
-                const LT ir = pr * rn, ii = -pi * rn; /* 1 / (pr + i pi) */
                 const bool piv = q == kk;
                 const LT xr = ar[kk], xi = ai[kk];
                 const LT fr = piv ? LT(0) : xr * ir - xi * ii;

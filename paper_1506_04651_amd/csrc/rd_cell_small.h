@@ -174,8 +174,16 @@ __device__ __forceinline__ bool lu_cplx(T (&ar)[M][M], T (&ai)[M][M], unsigned& 
         }
         const T pr = ar[k][k], pi = ai[k][k];
         ok = ok && !(pr == T(0) && pi == T(0));
-        const T rn = rcp(pr * pr + pi * pi);
-        const T ir = pr * rn, ii = -pi * rn; /* 1/(pr + i pi) */
+        /* 1/(pr + i pi) = (pr - i pi) / (pr^2 + pi^2); scaled first where the
+         * square leaves the reciprocal's safe range */
+        const T nn = pr * pr + pi * pi;
+        const T rn = rcp_nr(nn);
+        T ir = pr * rn, ii = -pi * rn;
+        if (!rcp_nr_ok(nn)) {
+            const auto z = slow_crcp(pr, pi);
+            ir = z.x;
+            ii = z.y;
+        }
         ar[k][k] = ir;
         ai[k][k] = ii;
 #pragma unroll

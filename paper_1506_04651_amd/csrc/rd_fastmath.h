@@ -27,6 +27,22 @@ __device__ __noinline__ double slow_sqrt(double x) { return __builtin_sqrt(x); }
 __device__ __noinline__ double slow_rroot4(double x) { return 1.0 / __builtin_sqrt(__builtin_sqrt(x)); }
 __device__ __noinline__ double slow_pow08(double x) { return pow(x, 0.8); }
 __device__ __noinline__ float slow_rcpf(float a) { return 1.0f / a; }
+/* 1 / (pr + i pi) where pr^2 + pi^2 leaves the reciprocal's safe range (the
+ * square overflows or underflows although the pivot itself is
+ * representable): both parts are first divided by the larger magnitude.
+ * Returns (Re, Im); zero in, non-finite out. */
+__device__ __noinline__ double2 slow_crcp(double pr, double pi) {
+    const double s = fmax(__builtin_fabs(pr), __builtin_fabs(pi));
+    const double a = pr / s, b = pi / s;
+    const double d = s * (a * a + b * b);
+    return make_double2(a / d, -b / d);
+}
+__device__ __noinline__ float2 slow_crcp(float pr, float pi) {
+    const float s = fmaxf(__builtin_fabsf(pr), __builtin_fabsf(pi));
+    const float a = pr / s, b = pi / s;
+    const float d = s * (a * a + b * b);
+    return make_float2(a / d, -b / d);
+}
 constexpr float kSeedLo = 1e-30f, kSeedHi = 1e30f;  /* FP32 seeds valid inside */
 
 /* 1/a for |a| in [kFastLo, kFastHi]: v_rcp_f64 and two Newton steps

@@ -63,6 +63,7 @@ static const KernelEntry g_group_table[] = {
     RD_GPERS_C(2, GroupKinetics, 1, float, 13, 256, 3, 3, 16, "kinetics.g16.mixed.persistent.b256.w3.fs3.cold"),
     RD_GPERS(2, GroupKinetics, 0, double, false, 10, 256, 2, 4, "kinetics.g16.fp64.persistent.b256.w2.fs4"),
     RD_GPERS_C(2, GroupKinetics, 0, double, 11, 256, 2, 4, 16, "kinetics.g16.fp64.persistent.b256.w2.fs4.cold"),
+    RD_GPERS_C(2, GroupKinetics, 0, double, 12, 128, 3, 4, 16, "kinetics.g16.fp64.persistent.b128.w3.fs4.cold"),
     RD_GONE(2, GroupKinetics, 0, double, true, 1, 256, 1, 1, "kinetics.g16.fp64.onelaunch.fixed"),
     RD_GPERS(2, GroupKinetics, 0, double, true, 1, 256, 1, 1, "kinetics.g16.fp64.persistent.fixed"),
     /* 8 columns (m = 5..8) */

@@ -207,3 +207,33 @@ def test_kinetics16_mixed_precision_error_report(rd, orc):
     rep = compare(y[:, idx], st[:, idx], yo, sto, w.atol, label="kin16 mixed full sampled")
     assert rep["max_err"] <= 1e-8
     assert rep["trace_divergent"] == 0
+
+
+def _extreme_linear(m, n=256, seed=11):
+    """du/dt = A u with one eigenvalue -1e300 beside modest coupled ones: the
+    iteration matrices get pivots near 1e300, outside the range of the
+    engines' fast reciprocals, and |p|^2 of the complex pivot overflows (the
+    scaled complex reciprocal and, on the 16-lane engine, the safe re-inversion
+    run).  The oracle solves the untransformed real system.  The stiff
+    component ends at e^(-1e299) u0, i.e. zero up to the rounding of
+    y0 + z3 ~ 1e-16 |u0|, so atol (the error floor) is 1e-6 here."""
+    rng = np.random.default_rng(seed)
+    A = -np.diag(np.concatenate([[1e300], np.arange(1.0, m)]))
+    for i in range(1, m):
+        A[i, 1 + (i % (m - 1))] += 0.3
+    u = rng.uniform(0.1, 1.0, (m, n))
+    return W.Workload(f"linear{m}_extreme", np.ascontiguousarray(u), W.KIND_LINEAR,
+                      np.ascontiguousarray(A.ravel()), 0.1, 1e-6, 1e-6, {})
+
+
+@pytest.mark.parametrize("m", [3, 5, 16])
+def test_pivots_outside_the_fast_reciprocal_range(rd, orc, m):
+    w = _extreme_linear(m)
+    say("extreme linear m", m, "n", w.n)
+    y, st, ret = run_gpu(rd, w)
+    yo, sto, reto = run_oracle(orc, w)
+    assert ret == reto == 0
+    assert (sto[0] == 0).all() and (st[0] == 0).all()
+    rep = compare(y, st, yo, sto, w.atol, label=f"extreme linear m{m}")
+    assert rep["max_err"] <= 1e-8
+    assert rep["trace_divergent"] == 0
