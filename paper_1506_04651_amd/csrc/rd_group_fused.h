@@ -157,101 +157,225 @@ __device__ __forceinline__ void fused_row4(double u, const double* k, double& li
 #undef RD_ROWK
 
 /* Gauss-Jordan elimination step with pivot lane KK (real):
- *   a[j] += a_j(lane KK) * (-f)  for every column j.
- * Column KK is updated too and overwritten by the caller afterwards. */
+ *   a[j] += a_j(lane KK) * (-f)  for every column j != KK
+ * (column KK is overwritten by the caller afterwards).  One body per pivot
+ * column, generated: each lists the fifteen other columns in order. */
 #define RD_GJR(OP, J) OP " %" #J ", %" #J ", -%16 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n\t"
-#define RD_GJR_BODY(OP)                                                                           \
-    "s_nop 1\n\t"                                                                                 \
-    RD_GJR(OP, 0) RD_GJR(OP, 1) RD_GJR(OP, 2) RD_GJR(OP, 3) RD_GJR(OP, 4) RD_GJR(OP, 5)           \
-    RD_GJR(OP, 6) RD_GJR(OP, 7) RD_GJR(OP, 8) RD_GJR(OP, 9) RD_GJR(OP, 10) RD_GJR(OP, 11)         \
-    RD_GJR(OP, 12) RD_GJR(OP, 13) RD_GJR(OP, 14) RD_GJR(OP, 15) "s_nop 1"
+#define RD_GJR_S0(OP) "s_nop 1\n\t" RD_GJR(OP, 1) RD_GJR(OP, 2) RD_GJR(OP, 3) RD_GJR(OP, 4) RD_GJR(OP, 5) RD_GJR(OP, 6) RD_GJR(OP, 7) RD_GJR(OP, 8) RD_GJR(OP, 9) RD_GJR(OP, 10) RD_GJR(OP, 11) RD_GJR(OP, 12) RD_GJR(OP, 13) RD_GJR(OP, 14) RD_GJR(OP, 15) "s_nop 1"
+#define RD_GJR_S1(OP) "s_nop 1\n\t" RD_GJR(OP, 0) RD_GJR(OP, 2) RD_GJR(OP, 3) RD_GJR(OP, 4) RD_GJR(OP, 5) RD_GJR(OP, 6) RD_GJR(OP, 7) RD_GJR(OP, 8) RD_GJR(OP, 9) RD_GJR(OP, 10) RD_GJR(OP, 11) RD_GJR(OP, 12) RD_GJR(OP, 13) RD_GJR(OP, 14) RD_GJR(OP, 15) "s_nop 1"
+#define RD_GJR_S2(OP) "s_nop 1\n\t" RD_GJR(OP, 0) RD_GJR(OP, 1) RD_GJR(OP, 3) RD_GJR(OP, 4) RD_GJR(OP, 5) RD_GJR(OP, 6) RD_GJR(OP, 7) RD_GJR(OP, 8) RD_GJR(OP, 9) RD_GJR(OP, 10) RD_GJR(OP, 11) RD_GJR(OP, 12) RD_GJR(OP, 13) RD_GJR(OP, 14) RD_GJR(OP, 15) "s_nop 1"
+#define RD_GJR_S3(OP) "s_nop 1\n\t" RD_GJR(OP, 0) RD_GJR(OP, 1) RD_GJR(OP, 2) RD_GJR(OP, 4) RD_GJR(OP, 5) RD_GJR(OP, 6) RD_GJR(OP, 7) RD_GJR(OP, 8) RD_GJR(OP, 9) RD_GJR(OP, 10) RD_GJR(OP, 11) RD_GJR(OP, 12) RD_GJR(OP, 13) RD_GJR(OP, 14) RD_GJR(OP, 15) "s_nop 1"
+#define RD_GJR_S4(OP) "s_nop 1\n\t" RD_GJR(OP, 0) RD_GJR(OP, 1) RD_GJR(OP, 2) RD_GJR(OP, 3) RD_GJR(OP, 5) RD_GJR(OP, 6) RD_GJR(OP, 7) RD_GJR(OP, 8) RD_GJR(OP, 9) RD_GJR(OP, 10) RD_GJR(OP, 11) RD_GJR(OP, 12) RD_GJR(OP, 13) RD_GJR(OP, 14) RD_GJR(OP, 15) "s_nop 1"
+#define RD_GJR_S5(OP) "s_nop 1\n\t" RD_GJR(OP, 0) RD_GJR(OP, 1) RD_GJR(OP, 2) RD_GJR(OP, 3) RD_GJR(OP, 4) RD_GJR(OP, 6) RD_GJR(OP, 7) RD_GJR(OP, 8) RD_GJR(OP, 9) RD_GJR(OP, 10) RD_GJR(OP, 11) RD_GJR(OP, 12) RD_GJR(OP, 13) RD_GJR(OP, 14) RD_GJR(OP, 15) "s_nop 1"
+#define RD_GJR_S6(OP) "s_nop 1\n\t" RD_GJR(OP, 0) RD_GJR(OP, 1) RD_GJR(OP, 2) RD_GJR(OP, 3) RD_GJR(OP, 4) RD_GJR(OP, 5) RD_GJR(OP, 7) RD_GJR(OP, 8) RD_GJR(OP, 9) RD_GJR(OP, 10) RD_GJR(OP, 11) RD_GJR(OP, 12) RD_GJR(OP, 13) RD_GJR(OP, 14) RD_GJR(OP, 15) "s_nop 1"
+#define RD_GJR_S7(OP) "s_nop 1\n\t" RD_GJR(OP, 0) RD_GJR(OP, 1) RD_GJR(OP, 2) RD_GJR(OP, 3) RD_GJR(OP, 4) RD_GJR(OP, 5) RD_GJR(OP, 6) RD_GJR(OP, 8) RD_GJR(OP, 9) RD_GJR(OP, 10) RD_GJR(OP, 11) RD_GJR(OP, 12) RD_GJR(OP, 13) RD_GJR(OP, 14) RD_GJR(OP, 15) "s_nop 1"
+#define RD_GJR_S8(OP) "s_nop 1\n\t" RD_GJR(OP, 0) RD_GJR(OP, 1) RD_GJR(OP, 2) RD_GJR(OP, 3) RD_GJR(OP, 4) RD_GJR(OP, 5) RD_GJR(OP, 6) RD_GJR(OP, 7) RD_GJR(OP, 9) RD_GJR(OP, 10) RD_GJR(OP, 11) RD_GJR(OP, 12) RD_GJR(OP, 13) RD_GJR(OP, 14) RD_GJR(OP, 15) "s_nop 1"
+#define RD_GJR_S9(OP) "s_nop 1\n\t" RD_GJR(OP, 0) RD_GJR(OP, 1) RD_GJR(OP, 2) RD_GJR(OP, 3) RD_GJR(OP, 4) RD_GJR(OP, 5) RD_GJR(OP, 6) RD_GJR(OP, 7) RD_GJR(OP, 8) RD_GJR(OP, 10) RD_GJR(OP, 11) RD_GJR(OP, 12) RD_GJR(OP, 13) RD_GJR(OP, 14) RD_GJR(OP, 15) "s_nop 1"
+#define RD_GJR_S10(OP) "s_nop 1\n\t" RD_GJR(OP, 0) RD_GJR(OP, 1) RD_GJR(OP, 2) RD_GJR(OP, 3) RD_GJR(OP, 4) RD_GJR(OP, 5) RD_GJR(OP, 6) RD_GJR(OP, 7) RD_GJR(OP, 8) RD_GJR(OP, 9) RD_GJR(OP, 11) RD_GJR(OP, 12) RD_GJR(OP, 13) RD_GJR(OP, 14) RD_GJR(OP, 15) "s_nop 1"
+#define RD_GJR_S11(OP) "s_nop 1\n\t" RD_GJR(OP, 0) RD_GJR(OP, 1) RD_GJR(OP, 2) RD_GJR(OP, 3) RD_GJR(OP, 4) RD_GJR(OP, 5) RD_GJR(OP, 6) RD_GJR(OP, 7) RD_GJR(OP, 8) RD_GJR(OP, 9) RD_GJR(OP, 10) RD_GJR(OP, 12) RD_GJR(OP, 13) RD_GJR(OP, 14) RD_GJR(OP, 15) "s_nop 1"
+#define RD_GJR_S12(OP) "s_nop 1\n\t" RD_GJR(OP, 0) RD_GJR(OP, 1) RD_GJR(OP, 2) RD_GJR(OP, 3) RD_GJR(OP, 4) RD_GJR(OP, 5) RD_GJR(OP, 6) RD_GJR(OP, 7) RD_GJR(OP, 8) RD_GJR(OP, 9) RD_GJR(OP, 10) RD_GJR(OP, 11) RD_GJR(OP, 13) RD_GJR(OP, 14) RD_GJR(OP, 15) "s_nop 1"
+#define RD_GJR_S13(OP) "s_nop 1\n\t" RD_GJR(OP, 0) RD_GJR(OP, 1) RD_GJR(OP, 2) RD_GJR(OP, 3) RD_GJR(OP, 4) RD_GJR(OP, 5) RD_GJR(OP, 6) RD_GJR(OP, 7) RD_GJR(OP, 8) RD_GJR(OP, 9) RD_GJR(OP, 10) RD_GJR(OP, 11) RD_GJR(OP, 12) RD_GJR(OP, 14) RD_GJR(OP, 15) "s_nop 1"
+#define RD_GJR_S14(OP) "s_nop 1\n\t" RD_GJR(OP, 0) RD_GJR(OP, 1) RD_GJR(OP, 2) RD_GJR(OP, 3) RD_GJR(OP, 4) RD_GJR(OP, 5) RD_GJR(OP, 6) RD_GJR(OP, 7) RD_GJR(OP, 8) RD_GJR(OP, 9) RD_GJR(OP, 10) RD_GJR(OP, 11) RD_GJR(OP, 12) RD_GJR(OP, 13) RD_GJR(OP, 15) "s_nop 1"
+#define RD_GJR_S15(OP) "s_nop 1\n\t" RD_GJR(OP, 0) RD_GJR(OP, 1) RD_GJR(OP, 2) RD_GJR(OP, 3) RD_GJR(OP, 4) RD_GJR(OP, 5) RD_GJR(OP, 6) RD_GJR(OP, 7) RD_GJR(OP, 8) RD_GJR(OP, 9) RD_GJR(OP, 10) RD_GJR(OP, 11) RD_GJR(OP, 12) RD_GJR(OP, 13) RD_GJR(OP, 14) "s_nop 1"
 template <int KK, typename T>
 __device__ __forceinline__ void fused_gj_real_k(T (&a)[16], T f) {
-    RD_ASM2(T, RD_GJR_BODY,
-            : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]), "+v"(a[6]),
-              "+v"(a[7]), "+v"(a[8]), "+v"(a[9]), "+v"(a[10]), "+v"(a[11]), "+v"(a[12]),
-              "+v"(a[13]), "+v"(a[14]), "+v"(a[15])
-            : "v"(f), "n"(KK));
+#define OPERANDS                                                                                  \
+    : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]), "+v"(a[6]),        \
+      "+v"(a[7]), "+v"(a[8]), "+v"(a[9]), "+v"(a[10]), "+v"(a[11]), "+v"(a[12]), "+v"(a[13]),     \
+      "+v"(a[14]), "+v"(a[15])                                                                    \
+    : "v"(f), "n"(KK)
+    if constexpr (KK == 0) RD_ASM2(T, RD_GJR_S0, OPERANDS);
+    else if constexpr (KK == 1) RD_ASM2(T, RD_GJR_S1, OPERANDS);
+    else if constexpr (KK == 2) RD_ASM2(T, RD_GJR_S2, OPERANDS);
+    else if constexpr (KK == 3) RD_ASM2(T, RD_GJR_S3, OPERANDS);
+    else if constexpr (KK == 4) RD_ASM2(T, RD_GJR_S4, OPERANDS);
+    else if constexpr (KK == 5) RD_ASM2(T, RD_GJR_S5, OPERANDS);
+    else if constexpr (KK == 6) RD_ASM2(T, RD_GJR_S6, OPERANDS);
+    else if constexpr (KK == 7) RD_ASM2(T, RD_GJR_S7, OPERANDS);
+    else if constexpr (KK == 8) RD_ASM2(T, RD_GJR_S8, OPERANDS);
+    else if constexpr (KK == 9) RD_ASM2(T, RD_GJR_S9, OPERANDS);
+    else if constexpr (KK == 10) RD_ASM2(T, RD_GJR_S10, OPERANDS);
+    else if constexpr (KK == 11) RD_ASM2(T, RD_GJR_S11, OPERANDS);
+    else if constexpr (KK == 12) RD_ASM2(T, RD_GJR_S12, OPERANDS);
+    else if constexpr (KK == 13) RD_ASM2(T, RD_GJR_S13, OPERANDS);
+    else if constexpr (KK == 14) RD_ASM2(T, RD_GJR_S14, OPERANDS);
+    else if constexpr (KK == 15) RD_ASM2(T, RD_GJR_S15, OPERANDS);
+#undef OPERANDS
 }
-#undef RD_GJR_BODY
+#undef RD_GJR_S0
+#undef RD_GJR_S1
+#undef RD_GJR_S2
+#undef RD_GJR_S3
+#undef RD_GJR_S4
+#undef RD_GJR_S5
+#undef RD_GJR_S6
+#undef RD_GJR_S7
+#undef RD_GJR_S8
+#undef RD_GJR_S9
+#undef RD_GJR_S10
+#undef RD_GJR_S11
+#undef RD_GJR_S12
+#undef RD_GJR_S13
+#undef RD_GJR_S14
+#undef RD_GJR_S15
 #undef RD_GJR
 
 /* The same step for the 8-column engine (m <= 8). */
 #define RD_GJR8(OP, J) OP " %" #J ", %" #J ", -%8 row_newbcast:%9 row_mask:0xf bank_mask:0xf\n\t"
-#define RD_GJR8_BODY(OP)                                                                          \
-    "s_nop 1\n\t"                                                                                 \
-    RD_GJR8(OP, 0) RD_GJR8(OP, 1) RD_GJR8(OP, 2) RD_GJR8(OP, 3) RD_GJR8(OP, 4) RD_GJR8(OP, 5)     \
-    RD_GJR8(OP, 6) RD_GJR8(OP, 7) "s_nop 1"
+#define RD_GJR8_S0(OP) "s_nop 1\n\t" RD_GJR8(OP, 1) RD_GJR8(OP, 2) RD_GJR8(OP, 3) RD_GJR8(OP, 4) RD_GJR8(OP, 5) RD_GJR8(OP, 6) RD_GJR8(OP, 7) "s_nop 1"
+#define RD_GJR8_S1(OP) "s_nop 1\n\t" RD_GJR8(OP, 0) RD_GJR8(OP, 2) RD_GJR8(OP, 3) RD_GJR8(OP, 4) RD_GJR8(OP, 5) RD_GJR8(OP, 6) RD_GJR8(OP, 7) "s_nop 1"
+#define RD_GJR8_S2(OP) "s_nop 1\n\t" RD_GJR8(OP, 0) RD_GJR8(OP, 1) RD_GJR8(OP, 3) RD_GJR8(OP, 4) RD_GJR8(OP, 5) RD_GJR8(OP, 6) RD_GJR8(OP, 7) "s_nop 1"
+#define RD_GJR8_S3(OP) "s_nop 1\n\t" RD_GJR8(OP, 0) RD_GJR8(OP, 1) RD_GJR8(OP, 2) RD_GJR8(OP, 4) RD_GJR8(OP, 5) RD_GJR8(OP, 6) RD_GJR8(OP, 7) "s_nop 1"
+#define RD_GJR8_S4(OP) "s_nop 1\n\t" RD_GJR8(OP, 0) RD_GJR8(OP, 1) RD_GJR8(OP, 2) RD_GJR8(OP, 3) RD_GJR8(OP, 5) RD_GJR8(OP, 6) RD_GJR8(OP, 7) "s_nop 1"
+#define RD_GJR8_S5(OP) "s_nop 1\n\t" RD_GJR8(OP, 0) RD_GJR8(OP, 1) RD_GJR8(OP, 2) RD_GJR8(OP, 3) RD_GJR8(OP, 4) RD_GJR8(OP, 6) RD_GJR8(OP, 7) "s_nop 1"
+#define RD_GJR8_S6(OP) "s_nop 1\n\t" RD_GJR8(OP, 0) RD_GJR8(OP, 1) RD_GJR8(OP, 2) RD_GJR8(OP, 3) RD_GJR8(OP, 4) RD_GJR8(OP, 5) RD_GJR8(OP, 7) "s_nop 1"
+#define RD_GJR8_S7(OP) "s_nop 1\n\t" RD_GJR8(OP, 0) RD_GJR8(OP, 1) RD_GJR8(OP, 2) RD_GJR8(OP, 3) RD_GJR8(OP, 4) RD_GJR8(OP, 5) RD_GJR8(OP, 6) "s_nop 1"
 template <int KK, typename T>
 __device__ __forceinline__ void fused_gj_real8_k(T (&a)[8], T f) {
-    RD_ASM2(T, RD_GJR8_BODY,
-            : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]), "+v"(a[6]),
-              "+v"(a[7])
-            : "v"(f), "n"(KK));
+#define OPERANDS                                                                                  \
+    : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]), "+v"(a[6]),        \
+      "+v"(a[7])                                                                                  \
+    : "v"(f), "n"(KK)
+    if constexpr (KK == 0) RD_ASM2(T, RD_GJR8_S0, OPERANDS);
+    else if constexpr (KK == 1) RD_ASM2(T, RD_GJR8_S1, OPERANDS);
+    else if constexpr (KK == 2) RD_ASM2(T, RD_GJR8_S2, OPERANDS);
+    else if constexpr (KK == 3) RD_ASM2(T, RD_GJR8_S3, OPERANDS);
+    else if constexpr (KK == 4) RD_ASM2(T, RD_GJR8_S4, OPERANDS);
+    else if constexpr (KK == 5) RD_ASM2(T, RD_GJR8_S5, OPERANDS);
+    else if constexpr (KK == 6) RD_ASM2(T, RD_GJR8_S6, OPERANDS);
+    else if constexpr (KK == 7) RD_ASM2(T, RD_GJR8_S7, OPERANDS);
+#undef OPERANDS
 }
-#undef RD_GJR8_BODY
+#undef RD_GJR8_S0
+#undef RD_GJR8_S1
+#undef RD_GJR8_S2
+#undef RD_GJR8_S3
+#undef RD_GJR8_S4
+#undef RD_GJR8_S5
+#undef RD_GJR8_S6
+#undef RD_GJR8_S7
 #undef RD_GJR8
 
 /* Gauss-Jordan elimination step with pivot lane KK (complex), for every
- * column j, with (ur, ui) the pivot row's entry of column j:
+ * column j != KK, with (ur, ui) the pivot row's entry of column j:
  *   ar[j] = (ar[j] + ui fi) - ur fr,   ai[j] = (ai[j] - ur fi) - ui fr.
  * Issued in four sweeps over the columns (ar += ui fi; ai -= ur fi;
  * ar -= ur fr; ai -= ui fr), so that a register written in one sweep is read
- * through DPP sixteen or more instructions later.  The sweeps read the pivot
+ * through DPP fifteen or more instructions later.  The sweeps read the pivot
  * lane's entries after the pivot lane has applied the earlier sweeps to
  * them, which add x * (+-0) there (fr = fi = 0 in the pivot lane): the
- * values read equal those of the plain order (a zero may change its sign). */
+ * values read equal those of the plain order (a zero may change its sign).
+ * Column KK is overwritten by the caller afterwards; one body per pivot
+ * column, generated. */
 #define RD_GJA(OP, R, I) OP " %" #R ", %" #I ", %33 row_newbcast:%34 row_mask:0xf bank_mask:0xf\n\t"
 #define RD_GJB(OP, R, I) OP " %" #I ", %" #R ", -%33 row_newbcast:%34 row_mask:0xf bank_mask:0xf\n\t"
 #define RD_GJC(OP, R, I) OP " %" #R ", %" #R ", -%32 row_newbcast:%34 row_mask:0xf bank_mask:0xf\n\t"
 #define RD_GJD(OP, R, I) OP " %" #I ", %" #I ", -%32 row_newbcast:%34 row_mask:0xf bank_mask:0xf\n\t"
-#define RD_SWEEP(S, OP)                                                                           \
-    S(OP, 0, 16) S(OP, 1, 17) S(OP, 2, 18) S(OP, 3, 19) S(OP, 4, 20) S(OP, 5, 21) S(OP, 6, 22)    \
-    S(OP, 7, 23) S(OP, 8, 24) S(OP, 9, 25) S(OP, 10, 26) S(OP, 11, 27) S(OP, 12, 28)              \
-    S(OP, 13, 29) S(OP, 14, 30) S(OP, 15, 31)
-#define RD_GJC_BODY(OP)                                                                           \
-    "s_nop 1\n\t" RD_SWEEP(RD_GJA, OP) RD_SWEEP(RD_GJB, OP) RD_SWEEP(RD_GJC, OP)                  \
-    RD_SWEEP(RD_GJD, OP) "s_nop 1"
+#define RD_GJC_S0(OP) "s_nop 1\n\t" RD_GJA(OP, 1, 17) RD_GJA(OP, 2, 18) RD_GJA(OP, 3, 19) RD_GJA(OP, 4, 20) RD_GJA(OP, 5, 21) RD_GJA(OP, 6, 22) RD_GJA(OP, 7, 23) RD_GJA(OP, 8, 24) RD_GJA(OP, 9, 25) RD_GJA(OP, 10, 26) RD_GJA(OP, 11, 27) RD_GJA(OP, 12, 28) RD_GJA(OP, 13, 29) RD_GJA(OP, 14, 30) RD_GJA(OP, 15, 31) RD_GJB(OP, 1, 17) RD_GJB(OP, 2, 18) RD_GJB(OP, 3, 19) RD_GJB(OP, 4, 20) RD_GJB(OP, 5, 21) RD_GJB(OP, 6, 22) RD_GJB(OP, 7, 23) RD_GJB(OP, 8, 24) RD_GJB(OP, 9, 25) RD_GJB(OP, 10, 26) RD_GJB(OP, 11, 27) RD_GJB(OP, 12, 28) RD_GJB(OP, 13, 29) RD_GJB(OP, 14, 30) RD_GJB(OP, 15, 31) RD_GJC(OP, 1, 17) RD_GJC(OP, 2, 18) RD_GJC(OP, 3, 19) RD_GJC(OP, 4, 20) RD_GJC(OP, 5, 21) RD_GJC(OP, 6, 22) RD_GJC(OP, 7, 23) RD_GJC(OP, 8, 24) RD_GJC(OP, 9, 25) RD_GJC(OP, 10, 26) RD_GJC(OP, 11, 27) RD_GJC(OP, 12, 28) RD_GJC(OP, 13, 29) RD_GJC(OP, 14, 30) RD_GJC(OP, 15, 31) RD_GJD(OP, 1, 17) RD_GJD(OP, 2, 18) RD_GJD(OP, 3, 19) RD_GJD(OP, 4, 20) RD_GJD(OP, 5, 21) RD_GJD(OP, 6, 22) RD_GJD(OP, 7, 23) RD_GJD(OP, 8, 24) RD_GJD(OP, 9, 25) RD_GJD(OP, 10, 26) RD_GJD(OP, 11, 27) RD_GJD(OP, 12, 28) RD_GJD(OP, 13, 29) RD_GJD(OP, 14, 30) RD_GJD(OP, 15, 31) "s_nop 1"
+#define RD_GJC_S1(OP) "s_nop 1\n\t" RD_GJA(OP, 0, 16) RD_GJA(OP, 2, 18) RD_GJA(OP, 3, 19) RD_GJA(OP, 4, 20) RD_GJA(OP, 5, 21) RD_GJA(OP, 6, 22) RD_GJA(OP, 7, 23) RD_GJA(OP, 8, 24) RD_GJA(OP, 9, 25) RD_GJA(OP, 10, 26) RD_GJA(OP, 11, 27) RD_GJA(OP, 12, 28) RD_GJA(OP, 13, 29) RD_GJA(OP, 14, 30) RD_GJA(OP, 15, 31) RD_GJB(OP, 0, 16) RD_GJB(OP, 2, 18) RD_GJB(OP, 3, 19) RD_GJB(OP, 4, 20) RD_GJB(OP, 5, 21) RD_GJB(OP, 6, 22) RD_GJB(OP, 7, 23) RD_GJB(OP, 8, 24) RD_GJB(OP, 9, 25) RD_GJB(OP, 10, 26) RD_GJB(OP, 11, 27) RD_GJB(OP, 12, 28) RD_GJB(OP, 13, 29) RD_GJB(OP, 14, 30) RD_GJB(OP, 15, 31) RD_GJC(OP, 0, 16) RD_GJC(OP, 2, 18) RD_GJC(OP, 3, 19) RD_GJC(OP, 4, 20) RD_GJC(OP, 5, 21) RD_GJC(OP, 6, 22) RD_GJC(OP, 7, 23) RD_GJC(OP, 8, 24) RD_GJC(OP, 9, 25) RD_GJC(OP, 10, 26) RD_GJC(OP, 11, 27) RD_GJC(OP, 12, 28) RD_GJC(OP, 13, 29) RD_GJC(OP, 14, 30) RD_GJC(OP, 15, 31) RD_GJD(OP, 0, 16) RD_GJD(OP, 2, 18) RD_GJD(OP, 3, 19) RD_GJD(OP, 4, 20) RD_GJD(OP, 5, 21) RD_GJD(OP, 6, 22) RD_GJD(OP, 7, 23) RD_GJD(OP, 8, 24) RD_GJD(OP, 9, 25) RD_GJD(OP, 10, 26) RD_GJD(OP, 11, 27) RD_GJD(OP, 12, 28) RD_GJD(OP, 13, 29) RD_GJD(OP, 14, 30) RD_GJD(OP, 15, 31) "s_nop 1"
+#define RD_GJC_S2(OP) "s_nop 1\n\t" RD_GJA(OP, 0, 16) RD_GJA(OP, 1, 17) RD_GJA(OP, 3, 19) RD_GJA(OP, 4, 20) RD_GJA(OP, 5, 21) RD_GJA(OP, 6, 22) RD_GJA(OP, 7, 23) RD_GJA(OP, 8, 24) RD_GJA(OP, 9, 25) RD_GJA(OP, 10, 26) RD_GJA(OP, 11, 27) RD_GJA(OP, 12, 28) RD_GJA(OP, 13, 29) RD_GJA(OP, 14, 30) RD_GJA(OP, 15, 31) RD_GJB(OP, 0, 16) RD_GJB(OP, 1, 17) RD_GJB(OP, 3, 19) RD_GJB(OP, 4, 20) RD_GJB(OP, 5, 21) RD_GJB(OP, 6, 22) RD_GJB(OP, 7, 23) RD_GJB(OP, 8, 24) RD_GJB(OP, 9, 25) RD_GJB(OP, 10, 26) RD_GJB(OP, 11, 27) RD_GJB(OP, 12, 28) RD_GJB(OP, 13, 29) RD_GJB(OP, 14, 30) RD_GJB(OP, 15, 31) RD_GJC(OP, 0, 16) RD_GJC(OP, 1, 17) RD_GJC(OP, 3, 19) RD_GJC(OP, 4, 20) RD_GJC(OP, 5, 21) RD_GJC(OP, 6, 22) RD_GJC(OP, 7, 23) RD_GJC(OP, 8, 24) RD_GJC(OP, 9, 25) RD_GJC(OP, 10, 26) RD_GJC(OP, 11, 27) RD_GJC(OP, 12, 28) RD_GJC(OP, 13, 29) RD_GJC(OP, 14, 30) RD_GJC(OP, 15, 31) RD_GJD(OP, 0, 16) RD_GJD(OP, 1, 17) RD_GJD(OP, 3, 19) RD_GJD(OP, 4, 20) RD_GJD(OP, 5, 21) RD_GJD(OP, 6, 22) RD_GJD(OP, 7, 23) RD_GJD(OP, 8, 24) RD_GJD(OP, 9, 25) RD_GJD(OP, 10, 26) RD_GJD(OP, 11, 27) RD_GJD(OP, 12, 28) RD_GJD(OP, 13, 29) RD_GJD(OP, 14, 30) RD_GJD(OP, 15, 31) "s_nop 1"
+#define RD_GJC_S3(OP) "s_nop 1\n\t" RD_GJA(OP, 0, 16) RD_GJA(OP, 1, 17) RD_GJA(OP, 2, 18) RD_GJA(OP, 4, 20) RD_GJA(OP, 5, 21) RD_GJA(OP, 6, 22) RD_GJA(OP, 7, 23) RD_GJA(OP, 8, 24) RD_GJA(OP, 9, 25) RD_GJA(OP, 10, 26) RD_GJA(OP, 11, 27) RD_GJA(OP, 12, 28) RD_GJA(OP, 13, 29) RD_GJA(OP, 14, 30) RD_GJA(OP, 15, 31) RD_GJB(OP, 0, 16) RD_GJB(OP, 1, 17) RD_GJB(OP, 2, 18) RD_GJB(OP, 4, 20) RD_GJB(OP, 5, 21) RD_GJB(OP, 6, 22) RD_GJB(OP, 7, 23) RD_GJB(OP, 8, 24) RD_GJB(OP, 9, 25) RD_GJB(OP, 10, 26) RD_GJB(OP, 11, 27) RD_GJB(OP, 12, 28) RD_GJB(OP, 13, 29) RD_GJB(OP, 14, 30) RD_GJB(OP, 15, 31) RD_GJC(OP, 0, 16) RD_GJC(OP, 1, 17) RD_GJC(OP, 2, 18) RD_GJC(OP, 4, 20) RD_GJC(OP, 5, 21) RD_GJC(OP, 6, 22) RD_GJC(OP, 7, 23) RD_GJC(OP, 8, 24) RD_GJC(OP, 9, 25) RD_GJC(OP, 10, 26) RD_GJC(OP, 11, 27) RD_GJC(OP, 12, 28) RD_GJC(OP, 13, 29) RD_GJC(OP, 14, 30) RD_GJC(OP, 15, 31) RD_GJD(OP, 0, 16) RD_GJD(OP, 1, 17) RD_GJD(OP, 2, 18) RD_GJD(OP, 4, 20) RD_GJD(OP, 5, 21) RD_GJD(OP, 6, 22) RD_GJD(OP, 7, 23) RD_GJD(OP, 8, 24) RD_GJD(OP, 9, 25) RD_GJD(OP, 10, 26) RD_GJD(OP, 11, 27) RD_GJD(OP, 12, 28) RD_GJD(OP, 13, 29) RD_GJD(OP, 14, 30) RD_GJD(OP, 15, 31) "s_nop 1"
+#define RD_GJC_S4(OP) "s_nop 1\n\t" RD_GJA(OP, 0, 16) RD_GJA(OP, 1, 17) RD_GJA(OP, 2, 18) RD_GJA(OP, 3, 19) RD_GJA(OP, 5, 21) RD_GJA(OP, 6, 22) RD_GJA(OP, 7, 23) RD_GJA(OP, 8, 24) RD_GJA(OP, 9, 25) RD_GJA(OP, 10, 26) RD_GJA(OP, 11, 27) RD_GJA(OP, 12, 28) RD_GJA(OP, 13, 29) RD_GJA(OP, 14, 30) RD_GJA(OP, 15, 31) RD_GJB(OP, 0, 16) RD_GJB(OP, 1, 17) RD_GJB(OP, 2, 18) RD_GJB(OP, 3, 19) RD_GJB(OP, 5, 21) RD_GJB(OP, 6, 22) RD_GJB(OP, 7, 23) RD_GJB(OP, 8, 24) RD_GJB(OP, 9, 25) RD_GJB(OP, 10, 26) RD_GJB(OP, 11, 27) RD_GJB(OP, 12, 28) RD_GJB(OP, 13, 29) RD_GJB(OP, 14, 30) RD_GJB(OP, 15, 31) RD_GJC(OP, 0, 16) RD_GJC(OP, 1, 17) RD_GJC(OP, 2, 18) RD_GJC(OP, 3, 19) RD_GJC(OP, 5, 21) RD_GJC(OP, 6, 22) RD_GJC(OP, 7, 23) RD_GJC(OP, 8, 24) RD_GJC(OP, 9, 25) RD_GJC(OP, 10, 26) RD_GJC(OP, 11, 27) RD_GJC(OP, 12, 28) RD_GJC(OP, 13, 29) RD_GJC(OP, 14, 30) RD_GJC(OP, 15, 31) RD_GJD(OP, 0, 16) RD_GJD(OP, 1, 17) RD_GJD(OP, 2, 18) RD_GJD(OP, 3, 19) RD_GJD(OP, 5, 21) RD_GJD(OP, 6, 22) RD_GJD(OP, 7, 23) RD_GJD(OP, 8, 24) RD_GJD(OP, 9, 25) RD_GJD(OP, 10, 26) RD_GJD(OP, 11, 27) RD_GJD(OP, 12, 28) RD_GJD(OP, 13, 29) RD_GJD(OP, 14, 30) RD_GJD(OP, 15, 31) "s_nop 1"
+#define RD_GJC_S5(OP) "s_nop 1\n\t" RD_GJA(OP, 0, 16) RD_GJA(OP, 1, 17) RD_GJA(OP, 2, 18) RD_GJA(OP, 3, 19) RD_GJA(OP, 4, 20) RD_GJA(OP, 6, 22) RD_GJA(OP, 7, 23) RD_GJA(OP, 8, 24) RD_GJA(OP, 9, 25) RD_GJA(OP, 10, 26) RD_GJA(OP, 11, 27) RD_GJA(OP, 12, 28) RD_GJA(OP, 13, 29) RD_GJA(OP, 14, 30) RD_GJA(OP, 15, 31) RD_GJB(OP, 0, 16) RD_GJB(OP, 1, 17) RD_GJB(OP, 2, 18) RD_GJB(OP, 3, 19) RD_GJB(OP, 4, 20) RD_GJB(OP, 6, 22) RD_GJB(OP, 7, 23) RD_GJB(OP, 8, 24) RD_GJB(OP, 9, 25) RD_GJB(OP, 10, 26) RD_GJB(OP, 11, 27) RD_GJB(OP, 12, 28) RD_GJB(OP, 13, 29) RD_GJB(OP, 14, 30) RD_GJB(OP, 15, 31) RD_GJC(OP, 0, 16) RD_GJC(OP, 1, 17) RD_GJC(OP, 2, 18) RD_GJC(OP, 3, 19) RD_GJC(OP, 4, 20) RD_GJC(OP, 6, 22) RD_GJC(OP, 7, 23) RD_GJC(OP, 8, 24) RD_GJC(OP, 9, 25) RD_GJC(OP, 10, 26) RD_GJC(OP, 11, 27) RD_GJC(OP, 12, 28) RD_GJC(OP, 13, 29) RD_GJC(OP, 14, 30) RD_GJC(OP, 15, 31) RD_GJD(OP, 0, 16) RD_GJD(OP, 1, 17) RD_GJD(OP, 2, 18) RD_GJD(OP, 3, 19) RD_GJD(OP, 4, 20) RD_GJD(OP, 6, 22) RD_GJD(OP, 7, 23) RD_GJD(OP, 8, 24) RD_GJD(OP, 9, 25) RD_GJD(OP, 10, 26) RD_GJD(OP, 11, 27) RD_GJD(OP, 12, 28) RD_GJD(OP, 13, 29) RD_GJD(OP, 14, 30) RD_GJD(OP, 15, 31) "s_nop 1"
+#define RD_GJC_S6(OP) "s_nop 1\n\t" RD_GJA(OP, 0, 16) RD_GJA(OP, 1, 17) RD_GJA(OP, 2, 18) RD_GJA(OP, 3, 19) RD_GJA(OP, 4, 20) RD_GJA(OP, 5, 21) RD_GJA(OP, 7, 23) RD_GJA(OP, 8, 24) RD_GJA(OP, 9, 25) RD_GJA(OP, 10, 26) RD_GJA(OP, 11, 27) RD_GJA(OP, 12, 28) RD_GJA(OP, 13, 29) RD_GJA(OP, 14, 30) RD_GJA(OP, 15, 31) RD_GJB(OP, 0, 16) RD_GJB(OP, 1, 17) RD_GJB(OP, 2, 18) RD_GJB(OP, 3, 19) RD_GJB(OP, 4, 20) RD_GJB(OP, 5, 21) RD_GJB(OP, 7, 23) RD_GJB(OP, 8, 24) RD_GJB(OP, 9, 25) RD_GJB(OP, 10, 26) RD_GJB(OP, 11, 27) RD_GJB(OP, 12, 28) RD_GJB(OP, 13, 29) RD_GJB(OP, 14, 30) RD_GJB(OP, 15, 31) RD_GJC(OP, 0, 16) RD_GJC(OP, 1, 17) RD_GJC(OP, 2, 18) RD_GJC(OP, 3, 19) RD_GJC(OP, 4, 20) RD_GJC(OP, 5, 21) RD_GJC(OP, 7, 23) RD_GJC(OP, 8, 24) RD_GJC(OP, 9, 25) RD_GJC(OP, 10, 26) RD_GJC(OP, 11, 27) RD_GJC(OP, 12, 28) RD_GJC(OP, 13, 29) RD_GJC(OP, 14, 30) RD_GJC(OP, 15, 31) RD_GJD(OP, 0, 16) RD_GJD(OP, 1, 17) RD_GJD(OP, 2, 18) RD_GJD(OP, 3, 19) RD_GJD(OP, 4, 20) RD_GJD(OP, 5, 21) RD_GJD(OP, 7, 23) RD_GJD(OP, 8, 24) RD_GJD(OP, 9, 25) RD_GJD(OP, 10, 26) RD_GJD(OP, 11, 27) RD_GJD(OP, 12, 28) RD_GJD(OP, 13, 29) RD_GJD(OP, 14, 30) RD_GJD(OP, 15, 31) "s_nop 1"
+#define RD_GJC_S7(OP) "s_nop 1\n\t" RD_GJA(OP, 0, 16) RD_GJA(OP, 1, 17) RD_GJA(OP, 2, 18) RD_GJA(OP, 3, 19) RD_GJA(OP, 4, 20) RD_GJA(OP, 5, 21) RD_GJA(OP, 6, 22) RD_GJA(OP, 8, 24) RD_GJA(OP, 9, 25) RD_GJA(OP, 10, 26) RD_GJA(OP, 11, 27) RD_GJA(OP, 12, 28) RD_GJA(OP, 13, 29) RD_GJA(OP, 14, 30) RD_GJA(OP, 15, 31) RD_GJB(OP, 0, 16) RD_GJB(OP, 1, 17) RD_GJB(OP, 2, 18) RD_GJB(OP, 3, 19) RD_GJB(OP, 4, 20) RD_GJB(OP, 5, 21) RD_GJB(OP, 6, 22) RD_GJB(OP, 8, 24) RD_GJB(OP, 9, 25) RD_GJB(OP, 10, 26) RD_GJB(OP, 11, 27) RD_GJB(OP, 12, 28) RD_GJB(OP, 13, 29) RD_GJB(OP, 14, 30) RD_GJB(OP, 15, 31) RD_GJC(OP, 0, 16) RD_GJC(OP, 1, 17) RD_GJC(OP, 2, 18) RD_GJC(OP, 3, 19) RD_GJC(OP, 4, 20) RD_GJC(OP, 5, 21) RD_GJC(OP, 6, 22) RD_GJC(OP, 8, 24) RD_GJC(OP, 9, 25) RD_GJC(OP, 10, 26) RD_GJC(OP, 11, 27) RD_GJC(OP, 12, 28) RD_GJC(OP, 13, 29) RD_GJC(OP, 14, 30) RD_GJC(OP, 15, 31) RD_GJD(OP, 0, 16) RD_GJD(OP, 1, 17) RD_GJD(OP, 2, 18) RD_GJD(OP, 3, 19) RD_GJD(OP, 4, 20) RD_GJD(OP, 5, 21) RD_GJD(OP, 6, 22) RD_GJD(OP, 8, 24) RD_GJD(OP, 9, 25) RD_GJD(OP, 10, 26) RD_GJD(OP, 11, 27) RD_GJD(OP, 12, 28) RD_GJD(OP, 13, 29) RD_GJD(OP, 14, 30) RD_GJD(OP, 15, 31) "s_nop 1"
+#define RD_GJC_S8(OP) "s_nop 1\n\t" RD_GJA(OP, 0, 16) RD_GJA(OP, 1, 17) RD_GJA(OP, 2, 18) RD_GJA(OP, 3, 19) RD_GJA(OP, 4, 20) RD_GJA(OP, 5, 21) RD_GJA(OP, 6, 22) RD_GJA(OP, 7, 23) RD_GJA(OP, 9, 25) RD_GJA(OP, 10, 26) RD_GJA(OP, 11, 27) RD_GJA(OP, 12, 28) RD_GJA(OP, 13, 29) RD_GJA(OP, 14, 30) RD_GJA(OP, 15, 31) RD_GJB(OP, 0, 16) RD_GJB(OP, 1, 17) RD_GJB(OP, 2, 18) RD_GJB(OP, 3, 19) RD_GJB(OP, 4, 20) RD_GJB(OP, 5, 21) RD_GJB(OP, 6, 22) RD_GJB(OP, 7, 23) RD_GJB(OP, 9, 25) RD_GJB(OP, 10, 26) RD_GJB(OP, 11, 27) RD_GJB(OP, 12, 28) RD_GJB(OP, 13, 29) RD_GJB(OP, 14, 30) RD_GJB(OP, 15, 31) RD_GJC(OP, 0, 16) RD_GJC(OP, 1, 17) RD_GJC(OP, 2, 18) RD_GJC(OP, 3, 19) RD_GJC(OP, 4, 20) RD_GJC(OP, 5, 21) RD_GJC(OP, 6, 22) RD_GJC(OP, 7, 23) RD_GJC(OP, 9, 25) RD_GJC(OP, 10, 26) RD_GJC(OP, 11, 27) RD_GJC(OP, 12, 28) RD_GJC(OP, 13, 29) RD_GJC(OP, 14, 30) RD_GJC(OP, 15, 31) RD_GJD(OP, 0, 16) RD_GJD(OP, 1, 17) RD_GJD(OP, 2, 18) RD_GJD(OP, 3, 19) RD_GJD(OP, 4, 20) RD_GJD(OP, 5, 21) RD_GJD(OP, 6, 22) RD_GJD(OP, 7, 23) RD_GJD(OP, 9, 25) RD_GJD(OP, 10, 26) RD_GJD(OP, 11, 27) RD_GJD(OP, 12, 28) RD_GJD(OP, 13, 29) RD_GJD(OP, 14, 30) RD_GJD(OP, 15, 31) "s_nop 1"
+#define RD_GJC_S9(OP) "s_nop 1\n\t" RD_GJA(OP, 0, 16) RD_GJA(OP, 1, 17) RD_GJA(OP, 2, 18) RD_GJA(OP, 3, 19) RD_GJA(OP, 4, 20) RD_GJA(OP, 5, 21) RD_GJA(OP, 6, 22) RD_GJA(OP, 7, 23) RD_GJA(OP, 8, 24) RD_GJA(OP, 10, 26) RD_GJA(OP, 11, 27) RD_GJA(OP, 12, 28) RD_GJA(OP, 13, 29) RD_GJA(OP, 14, 30) RD_GJA(OP, 15, 31) RD_GJB(OP, 0, 16) RD_GJB(OP, 1, 17) RD_GJB(OP, 2, 18) RD_GJB(OP, 3, 19) RD_GJB(OP, 4, 20) RD_GJB(OP, 5, 21) RD_GJB(OP, 6, 22) RD_GJB(OP, 7, 23) RD_GJB(OP, 8, 24) RD_GJB(OP, 10, 26) RD_GJB(OP, 11, 27) RD_GJB(OP, 12, 28) RD_GJB(OP, 13, 29) RD_GJB(OP, 14, 30) RD_GJB(OP, 15, 31) RD_GJC(OP, 0, 16) RD_GJC(OP, 1, 17) RD_GJC(OP, 2, 18) RD_GJC(OP, 3, 19) RD_GJC(OP, 4, 20) RD_GJC(OP, 5, 21) RD_GJC(OP, 6, 22) RD_GJC(OP, 7, 23) RD_GJC(OP, 8, 24) RD_GJC(OP, 10, 26) RD_GJC(OP, 11, 27) RD_GJC(OP, 12, 28) RD_GJC(OP, 13, 29) RD_GJC(OP, 14, 30) RD_GJC(OP, 15, 31) RD_GJD(OP, 0, 16) RD_GJD(OP, 1, 17) RD_GJD(OP, 2, 18) RD_GJD(OP, 3, 19) RD_GJD(OP, 4, 20) RD_GJD(OP, 5, 21) RD_GJD(OP, 6, 22) RD_GJD(OP, 7, 23) RD_GJD(OP, 8, 24) RD_GJD(OP, 10, 26) RD_GJD(OP, 11, 27) RD_GJD(OP, 12, 28) RD_GJD(OP, 13, 29) RD_GJD(OP, 14, 30) RD_GJD(OP, 15, 31) "s_nop 1"
+#define RD_GJC_S10(OP) "s_nop 1\n\t" RD_GJA(OP, 0, 16) RD_GJA(OP, 1, 17) RD_GJA(OP, 2, 18) RD_GJA(OP, 3, 19) RD_GJA(OP, 4, 20) RD_GJA(OP, 5, 21) RD_GJA(OP, 6, 22) RD_GJA(OP, 7, 23) RD_GJA(OP, 8, 24) RD_GJA(OP, 9, 25) RD_GJA(OP, 11, 27) RD_GJA(OP, 12, 28) RD_GJA(OP, 13, 29) RD_GJA(OP, 14, 30) RD_GJA(OP, 15, 31) RD_GJB(OP, 0, 16) RD_GJB(OP, 1, 17) RD_GJB(OP, 2, 18) RD_GJB(OP, 3, 19) RD_GJB(OP, 4, 20) RD_GJB(OP, 5, 21) RD_GJB(OP, 6, 22) RD_GJB(OP, 7, 23) RD_GJB(OP, 8, 24) RD_GJB(OP, 9, 25) RD_GJB(OP, 11, 27) RD_GJB(OP, 12, 28) RD_GJB(OP, 13, 29) RD_GJB(OP, 14, 30) RD_GJB(OP, 15, 31) RD_GJC(OP, 0, 16) RD_GJC(OP, 1, 17) RD_GJC(OP, 2, 18) RD_GJC(OP, 3, 19) RD_GJC(OP, 4, 20) RD_GJC(OP, 5, 21) RD_GJC(OP, 6, 22) RD_GJC(OP, 7, 23) RD_GJC(OP, 8, 24) RD_GJC(OP, 9, 25) RD_GJC(OP, 11, 27) RD_GJC(OP, 12, 28) RD_GJC(OP, 13, 29) RD_GJC(OP, 14, 30) RD_GJC(OP, 15, 31) RD_GJD(OP, 0, 16) RD_GJD(OP, 1, 17) RD_GJD(OP, 2, 18) RD_GJD(OP, 3, 19) RD_GJD(OP, 4, 20) RD_GJD(OP, 5, 21) RD_GJD(OP, 6, 22) RD_GJD(OP, 7, 23) RD_GJD(OP, 8, 24) RD_GJD(OP, 9, 25) RD_GJD(OP, 11, 27) RD_GJD(OP, 12, 28) RD_GJD(OP, 13, 29) RD_GJD(OP, 14, 30) RD_GJD(OP, 15, 31) "s_nop 1"
+#define RD_GJC_S11(OP) "s_nop 1\n\t" RD_GJA(OP, 0, 16) RD_GJA(OP, 1, 17) RD_GJA(OP, 2, 18) RD_GJA(OP, 3, 19) RD_GJA(OP, 4, 20) RD_GJA(OP, 5, 21) RD_GJA(OP, 6, 22) RD_GJA(OP, 7, 23) RD_GJA(OP, 8, 24) RD_GJA(OP, 9, 25) RD_GJA(OP, 10, 26) RD_GJA(OP, 12, 28) RD_GJA(OP, 13, 29) RD_GJA(OP, 14, 30) RD_GJA(OP, 15, 31) RD_GJB(OP, 0, 16) RD_GJB(OP, 1, 17) RD_GJB(OP, 2, 18) RD_GJB(OP, 3, 19) RD_GJB(OP, 4, 20) RD_GJB(OP, 5, 21) RD_GJB(OP, 6, 22) RD_GJB(OP, 7, 23) RD_GJB(OP, 8, 24) RD_GJB(OP, 9, 25) RD_GJB(OP, 10, 26) RD_GJB(OP, 12, 28) RD_GJB(OP, 13, 29) RD_GJB(OP, 14, 30) RD_GJB(OP, 15, 31) RD_GJC(OP, 0, 16) RD_GJC(OP, 1, 17) RD_GJC(OP, 2, 18) RD_GJC(OP, 3, 19) RD_GJC(OP, 4, 20) RD_GJC(OP, 5, 21) RD_GJC(OP, 6, 22) RD_GJC(OP, 7, 23) RD_GJC(OP, 8, 24) RD_GJC(OP, 9, 25) RD_GJC(OP, 10, 26) RD_GJC(OP, 12, 28) RD_GJC(OP, 13, 29) RD_GJC(OP, 14, 30) RD_GJC(OP, 15, 31) RD_GJD(OP, 0, 16) RD_GJD(OP, 1, 17) RD_GJD(OP, 2, 18) RD_GJD(OP, 3, 19) RD_GJD(OP, 4, 20) RD_GJD(OP, 5, 21) RD_GJD(OP, 6, 22) RD_GJD(OP, 7, 23) RD_GJD(OP, 8, 24) RD_GJD(OP, 9, 25) RD_GJD(OP, 10, 26) RD_GJD(OP, 12, 28) RD_GJD(OP, 13, 29) RD_GJD(OP, 14, 30) RD_GJD(OP, 15, 31) "s_nop 1"
+#define RD_GJC_S12(OP) "s_nop 1\n\t" RD_GJA(OP, 0, 16) RD_GJA(OP, 1, 17) RD_GJA(OP, 2, 18) RD_GJA(OP, 3, 19) RD_GJA(OP, 4, 20) RD_GJA(OP, 5, 21) RD_GJA(OP, 6, 22) RD_GJA(OP, 7, 23) RD_GJA(OP, 8, 24) RD_GJA(OP, 9, 25) RD_GJA(OP, 10, 26) RD_GJA(OP, 11, 27) RD_GJA(OP, 13, 29) RD_GJA(OP, 14, 30) RD_GJA(OP, 15, 31) RD_GJB(OP, 0, 16) RD_GJB(OP, 1, 17) RD_GJB(OP, 2, 18) RD_GJB(OP, 3, 19) RD_GJB(OP, 4, 20) RD_GJB(OP, 5, 21) RD_GJB(OP, 6, 22) RD_GJB(OP, 7, 23) RD_GJB(OP, 8, 24) RD_GJB(OP, 9, 25) RD_GJB(OP, 10, 26) RD_GJB(OP, 11, 27) RD_GJB(OP, 13, 29) RD_GJB(OP, 14, 30) RD_GJB(OP, 15, 31) RD_GJC(OP, 0, 16) RD_GJC(OP, 1, 17) RD_GJC(OP, 2, 18) RD_GJC(OP, 3, 19) RD_GJC(OP, 4, 20) RD_GJC(OP, 5, 21) RD_GJC(OP, 6, 22) RD_GJC(OP, 7, 23) RD_GJC(OP, 8, 24) RD_GJC(OP, 9, 25) RD_GJC(OP, 10, 26) RD_GJC(OP, 11, 27) RD_GJC(OP, 13, 29) RD_GJC(OP, 14, 30) RD_GJC(OP, 15, 31) RD_GJD(OP, 0, 16) RD_GJD(OP, 1, 17) RD_GJD(OP, 2, 18) RD_GJD(OP, 3, 19) RD_GJD(OP, 4, 20) RD_GJD(OP, 5, 21) RD_GJD(OP, 6, 22) RD_GJD(OP, 7, 23) RD_GJD(OP, 8, 24) RD_GJD(OP, 9, 25) RD_GJD(OP, 10, 26) RD_GJD(OP, 11, 27) RD_GJD(OP, 13, 29) RD_GJD(OP, 14, 30) RD_GJD(OP, 15, 31) "s_nop 1"
+#define RD_GJC_S13(OP) "s_nop 1\n\t" RD_GJA(OP, 0, 16) RD_GJA(OP, 1, 17) RD_GJA(OP, 2, 18) RD_GJA(OP, 3, 19) RD_GJA(OP, 4, 20) RD_GJA(OP, 5, 21) RD_GJA(OP, 6, 22) RD_GJA(OP, 7, 23) RD_GJA(OP, 8, 24) RD_GJA(OP, 9, 25) RD_GJA(OP, 10, 26) RD_GJA(OP, 11, 27) RD_GJA(OP, 12, 28) RD_GJA(OP, 14, 30) RD_GJA(OP, 15, 31) RD_GJB(OP, 0, 16) RD_GJB(OP, 1, 17) RD_GJB(OP, 2, 18) RD_GJB(OP, 3, 19) RD_GJB(OP, 4, 20) RD_GJB(OP, 5, 21) RD_GJB(OP, 6, 22) RD_GJB(OP, 7, 23) RD_GJB(OP, 8, 24) RD_GJB(OP, 9, 25) RD_GJB(OP, 10, 26) RD_GJB(OP, 11, 27) RD_GJB(OP, 12, 28) RD_GJB(OP, 14, 30) RD_GJB(OP, 15, 31) RD_GJC(OP, 0, 16) RD_GJC(OP, 1, 17) RD_GJC(OP, 2, 18) RD_GJC(OP, 3, 19) RD_GJC(OP, 4, 20) RD_GJC(OP, 5, 21) RD_GJC(OP, 6, 22) RD_GJC(OP, 7, 23) RD_GJC(OP, 8, 24) RD_GJC(OP, 9, 25) RD_GJC(OP, 10, 26) RD_GJC(OP, 11, 27) RD_GJC(OP, 12, 28) RD_GJC(OP, 14, 30) RD_GJC(OP, 15, 31) RD_GJD(OP, 0, 16) RD_GJD(OP, 1, 17) RD_GJD(OP, 2, 18) RD_GJD(OP, 3, 19) RD_GJD(OP, 4, 20) RD_GJD(OP, 5, 21) RD_GJD(OP, 6, 22) RD_GJD(OP, 7, 23) RD_GJD(OP, 8, 24) RD_GJD(OP, 9, 25) RD_GJD(OP, 10, 26) RD_GJD(OP, 11, 27) RD_GJD(OP, 12, 28) RD_GJD(OP, 14, 30) RD_GJD(OP, 15, 31) "s_nop 1"
+#define RD_GJC_S14(OP) "s_nop 1\n\t" RD_GJA(OP, 0, 16) RD_GJA(OP, 1, 17) RD_GJA(OP, 2, 18) RD_GJA(OP, 3, 19) RD_GJA(OP, 4, 20) RD_GJA(OP, 5, 21) RD_GJA(OP, 6, 22) RD_GJA(OP, 7, 23) RD_GJA(OP, 8, 24) RD_GJA(OP, 9, 25) RD_GJA(OP, 10, 26) RD_GJA(OP, 11, 27) RD_GJA(OP, 12, 28) RD_GJA(OP, 13, 29) RD_GJA(OP, 15, 31) RD_GJB(OP, 0, 16) RD_GJB(OP, 1, 17) RD_GJB(OP, 2, 18) RD_GJB(OP, 3, 19) RD_GJB(OP, 4, 20) RD_GJB(OP, 5, 21) RD_GJB(OP, 6, 22) RD_GJB(OP, 7, 23) RD_GJB(OP, 8, 24) RD_GJB(OP, 9, 25) RD_GJB(OP, 10, 26) RD_GJB(OP, 11, 27) RD_GJB(OP, 12, 28) RD_GJB(OP, 13, 29) RD_GJB(OP, 15, 31) RD_GJC(OP, 0, 16) RD_GJC(OP, 1, 17) RD_GJC(OP, 2, 18) RD_GJC(OP, 3, 19) RD_GJC(OP, 4, 20) RD_GJC(OP, 5, 21) RD_GJC(OP, 6, 22) RD_GJC(OP, 7, 23) RD_GJC(OP, 8, 24) RD_GJC(OP, 9, 25) RD_GJC(OP, 10, 26) RD_GJC(OP, 11, 27) RD_GJC(OP, 12, 28) RD_GJC(OP, 13, 29) RD_GJC(OP, 15, 31) RD_GJD(OP, 0, 16) RD_GJD(OP, 1, 17) RD_GJD(OP, 2, 18) RD_GJD(OP, 3, 19) RD_GJD(OP, 4, 20) RD_GJD(OP, 5, 21) RD_GJD(OP, 6, 22) RD_GJD(OP, 7, 23) RD_GJD(OP, 8, 24) RD_GJD(OP, 9, 25) RD_GJD(OP, 10, 26) RD_GJD(OP, 11, 27) RD_GJD(OP, 12, 28) RD_GJD(OP, 13, 29) RD_GJD(OP, 15, 31) "s_nop 1"
+#define RD_GJC_S15(OP) "s_nop 1\n\t" RD_GJA(OP, 0, 16) RD_GJA(OP, 1, 17) RD_GJA(OP, 2, 18) RD_GJA(OP, 3, 19) RD_GJA(OP, 4, 20) RD_GJA(OP, 5, 21) RD_GJA(OP, 6, 22) RD_GJA(OP, 7, 23) RD_GJA(OP, 8, 24) RD_GJA(OP, 9, 25) RD_GJA(OP, 10, 26) RD_GJA(OP, 11, 27) RD_GJA(OP, 12, 28) RD_GJA(OP, 13, 29) RD_GJA(OP, 14, 30) RD_GJB(OP, 0, 16) RD_GJB(OP, 1, 17) RD_GJB(OP, 2, 18) RD_GJB(OP, 3, 19) RD_GJB(OP, 4, 20) RD_GJB(OP, 5, 21) RD_GJB(OP, 6, 22) RD_GJB(OP, 7, 23) RD_GJB(OP, 8, 24) RD_GJB(OP, 9, 25) RD_GJB(OP, 10, 26) RD_GJB(OP, 11, 27) RD_GJB(OP, 12, 28) RD_GJB(OP, 13, 29) RD_GJB(OP, 14, 30) RD_GJC(OP, 0, 16) RD_GJC(OP, 1, 17) RD_GJC(OP, 2, 18) RD_GJC(OP, 3, 19) RD_GJC(OP, 4, 20) RD_GJC(OP, 5, 21) RD_GJC(OP, 6, 22) RD_GJC(OP, 7, 23) RD_GJC(OP, 8, 24) RD_GJC(OP, 9, 25) RD_GJC(OP, 10, 26) RD_GJC(OP, 11, 27) RD_GJC(OP, 12, 28) RD_GJC(OP, 13, 29) RD_GJC(OP, 14, 30) RD_GJD(OP, 0, 16) RD_GJD(OP, 1, 17) RD_GJD(OP, 2, 18) RD_GJD(OP, 3, 19) RD_GJD(OP, 4, 20) RD_GJD(OP, 5, 21) RD_GJD(OP, 6, 22) RD_GJD(OP, 7, 23) RD_GJD(OP, 8, 24) RD_GJD(OP, 9, 25) RD_GJD(OP, 10, 26) RD_GJD(OP, 11, 27) RD_GJD(OP, 12, 28) RD_GJD(OP, 13, 29) RD_GJD(OP, 14, 30) "s_nop 1"
 template <int KK, typename T>
 __device__ __forceinline__ void fused_gj_cplx_k(T (&ar)[16], T (&ai)[16], T fr, T fi) {
-    RD_ASM2(T, RD_GJC_BODY,
-            : "+v"(ar[0]), "+v"(ar[1]), "+v"(ar[2]), "+v"(ar[3]), "+v"(ar[4]), "+v"(ar[5]),
-              "+v"(ar[6]), "+v"(ar[7]), "+v"(ar[8]), "+v"(ar[9]), "+v"(ar[10]), "+v"(ar[11]),
-              "+v"(ar[12]), "+v"(ar[13]), "+v"(ar[14]), "+v"(ar[15]), "+v"(ai[0]), "+v"(ai[1]),
-              "+v"(ai[2]), "+v"(ai[3]), "+v"(ai[4]), "+v"(ai[5]), "+v"(ai[6]), "+v"(ai[7]),
-              "+v"(ai[8]), "+v"(ai[9]), "+v"(ai[10]), "+v"(ai[11]), "+v"(ai[12]), "+v"(ai[13]),
-              "+v"(ai[14]), "+v"(ai[15])
-            : "v"(fr), "v"(fi), "n"(KK));
+#define OPERANDS                                                                                  \
+    : "+v"(ar[0]), "+v"(ar[1]), "+v"(ar[2]), "+v"(ar[3]), "+v"(ar[4]), "+v"(ar[5]),             \
+      "+v"(ar[6]), "+v"(ar[7]), "+v"(ar[8]), "+v"(ar[9]), "+v"(ar[10]), "+v"(ar[11]),            \
+      "+v"(ar[12]), "+v"(ar[13]), "+v"(ar[14]), "+v"(ar[15]), "+v"(ai[0]), "+v"(ai[1]),          \
+      "+v"(ai[2]), "+v"(ai[3]), "+v"(ai[4]), "+v"(ai[5]), "+v"(ai[6]), "+v"(ai[7]),              \
+      "+v"(ai[8]), "+v"(ai[9]), "+v"(ai[10]), "+v"(ai[11]), "+v"(ai[12]), "+v"(ai[13]),          \
+      "+v"(ai[14]), "+v"(ai[15])                                                                  \
+    : "v"(fr), "v"(fi), "n"(KK)
+    if constexpr (KK == 0) RD_ASM2(T, RD_GJC_S0, OPERANDS);
+    else if constexpr (KK == 1) RD_ASM2(T, RD_GJC_S1, OPERANDS);
+    else if constexpr (KK == 2) RD_ASM2(T, RD_GJC_S2, OPERANDS);
+    else if constexpr (KK == 3) RD_ASM2(T, RD_GJC_S3, OPERANDS);
+    else if constexpr (KK == 4) RD_ASM2(T, RD_GJC_S4, OPERANDS);
+    else if constexpr (KK == 5) RD_ASM2(T, RD_GJC_S5, OPERANDS);
+    else if constexpr (KK == 6) RD_ASM2(T, RD_GJC_S6, OPERANDS);
+    else if constexpr (KK == 7) RD_ASM2(T, RD_GJC_S7, OPERANDS);
+    else if constexpr (KK == 8) RD_ASM2(T, RD_GJC_S8, OPERANDS);
+    else if constexpr (KK == 9) RD_ASM2(T, RD_GJC_S9, OPERANDS);
+    else if constexpr (KK == 10) RD_ASM2(T, RD_GJC_S10, OPERANDS);
+    else if constexpr (KK == 11) RD_ASM2(T, RD_GJC_S11, OPERANDS);
+    else if constexpr (KK == 12) RD_ASM2(T, RD_GJC_S12, OPERANDS);
+    else if constexpr (KK == 13) RD_ASM2(T, RD_GJC_S13, OPERANDS);
+    else if constexpr (KK == 14) RD_ASM2(T, RD_GJC_S14, OPERANDS);
+    else if constexpr (KK == 15) RD_ASM2(T, RD_GJC_S15, OPERANDS);
+#undef OPERANDS
 }
-#undef RD_GJC_BODY
-#undef RD_SWEEP
+#undef RD_GJC_S0
+#undef RD_GJC_S1
+#undef RD_GJC_S2
+#undef RD_GJC_S3
+#undef RD_GJC_S4
+#undef RD_GJC_S5
+#undef RD_GJC_S6
+#undef RD_GJC_S7
+#undef RD_GJC_S8
+#undef RD_GJC_S9
+#undef RD_GJC_S10
+#undef RD_GJC_S11
+#undef RD_GJC_S12
+#undef RD_GJC_S13
+#undef RD_GJC_S14
+#undef RD_GJC_S15
 #undef RD_GJA
 #undef RD_GJB
 #undef RD_GJC
 #undef RD_GJD
 
-/* The same step for the 8-column engine (m <= 8); four sweeps of eight, so
- * a register written in one sweep is read through DPP eight or more
+/* The same step for the 8-column engine (m <= 8); four sweeps of seven, so
+ * a register written in one sweep is read through DPP seven or more
  * instructions later. */
 #define RD_GJA8(OP, R, I) OP " %" #R ", %" #I ", %17 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n\t"
 #define RD_GJB8(OP, R, I) OP " %" #I ", %" #R ", -%17 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n\t"
 #define RD_GJC8(OP, R, I) OP " %" #R ", %" #R ", -%16 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n\t"
 #define RD_GJD8(OP, R, I) OP " %" #I ", %" #I ", -%16 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n\t"
-#define RD_SWEEP8(S, OP) \
-    S(OP, 0, 8) S(OP, 1, 9) S(OP, 2, 10) S(OP, 3, 11) S(OP, 4, 12) S(OP, 5, 13) S(OP, 6, 14) S(OP, 7, 15)
-#define RD_GJC8_BODY(OP)                                                                          \
-    "s_nop 1\n\t" RD_SWEEP8(RD_GJA8, OP) RD_SWEEP8(RD_GJB8, OP) RD_SWEEP8(RD_GJC8, OP)           \
-    RD_SWEEP8(RD_GJD8, OP) "s_nop 1"
+#define RD_GJC8_S0(OP) "s_nop 1\n\t" RD_GJA8(OP, 1, 9) RD_GJA8(OP, 2, 10) RD_GJA8(OP, 3, 11) RD_GJA8(OP, 4, 12) RD_GJA8(OP, 5, 13) RD_GJA8(OP, 6, 14) RD_GJA8(OP, 7, 15) RD_GJB8(OP, 1, 9) RD_GJB8(OP, 2, 10) RD_GJB8(OP, 3, 11) RD_GJB8(OP, 4, 12) RD_GJB8(OP, 5, 13) RD_GJB8(OP, 6, 14) RD_GJB8(OP, 7, 15) RD_GJC8(OP, 1, 9) RD_GJC8(OP, 2, 10) RD_GJC8(OP, 3, 11) RD_GJC8(OP, 4, 12) RD_GJC8(OP, 5, 13) RD_GJC8(OP, 6, 14) RD_GJC8(OP, 7, 15) RD_GJD8(OP, 1, 9) RD_GJD8(OP, 2, 10) RD_GJD8(OP, 3, 11) RD_GJD8(OP, 4, 12) RD_GJD8(OP, 5, 13) RD_GJD8(OP, 6, 14) RD_GJD8(OP, 7, 15) "s_nop 1"
+#define RD_GJC8_S1(OP) "s_nop 1\n\t" RD_GJA8(OP, 0, 8) RD_GJA8(OP, 2, 10) RD_GJA8(OP, 3, 11) RD_GJA8(OP, 4, 12) RD_GJA8(OP, 5, 13) RD_GJA8(OP, 6, 14) RD_GJA8(OP, 7, 15) RD_GJB8(OP, 0, 8) RD_GJB8(OP, 2, 10) RD_GJB8(OP, 3, 11) RD_GJB8(OP, 4, 12) RD_GJB8(OP, 5, 13) RD_GJB8(OP, 6, 14) RD_GJB8(OP, 7, 15) RD_GJC8(OP, 0, 8) RD_GJC8(OP, 2, 10) RD_GJC8(OP, 3, 11) RD_GJC8(OP, 4, 12) RD_GJC8(OP, 5, 13) RD_GJC8(OP, 6, 14) RD_GJC8(OP, 7, 15) RD_GJD8(OP, 0, 8) RD_GJD8(OP, 2, 10) RD_GJD8(OP, 3, 11) RD_GJD8(OP, 4, 12) RD_GJD8(OP, 5, 13) RD_GJD8(OP, 6, 14) RD_GJD8(OP, 7, 15) "s_nop 1"
+#define RD_GJC8_S2(OP) "s_nop 1\n\t" RD_GJA8(OP, 0, 8) RD_GJA8(OP, 1, 9) RD_GJA8(OP, 3, 11) RD_GJA8(OP, 4, 12) RD_GJA8(OP, 5, 13) RD_GJA8(OP, 6, 14) RD_GJA8(OP, 7, 15) RD_GJB8(OP, 0, 8) RD_GJB8(OP, 1, 9) RD_GJB8(OP, 3, 11) RD_GJB8(OP, 4, 12) RD_GJB8(OP, 5, 13) RD_GJB8(OP, 6, 14) RD_GJB8(OP, 7, 15) RD_GJC8(OP, 0, 8) RD_GJC8(OP, 1, 9) RD_GJC8(OP, 3, 11) RD_GJC8(OP, 4, 12) RD_GJC8(OP, 5, 13) RD_GJC8(OP, 6, 14) RD_GJC8(OP, 7, 15) RD_GJD8(OP, 0, 8) RD_GJD8(OP, 1, 9) RD_GJD8(OP, 3, 11) RD_GJD8(OP, 4, 12) RD_GJD8(OP, 5, 13) RD_GJD8(OP, 6, 14) RD_GJD8(OP, 7, 15) "s_nop 1"
+#define RD_GJC8_S3(OP) "s_nop 1\n\t" RD_GJA8(OP, 0, 8) RD_GJA8(OP, 1, 9) RD_GJA8(OP, 2, 10) RD_GJA8(OP, 4, 12) RD_GJA8(OP, 5, 13) RD_GJA8(OP, 6, 14) RD_GJA8(OP, 7, 15) RD_GJB8(OP, 0, 8) RD_GJB8(OP, 1, 9) RD_GJB8(OP, 2, 10) RD_GJB8(OP, 4, 12) RD_GJB8(OP, 5, 13) RD_GJB8(OP, 6, 14) RD_GJB8(OP, 7, 15) RD_GJC8(OP, 0, 8) RD_GJC8(OP, 1, 9) RD_GJC8(OP, 2, 10) RD_GJC8(OP, 4, 12) RD_GJC8(OP, 5, 13) RD_GJC8(OP, 6, 14) RD_GJC8(OP, 7, 15) RD_GJD8(OP, 0, 8) RD_GJD8(OP, 1, 9) RD_GJD8(OP, 2, 10) RD_GJD8(OP, 4, 12) RD_GJD8(OP, 5, 13) RD_GJD8(OP, 6, 14) RD_GJD8(OP, 7, 15) "s_nop 1"
+#define RD_GJC8_S4(OP) "s_nop 1\n\t" RD_GJA8(OP, 0, 8) RD_GJA8(OP, 1, 9) RD_GJA8(OP, 2, 10) RD_GJA8(OP, 3, 11) RD_GJA8(OP, 5, 13) RD_GJA8(OP, 6, 14) RD_GJA8(OP, 7, 15) RD_GJB8(OP, 0, 8) RD_GJB8(OP, 1, 9) RD_GJB8(OP, 2, 10) RD_GJB8(OP, 3, 11) RD_GJB8(OP, 5, 13) RD_GJB8(OP, 6, 14) RD_GJB8(OP, 7, 15) RD_GJC8(OP, 0, 8) RD_GJC8(OP, 1, 9) RD_GJC8(OP, 2, 10) RD_GJC8(OP, 3, 11) RD_GJC8(OP, 5, 13) RD_GJC8(OP, 6, 14) RD_GJC8(OP, 7, 15) RD_GJD8(OP, 0, 8) RD_GJD8(OP, 1, 9) RD_GJD8(OP, 2, 10) RD_GJD8(OP, 3, 11) RD_GJD8(OP, 5, 13) RD_GJD8(OP, 6, 14) RD_GJD8(OP, 7, 15) "s_nop 1"
+#define RD_GJC8_S5(OP) "s_nop 1\n\t" RD_GJA8(OP, 0, 8) RD_GJA8(OP, 1, 9) RD_GJA8(OP, 2, 10) RD_GJA8(OP, 3, 11) RD_GJA8(OP, 4, 12) RD_GJA8(OP, 6, 14) RD_GJA8(OP, 7, 15) RD_GJB8(OP, 0, 8) RD_GJB8(OP, 1, 9) RD_GJB8(OP, 2, 10) RD_GJB8(OP, 3, 11) RD_GJB8(OP, 4, 12) RD_GJB8(OP, 6, 14) RD_GJB8(OP, 7, 15) RD_GJC8(OP, 0, 8) RD_GJC8(OP, 1, 9) RD_GJC8(OP, 2, 10) RD_GJC8(OP, 3, 11) RD_GJC8(OP, 4, 12) RD_GJC8(OP, 6, 14) RD_GJC8(OP, 7, 15) RD_GJD8(OP, 0, 8) RD_GJD8(OP, 1, 9) RD_GJD8(OP, 2, 10) RD_GJD8(OP, 3, 11) RD_GJD8(OP, 4, 12) RD_GJD8(OP, 6, 14) RD_GJD8(OP, 7, 15) "s_nop 1"
+#define RD_GJC8_S6(OP) "s_nop 1\n\t" RD_GJA8(OP, 0, 8) RD_GJA8(OP, 1, 9) RD_GJA8(OP, 2, 10) RD_GJA8(OP, 3, 11) RD_GJA8(OP, 4, 12) RD_GJA8(OP, 5, 13) RD_GJA8(OP, 7, 15) RD_GJB8(OP, 0, 8) RD_GJB8(OP, 1, 9) RD_GJB8(OP, 2, 10) RD_GJB8(OP, 3, 11) RD_GJB8(OP, 4, 12) RD_GJB8(OP, 5, 13) RD_GJB8(OP, 7, 15) RD_GJC8(OP, 0, 8) RD_GJC8(OP, 1, 9) RD_GJC8(OP, 2, 10) RD_GJC8(OP, 3, 11) RD_GJC8(OP, 4, 12) RD_GJC8(OP, 5, 13) RD_GJC8(OP, 7, 15) RD_GJD8(OP, 0, 8) RD_GJD8(OP, 1, 9) RD_GJD8(OP, 2, 10) RD_GJD8(OP, 3, 11) RD_GJD8(OP, 4, 12) RD_GJD8(OP, 5, 13) RD_GJD8(OP, 7, 15) "s_nop 1"
+#define RD_GJC8_S7(OP) "s_nop 1\n\t" RD_GJA8(OP, 0, 8) RD_GJA8(OP, 1, 9) RD_GJA8(OP, 2, 10) RD_GJA8(OP, 3, 11) RD_GJA8(OP, 4, 12) RD_GJA8(OP, 5, 13) RD_GJA8(OP, 6, 14) RD_GJB8(OP, 0, 8) RD_GJB8(OP, 1, 9) RD_GJB8(OP, 2, 10) RD_GJB8(OP, 3, 11) RD_GJB8(OP, 4, 12) RD_GJB8(OP, 5, 13) RD_GJB8(OP, 6, 14) RD_GJC8(OP, 0, 8) RD_GJC8(OP, 1, 9) RD_GJC8(OP, 2, 10) RD_GJC8(OP, 3, 11) RD_GJC8(OP, 4, 12) RD_GJC8(OP, 5, 13) RD_GJC8(OP, 6, 14) RD_GJD8(OP, 0, 8) RD_GJD8(OP, 1, 9) RD_GJD8(OP, 2, 10) RD_GJD8(OP, 3, 11) RD_GJD8(OP, 4, 12) RD_GJD8(OP, 5, 13) RD_GJD8(OP, 6, 14) "s_nop 1"
 template <int KK, typename T>
 __device__ __forceinline__ void fused_gj_cplx8_k(T (&ar)[8], T (&ai)[8], T fr, T fi) {
-    RD_ASM2(T, RD_GJC8_BODY,
-            : "+v"(ar[0]), "+v"(ar[1]), "+v"(ar[2]), "+v"(ar[3]), "+v"(ar[4]), "+v"(ar[5]),
-              "+v"(ar[6]), "+v"(ar[7]), "+v"(ai[0]), "+v"(ai[1]), "+v"(ai[2]), "+v"(ai[3]),
-              "+v"(ai[4]), "+v"(ai[5]), "+v"(ai[6]), "+v"(ai[7])
-            : "v"(fr), "v"(fi), "n"(KK));
+#define OPERANDS                                                                                  \
+    : "+v"(ar[0]), "+v"(ar[1]), "+v"(ar[2]), "+v"(ar[3]), "+v"(ar[4]), "+v"(ar[5]),             \
+      "+v"(ar[6]), "+v"(ar[7]), "+v"(ai[0]), "+v"(ai[1]), "+v"(ai[2]), "+v"(ai[3]),              \
+      "+v"(ai[4]), "+v"(ai[5]), "+v"(ai[6]), "+v"(ai[7])                                         \
+    : "v"(fr), "v"(fi), "n"(KK)
+    if constexpr (KK == 0) RD_ASM2(T, RD_GJC8_S0, OPERANDS);
+    else if constexpr (KK == 1) RD_ASM2(T, RD_GJC8_S1, OPERANDS);
+    else if constexpr (KK == 2) RD_ASM2(T, RD_GJC8_S2, OPERANDS);
+    else if constexpr (KK == 3) RD_ASM2(T, RD_GJC8_S3, OPERANDS);
+    else if constexpr (KK == 4) RD_ASM2(T, RD_GJC8_S4, OPERANDS);
+    else if constexpr (KK == 5) RD_ASM2(T, RD_GJC8_S5, OPERANDS);
+    else if constexpr (KK == 6) RD_ASM2(T, RD_GJC8_S6, OPERANDS);
+    else if constexpr (KK == 7) RD_ASM2(T, RD_GJC8_S7, OPERANDS);
+#undef OPERANDS
 }
-#undef RD_GJC8_BODY
-#undef RD_SWEEP8
+#undef RD_GJC8_S0
+#undef RD_GJC8_S1
+#undef RD_GJC8_S2
+#undef RD_GJC8_S3
+#undef RD_GJC8_S4
+#undef RD_GJC8_S5
+#undef RD_GJC8_S6
+#undef RD_GJC8_S7
 #undef RD_GJA8
 #undef RD_GJB8
 #undef RD_GJC8
