@@ -270,6 +270,30 @@ struct GroupCell {
         }
     }
 
+    /* f_q at the three stage arguments of a Newton iteration; for the fused
+     * kinetics rows in one pass over the model rows (each LDS row entry read
+     * once), which gives the bits of three rhs calls */
+    __device__ __forceinline__ void rhs3(double u1, double u2, double u3, double& F1, double& F2,
+                                         double& F3) const {
+        if constexpr (kFused && HAS_G && !BC && !FDJ) {
+            double lin[3] = {0.0, 0.0, 0.0}, loss[3] = {0.0, 0.0, 0.0};
+            fused_row4x3<0>(u1, u2, u3, kg, kg + kGroup, lin, loss);
+            fused_row4x3<4>(u1, u2, u3, kg, kg + kGroup, lin, loss);
+            if constexpr (NC == 16) {
+                fused_row4x3<8>(u1, u2, u3, kg, kg + kGroup, lin, loss);
+                fused_row4x3<12>(u1, u2, u3, kg, kg + kGroup, lin, loss);
+            }
+            F1 = lin[0] - u1 * loss[0];
+            F2 = lin[1] - u2 * loss[1];
+            F3 = lin[2] - u3 * loss[2];
+        } else {
+            double gu;
+            F1 = rhs(u1, gu);
+            F2 = rhs(u2, gu);
+            F3 = rhs(u3, gu);
+        }
+    }
+
     /* (J x)_q with the current Jacobian: from the LDS rows (forward
      * differences), else (K x)_q - uJ (G x)_q - gJ x_q at the stored point */
     __device__ __forceinline__ double jmul(double x) const {
@@ -285,6 +309,29 @@ struct GroupCell {
             double lin, loss;
             rows(x, lin, loss);
             return HAS_G ? lin - cv(C_UJ) * loss - cv(C_GJ) * x : lin;
+        }
+    }
+
+    /* jmul at three arguments; for the fused kinetics rows in one pass over
+     * the model rows, with the bits of three jmul calls */
+    __device__ __forceinline__ void jmul3(double x1, double x2, double x3, double& j1, double& j2,
+                                          double& j3) const {
+        if constexpr (kFused && HAS_G && !BC && !FDJ) {
+            double lin[3] = {0.0, 0.0, 0.0}, loss[3] = {0.0, 0.0, 0.0};
+            fused_row4x3<0>(x1, x2, x3, kg, kg + kGroup, lin, loss);
+            fused_row4x3<4>(x1, x2, x3, kg, kg + kGroup, lin, loss);
+            if constexpr (NC == 16) {
+                fused_row4x3<8>(x1, x2, x3, kg, kg + kGroup, lin, loss);
+                fused_row4x3<12>(x1, x2, x3, kg, kg + kGroup, lin, loss);
+            }
+            const double uj = cv(C_UJ), gj = cv(C_GJ);
+            j1 = lin[0] - uj * loss[0] - gj * x1;
+            j2 = lin[1] - uj * loss[1] - gj * x2;
+            j3 = lin[2] - uj * loss[2] - gj * x3;
+        } else {
+            j1 = jmul(x1);
+            j2 = jmul(x2);
+            j3 = jmul(x3);
         }
     }
 
@@ -657,28 +704,22 @@ struct GroupCell {
 
     __device__ __forceinline__ int newton(const StepParams& P) {
         ++k;
-        double G1, G2, G3, gu;
+        double G1, G2, G3, Fs1, Fs2, Fs3;
         {
-            const double z = radau::T11 * w1 + radau::T12 * w2 + radau::T13 * w3;
-            const double F = rhs(y + z, gu);
-            G1 = radau::TI11 * F;
-            G2 = radau::TI21 * F;
-            G3 = radau::TI31 * F;
+            const double z1 = radau::T11 * w1 + radau::T12 * w2 + radau::T13 * w3;
+            const double z2 = radau::T21 * w1 + radau::T22 * w2 + radau::T23 * w3;
+            const double z3 = w1 + w2;
+            rhs3(y + z1, y + z2, y + z3, Fs1, Fs2, Fs3);
         }
-        {
-            const double z = radau::T21 * w1 + radau::T22 * w2 + radau::T23 * w3;
-            const double F = rhs(y + z, gu);
-            G1 += radau::TI12 * F;
-            G2 += radau::TI22 * F;
-            G3 += radau::TI32 * F;
-        }
-        {
-            const double z = w1 + w2;
-            const double F = rhs(y + z, gu);
-            G1 += radau::TI13 * F;
-            G2 += radau::TI23 * F;
-            G3 += radau::TI33 * F;
-        }
+        G1 = radau::TI11 * Fs1;
+        G2 = radau::TI21 * Fs1;
+        G3 = radau::TI31 * Fs1;
+        G1 += radau::TI12 * Fs2;
+        G2 += radau::TI22 * Fs2;
+        G3 += radau::TI32 * Fs2;
+        G1 += radau::TI13 * Fs3;
+        G2 += radau::TI23 * Fs3;
+        G3 += radau::TI33 * Fs3;
         const double g = radau::GAMMA * ih, al = radau::ALPHA * ih, be = radau::BETA * ih;
         const double b1 = G1 - g * w1, b2 = G2 - al * w2 + be * w3, b3 = G3 - be * w2 - al * w3;
         const LT r1 = solve_real((LT)b1);
@@ -688,7 +729,8 @@ struct GroupCell {
         if constexpr (kRefine) {
             /* one step of iterative refinement against the FP64 matrices
              * E1 = g I - J, E2 = (al + i be) I - J: x += E32^{-1} (b - E x) */
-            const double j1 = jmul(d1), j2 = jmul(d2), j3 = jmul(d3);
+            double j1, j2, j3;
+            jmul3(d1, d2, d3, j1, j2, j3);
             const LT c1 = solve_real((LT)(b1 - g * d1 + j1));
             LT c2 = (LT)(b2 - al * d2 + be * d3 + j2), c3 = (LT)(b3 - be * d2 - al * d3 + j3);
             solve_cplx(c2, c3);

@@ -143,6 +143,30 @@ __device__ __forceinline__ void fused_row4(double u, const double* k, const doub
                        "v"(g3), "n"(J0), "n"(J0 + 1), "n"(J0 + 2), "n"(J0 + 3));
 }
 #undef RD_ROW
+/* The same four columns for three arguments u1, u2, u3 at once (the three
+ * stages of a Newton iteration): each k[j], g[j] is read from LDS once, and
+ * each of the six sums receives its products column by column as above. */
+#define RD_ROW3(J, K, G)                                                                    \
+    RD_F64 " %0, %6, %" #K " row_newbcast:%" #J " row_mask:0xf bank_mask:0xf\n\t"          \
+    RD_F64 " %1, %6, %" #G " row_newbcast:%" #J " row_mask:0xf bank_mask:0xf\n\t"          \
+    RD_F64 " %2, %7, %" #K " row_newbcast:%" #J " row_mask:0xf bank_mask:0xf\n\t"          \
+    RD_F64 " %3, %7, %" #G " row_newbcast:%" #J " row_mask:0xf bank_mask:0xf\n\t"          \
+    RD_F64 " %4, %8, %" #K " row_newbcast:%" #J " row_mask:0xf bank_mask:0xf\n\t"          \
+    RD_F64 " %5, %8, %" #G " row_newbcast:%" #J " row_mask:0xf bank_mask:0xf\n\t"
+template <int J0>
+__device__ __forceinline__ void fused_row4x3(double u1, double u2, double u3, const double* k,
+                                             const double* g, double (&lin)[3], double (&loss)[3]) {
+    const double k0 = k[J0], k1 = k[J0 + 1], k2 = k[J0 + 2], k3 = k[J0 + 3];
+    const double g0 = g[J0], g1 = g[J0 + 1], g2 = g[J0 + 2], g3 = g[J0 + 3];
+    __asm__ volatile("s_nop 1\n\t"
+                     RD_ROW3(17, 9, 13) RD_ROW3(18, 10, 14) RD_ROW3(19, 11, 15) RD_ROW3(20, 12, 16)
+                     "s_nop 1"
+                     : "+v"(lin[0]), "+v"(loss[0]), "+v"(lin[1]), "+v"(loss[1]), "+v"(lin[2]),
+                       "+v"(loss[2])
+                     : "v"(u1), "v"(u2), "v"(u3), "v"(k0), "v"(k1), "v"(k2), "v"(k3), "v"(g0),
+                       "v"(g1), "v"(g2), "v"(g3), "n"(J0), "n"(J0 + 1), "n"(J0 + 2), "n"(J0 + 3));
+}
+#undef RD_ROW3
 #define RD_ROWK(J, K) RD_F64 " %0, %1, %" #K " row_newbcast:%" #J " row_mask:0xf bank_mask:0xf\n\t"
 template <int J0>
 __device__ __forceinline__ void fused_row4(double u, const double* k, double& lin) {
