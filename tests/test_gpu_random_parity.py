@@ -69,8 +69,10 @@ def draw_case(seed):
     return w, opts
 
 
-# the committed sweep is seeds 0..19; RD_RANDOM_SEEDS=a:b runs seeds a..b-1
+# the committed sweep is seeds 0..19 in FP64; RD_RANDOM_SEEDS=a:b runs seeds
+# a..b-1, RD_RANDOM_PRECISION=1 the mixed-precision path
 _SEEDS = range(*(int(x) for x in os.environ.get("RD_RANDOM_SEEDS", "0:20").split(":")))
+_PRECISION = int(os.environ.get("RD_RANDOM_PRECISION", "0"))
 
 
 @pytest.mark.parametrize("seed", _SEEDS)
@@ -79,7 +81,8 @@ def test_random_configuration_matches_oracle(rd, orc, seed):
     say("random case", seed, w.name, "m", w.m, "n", w.n, "dt", w.dt, "rtol", w.rtol, opts)
     u = torch.tensor(w.states, dtype=torch.float64, device="cuda")
     st = torch.zeros((9, w.n), dtype=torch.int32, device="cuda")
-    ret = rd.reaction_step(u, w.dt, w.rtol, w.atol, w.kind, w.params, stats=st, **opts)
+    ret = rd.reaction_step(u, w.dt, w.rtol, w.atol, w.kind, w.params, stats=st,
+                           precision=_PRECISION, **opts)
     torch.cuda.synchronize()
     y, s = u.cpu().numpy(), st.cpu().numpy()
     yo, so, reto = orc.reaction_step(w.states, w.dt, w.rtol, w.atol, w.kind, w.params)
