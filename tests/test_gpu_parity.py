@@ -267,9 +267,10 @@ def test_oregonator_2d_mixed_every_cell_vs_oracle(rd, orc):
 
 
 def test_oregonator_3d_every_cell_vs_oracle(rd, orc):
-    """All 4 194 304 cells of the scroll-wave batch, FP64, in the benchmark's
-    launch configuration (persistent, longest-first claim order), each
-    against the oracle (whole batch on the host's threads)."""
+    """All 4 194 304 cells of the scroll-wave batch, FP64 and mixed precision,
+    in the benchmark's launch configuration (persistent, longest-first claim
+    order, claim rounds), each against the oracle (whole batch on the host's
+    threads)."""
     w = W.oregonator_3d()
     say("oregonator_3d every cell, n", w.n)
     y, st, ret = run_gpu(rd, w)
@@ -278,3 +279,8 @@ def test_oregonator_3d_every_cell_vs_oracle(rd, orc):
     rep = compare(y, st, yo, sto, w.atol, label="3d fp64 every cell")
     assert rep["max_err"] <= 1e-8
     assert rep["trace_divergent"] == 0
+    ym, stm, retm = run_gpu(rd, w, precision=1)
+    assert retm == 0
+    repm = compare(ym, stm, yo, sto, w.atol, label="3d mixed every cell")
+    assert repm["max_err"] <= 1e-8
+    assert repm["trace_divergent"] == 0
