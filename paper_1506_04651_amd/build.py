@@ -35,10 +35,14 @@ EXTRA = {"rd_kernels_group.hip": ["-mllvm", "-pragma-unroll-threshold=200000"],
          "rd_mra.hip": ["-ffp-contract=off"]}
 
 
-def _compile(src, verbose):
+PHASE_BUILD = os.path.join(os.path.dirname(HERE), "_build_phase")
+PHASE_LIB = os.path.join(HERE, "librd_phase.so")
+
+
+def _compile(src, verbose, build_dir=BUILD, defines=()):
     path = os.path.join(CSRC, src)
-    obj = os.path.join(BUILD, src + ".o")
-    cmd = [HIPCC] + FLAGS + EXTRA.get(src, []) + ["-x", "hip", "-c", path, "-o", obj]
+    obj = os.path.join(build_dir, src + ".o")
+    cmd = [HIPCC] + FLAGS + list(defines) + EXTRA.get(src, []) + ["-x", "hip", "-c", path, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -47,19 +51,33 @@ def _compile(src, verbose):
     return obj
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def _build(lib, build_dir, defines, verbose, jobs):
+    os.makedirs(build_dir, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     with cf.ThreadPoolExecutor(max_workers=min(jobs, len(srcs))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, verbose, build_dir, defines), srcs))
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(verbose: bool = False, jobs: int = 8) -> str:
+    return _build(LIB, BUILD, (), verbose, jobs)
+
+
+def build_phase_profile(verbose: bool = False, jobs: int = 8) -> str:
+    """A diagnostic copy of the library whose persistent kernels count the
+    cycles of their phases (RD_PHASE_PROFILE, rd_phase.h), for
+    phase_profile.py; the product library is not touched."""
+    return _build(PHASE_LIB, PHASE_BUILD, ("-DRD_PHASE_PROFILE",), verbose, jobs)
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--phase-profile" in sys.argv:
+        print(build_phase_profile(verbose="-v" in sys.argv))
+    else:
+        print(build(verbose="-v" in sys.argv))

@@ -662,6 +662,7 @@ struct GroupCell {
             ++kc(K_NJAC);
             flags = (flags & ~(F_JSTALE | F_LUOK)) | F_JATY0;
         }
+        RD_PH_BEGIN(ph_f)
         if (FIXED || !has(F_LUOK)) {
             ++kc(K_NDEC);
             if (!factor()) {
@@ -673,6 +674,7 @@ struct GroupCell {
             nsing = 0;
             flags |= F_LUOK;
         }
+        RD_PH_END(ph_f, PHASE_FACTOR);
         /* start values (zero on the cell's first step); every branch ends in
          * the same single assignment of w1, w2, w3 */
         double za = 0.0, zb = 0.0, zc = 0.0;

@@ -398,6 +398,7 @@ struct SmallCell {
             ++ilds[L::NJAC];
             flags = (flags & ~(F_JSTALE | F_LUOK)) | F_JATY0;
         }
+        RD_PH_BEGIN(ph_f)
         if (FIXED || !has(F_LUOK)) {
             ++ilds[L::NDEC];
             if (!factor()) {
@@ -409,6 +410,7 @@ struct SmallCell {
             nsing = 0;
             flags |= F_LUOK;
         }
+        RD_PH_END(ph_f, PHASE_FACTOR);
         /* Newton start: zero, or the collocation cubic of the last accepted
          * step continued to the new stage points (nodes s = -1, c1-1, c2-1, 0
          * in units of h_old; values -z3, z1 - z3, z2 - z3, 0), then W = T^-1 Z. */

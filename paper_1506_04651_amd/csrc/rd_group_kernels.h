@@ -67,7 +67,9 @@ __device__ __forceinline__ void advance_group(Cell& cell, const StepParams& P) {
     /* keep the LDS model rows out of registers: they are re-read, not hoisted */
     __asm__ volatile("" ::: "memory");
     if (cell.phase == PH_NEWTON) {
+        RD_PH_BEGIN(ph_n)
         const int o = cell.newton(P);
+        RD_PH_END(ph_n, PHASE_NEWTON);
         if (o != NW_CONTINUE) {
             cell.outcome = o;
             cell.phase = PH_END;
@@ -81,8 +83,16 @@ __device__ __forceinline__ void advance_group(Cell& cell, const StepParams& P) {
             __ballot(cell.phase == PH_NEWTON) != 0ull)
             return;
     }
-    if (cell.phase == PH_END) cell.template finish<FIXED>(P, cell.outcome);
-    if (cell.phase == PH_START) cell.template start<FIXED>(P);
+    if (cell.phase == PH_END) {
+        RD_PH_BEGIN(ph_e)
+        cell.template finish<FIXED>(P, cell.outcome);
+        RD_PH_END(ph_e, PHASE_FINISH);
+    }
+    if (cell.phase == PH_START) {
+        RD_PH_BEGIN(ph_s)
+        cell.template start<FIXED>(P);
+        RD_PH_END(ph_s, PHASE_START);
+    }
 }
 
 template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN, bool FUSE, int NC,
@@ -122,7 +132,9 @@ k_group_persistent(LaunchArgs a, int m) {
     const unsigned lane = __lane_id();
     const unsigned long long below = (1ull << lane) - 1ull;
     unsigned long long qnext = 0, qend = 0; /* wave-uniform claim queue, in cells */
+    RD_PH_KERNEL_BEGIN(ph_k)
     for (;;) {
+        RD_PH_BEGIN(ph_c)
         const bool need = alive && cell.phase == PH_IDLE; /* group-uniform */
         if (need && c >= 0) {
             cell.store(a.states, a.stats, a.n, c, a.hcell);
@@ -158,9 +170,11 @@ k_group_persistent(LaunchArgs a, int m) {
                 }
             }
         }
+        RD_PH_END(ph_c, PHASE_CLAIM);
         if (__ballot(alive) == 0ull) break;
         advance_group<FIXED, FSMIN>(cell, sP);
     }
+    RD_PH_KERNEL_END(ph_k);
 }
 
 /* the species count travels in StepParams::m */

@@ -111,3 +111,5 @@ const KernelEntry* group_kernel_table(int* count) {
 }
 
 }  // namespace rd
+
+RD_PH_READER(rd_phase_read_group)

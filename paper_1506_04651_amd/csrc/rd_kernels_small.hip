@@ -102,3 +102,5 @@ const KernelEntry* small_kernel_table(int* count) {
 }
 
 }  // namespace rd
+
+RD_PH_READER(rd_phase_read_small)

@@ -24,7 +24,9 @@ template <class Model, typename LT, bool FIXED, int BLOCK, int FSMIN>
 __device__ __forceinline__ void advance(SmallCell<Model, LT, BLOCK>& cell, const Model& md,
                                         const StepParams& P, int fsmin = FSMIN) {
     if (cell.phase == PH_NEWTON) {
+        RD_PH_BEGIN(ph_n)
         const int o = cell.newton(md, P);
+        RD_PH_END(ph_n, PHASE_NEWTON);
         if (o != NW_CONTINUE) {
             cell.outcome = o;
             cell.phase = PH_END;
@@ -37,8 +39,16 @@ __device__ __forceinline__ void advance(SmallCell<Model, LT, BLOCK>& cell, const
         if ((unsigned)__popcll(wmask) < (unsigned)fsmin && __ballot(cell.phase == PH_NEWTON) != 0ull)
             return;
     }
-    if (cell.phase == PH_END) cell.template finish<FIXED>(md, P, cell.outcome);
-    if (cell.phase == PH_START) cell.template start<FIXED>(md, P);
+    if (cell.phase == PH_END) {
+        RD_PH_BEGIN(ph_e)
+        cell.template finish<FIXED>(md, P, cell.outcome);
+        RD_PH_END(ph_e, PHASE_FINISH);
+    }
+    if (cell.phase == PH_START) {
+        RD_PH_BEGIN(ph_s)
+        cell.template start<FIXED>(md, P);
+        RD_PH_END(ph_s, PHASE_START);
+    }
 }
 
 template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN>
@@ -128,7 +138,9 @@ k_persistent(LaunchArgs a) {
     unsigned long long held = ~0ull;         /* claim position of the cell held */
     int fs = FSL;                            /* wave-uniform step-end batching threshold */
     int claims = 0;                          /* claim rounds of the wave so far */
+    RD_PH_KERNEL_BEGIN(ph_k)
     for (;;) {
+        RD_PH_BEGIN(ph_c)
         const bool need = alive && cell.phase == PH_IDLE;
         if (need && c >= 0) {
             cell.store(a.states, a.stats, a.n, c, a.hcell);
@@ -175,10 +187,12 @@ k_persistent(LaunchArgs a) {
                 fs = claims == 1 ? FSL : (prio == 3 ? FSU : FSMIN);
             }
         }
+        RD_PH_END(ph_c, PHASE_CLAIM);
         if (__ballot(alive) == 0ull) break;
         if (PLDS) __asm__ volatile("" ::: "memory"); /* re-read sP from LDS each pass */
         advance<Model, LT, FIXED, RS, FSMIN>(cell, md, sP, fs);
     }
+    RD_PH_KERNEL_END(ph_k);
 }
 
 template <class Model, typename LT, bool FIXED, int BLOCK, int WPE, int FSMIN>
