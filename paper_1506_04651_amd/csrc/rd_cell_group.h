@@ -116,9 +116,10 @@ struct GroupCell {
     /* lane-q components */
     double y, f0, isc, w1, w2, w3;
     /* cold values: Z of the last accepted step, lane q's component of the
-     * Jacobian point and (G u)_q there, the step-control scalars and the
-     * Newton rate estimates (eta, 1/norm of the last increment) */
-    enum : int { C_Z1 = 0, C_Z2, C_Z3, C_UJ, C_GJ, C_HOLD, C_IHACC, C_QACC, C_HPRE, C_ETA, C_INPREV, C_N };
+     * Jacobian point and (G u)_q there, the step-control scalars, the
+     * Newton rate estimates (eta, 1/norm of the last increment) and the time
+     * reached in the substep */
+    enum : int { C_Z1 = 0, C_Z2, C_Z3, C_UJ, C_GJ, C_HOLD, C_IHACC, C_QACC, C_HPRE, C_ETA, C_INPREV, C_T, C_N };
     double creg[C_N];
     double* cl; /* COLD: slot i at cl[i * jstride] (LDS) */
     __device__ __forceinline__ double& cv(int i) {
@@ -155,7 +156,7 @@ struct GroupCell {
     bool act;         /* q < m */
     /* per-cell scalars, replicated across the group (the step-control ones
      * that change once per step are cold values, cv) */
-    double t, h, ih;
+    double h, ih;
     unsigned flags;
     int phase, status, k, nsing, outcome;
 
@@ -362,7 +363,7 @@ struct GroupCell {
         f0 = rhs(y, gu);
         status = ST_OK;
         const bool fin = grp_bits(finite_d(y) && finite_d(f0)) == 0xFFFFu;
-        t = 0.0;
+        cv(C_T) = 0.0;
         const double hw = hcell ? hcell[c] : 0.0;
         h = P.fixed_steps > 0 ? P.dt / P.fixed_steps
                               : fmin(hw > 0.0 ? hw : (P.h0 > 0.0 ? P.h0 : P.dt), P.dt);
@@ -640,9 +641,9 @@ struct GroupCell {
             cv(C_HPRE) = h;
             if (kc(K_NACC) + kc(K_NREJ) >= P.max_steps) { status = ST_MAXSTEPS; phase = PH_IDLE; return; }
             if (h < P.h_min) { status = ST_HSMALL; phase = PH_IDLE; return; }
-            const bool last = t + 1.0001 * h >= P.dt;
+            const bool last = cv(C_T) + 1.0001 * h >= P.dt;
             if (last) {
-                const double hl = P.dt - t;
+                const double hl = P.dt - cv(C_T);
                 if (hl != h) flags &= ~F_LUOK;
                 h = hl;
             }
@@ -858,7 +859,8 @@ struct GroupCell {
             cv(C_Z1) = zz1;
             cv(C_Z2) = zz2;
             cv(C_Z3) = zz3;
-            t = has(F_LAST) ? P.dt : t + h;
+            const double t = has(F_LAST) ? P.dt : cv(C_T) + h;
+            cv(C_T) = t;
             cv(C_HOLD) = h;
             cv(C_ETA) = pow08(fmax(cv(C_ETA), UROUND));
             ++kc(K_NACC);
