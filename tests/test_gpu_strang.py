@@ -45,6 +45,35 @@ def test_diffusion_step_matches_oracle(rd, shape, dt, stages):
     assert np.allclose(got.sum(axis=1), u0.sum(axis=1), rtol=1e-12)
 
 
+@pytest.mark.parametrize("shape,dt", [((64, 48), 1e-3), ((32, 30, 18), 5e-3), ((2, 150), 1e-2)])
+def test_two_cells_per_thread_equal_one_cell(rd, shape, dt):
+    """With rows of even length and 16-byte aligned vectors the stage kernels
+    take two neighbouring cells per thread; the same states placed one double
+    off that alignment run the one-cell kernels.  Both give bitwise the same
+    result, and the oracle's to 1e-12 (row length 2: the pair is the whole
+    row, with no neighbour on either side)."""
+    n = int(np.prod(shape))
+    h = 1.0 / shape[0]
+    rng = np.random.default_rng(n + 1)
+    u0 = rng.uniform(0.0, 1.0, (3, n))
+    say("diffusion pairs vs single cells", shape, "dt", dt)
+    a = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    buf = torch.zeros(3 * n + 1, dtype=torch.float64, device="cuda")
+    b = buf[1:].view(3, n)
+    b.copy_(a)
+    assert a.data_ptr() % 16 == 0 and b.data_ptr() % 16 == 8
+    sa = rd.diffusion_step(a, shape, h, BZ_DIFF, dt)
+    sb = rd.diffusion_step(b, shape, h, BZ_DIFF, dt)
+    torch.cuda.synchronize()
+    assert sa == sb and sa >= 2
+    assert torch.equal(a, b)
+    ref, s_ref = D.diffusion_step(u0, shape, h, BZ_DIFF, dt)
+    assert s_ref == sa
+    err = np.max(np.abs(a.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    say("stages", sa, "max rel diff", err)
+    assert err <= 1e-12
+
+
 def test_strang_steps_match_oracle(rd, orc):
     """Three Strang steps on the paper-constant BZ field (96^2), GPU and
     oracle each from the same generated states."""
