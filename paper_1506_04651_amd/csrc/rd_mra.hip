@@ -72,47 +72,69 @@ __device__ __forceinline__ double* lvl(const Pyr& P, int i, int j) {
 /* even reflection at the domain edge */
 __device__ __forceinline__ int clampc(int c, int N) { return c < 0 ? 0 : (c >= N ? N - 1 : c); }
 
-/* Prediction of the child with per-axis bits cb of the level-jc node with
- * coordinates pc, from level-jc values uc, one direction at a time. */
+/* bit b of v moved to bit d b (b < bits) */
+__device__ __forceinline__ int64_t spread_bits(int v, int d, int bits) {
+    int64_t out = 0;
+    for (int b = 0; b < bits; ++b) out |= (int64_t)((v >> b) & 1) << (d * b);
+    return out;
+}
+
+/* Level-jc indices of the 3^D stencil around the node with coordinates pc,
+ * each coordinate clamped to the domain (even reflection), x fastest then y
+ * then z: the Morton index of a node is the OR of its coordinates' spread
+ * bits (x most significant within each group of D bits), so the 3^D indices
+ * take 3 D spreads instead of 3^D full encodings.  A level holds at most
+ * 2^(d (J - 1)) <= 2^28 nodes below the finest (d J <= 30), so 32 bits hold
+ * the indices. */
 template <int D>
-__device__ __forceinline__ double predict(const double* uc, int jc, const int* pc, const int* cb) {
+__device__ __forceinline__ void stencil_index(int jc, const int* pc, uint32_t* idx) {
     const int N = 1 << jc;
+    int64_t sp[3][3];
+    for (int a = 0; a < D; ++a)
+        for (int o = 0; o < 3; ++o) sp[a][o] = spread_bits(clampc(pc[a] + o - 1, N), D, jc) << (D - 1 - a);
+    if (D == 2) {
+        for (int oy = 0; oy < 3; ++oy)
+            for (int ox = 0; ox < 3; ++ox) idx[oy * 3 + ox] = (uint32_t)(sp[0][ox] | sp[1][oy]);
+    } else {
+        for (int oz = 0; oz < 3; ++oz)
+            for (int oy = 0; oy < 3; ++oy)
+                for (int ox = 0; ox < 3; ++ox)
+                    idx[(oz * 3 + oy) * 3 + ox] = (uint32_t)(sp[0][ox] | sp[1][oy] | sp[2][oz]);
+    }
+}
+
+/* Prediction of the child with per-axis bits cb from the parent's 3^D
+ * stencil values v (ordered as stencil_index), one direction at a time: in
+ * x along each row, then in y over the three rows, then in z over the three
+ * planes; each step is centre + sign/8 (minus-side value - plus-side value). */
+template <int D>
+__device__ __forceinline__ double predict(const double* v, const int* cb) {
     double sg[3];
     for (int a = 0; a < D; ++a) sg[a] = cb[a] == 0 ? 0.125 : -0.125;
     if (D == 2) {
         double rows[3];
-        for (int oy = -1; oy <= 1; ++oy) {
-            int c0[2] = {clampc(pc[0] - 1, N), clampc(pc[1] + oy, N)};
-            int c1[2] = {clampc(pc[0], N), clampc(pc[1] + oy, N)};
-            int c2[2] = {clampc(pc[0] + 1, N), clampc(pc[1] + oy, N)};
-            const double vm = uc[morton_encode(c0, 2, jc)];
-            const double v0 = uc[morton_encode(c1, 2, jc)];
-            const double vp = uc[morton_encode(c2, 2, jc)];
+        for (int oy = 0; oy < 3; ++oy) {
+            const double vm = v[oy * 3], v0 = v[oy * 3 + 1], vp = v[oy * 3 + 2];
             const double dif = vm - vp;
             const double t = sg[0] * dif;
-            rows[oy + 1] = v0 + t;
+            rows[oy] = v0 + t;
         }
         const double dif = rows[0] - rows[2];
         const double t = sg[1] * dif;
         return rows[1] + t;
     } else {
         double planes[3];
-        for (int oz = -1; oz <= 1; ++oz) {
+        for (int oz = 0; oz < 3; ++oz) {
             double rows[3];
-            for (int oy = -1; oy <= 1; ++oy) {
-                int c0[3] = {clampc(pc[0] - 1, N), clampc(pc[1] + oy, N), clampc(pc[2] + oz, N)};
-                int c1[3] = {clampc(pc[0], N), clampc(pc[1] + oy, N), clampc(pc[2] + oz, N)};
-                int c2[3] = {clampc(pc[0] + 1, N), clampc(pc[1] + oy, N), clampc(pc[2] + oz, N)};
-                const double vm = uc[morton_encode(c0, 3, jc)];
-                const double v0 = uc[morton_encode(c1, 3, jc)];
-                const double vp = uc[morton_encode(c2, 3, jc)];
-                const double dif = vm - vp;
+            for (int oy = 0; oy < 3; ++oy) {
+                const double* r = v + (oz * 3 + oy) * 3;
+                const double dif = r[0] - r[2];
                 const double t = sg[0] * dif;
-                rows[oy + 1] = v0 + t;
+                rows[oy] = r[1] + t;
             }
             const double dif = rows[0] - rows[2];
             const double t = sg[1] * dif;
-            planes[oz + 1] = rows[1] + t;
+            planes[oz] = rows[1] + t;
         }
         const double dif = planes[0] - planes[2];
         const double t = sg[2] * dif;
@@ -163,7 +185,9 @@ __global__ void k_project(Pyr P, int j) {
 }
 
 /* details of the children of level-(j-1) node p and its refine flag; with
- * refine, a significant child below the finest level gets children too */
+ * refine, a significant child below the finest level gets children too.  The
+ * stencil is gathered once per species and serves all 2^D children; each
+ * child's sum over the species runs in species order. */
 template <int D>
 __global__ void k_detail_flags(Pyr P, int j, double eps_j2, const double* __restrict__ scale,
                                int refine) {
@@ -171,22 +195,30 @@ __global__ void k_detail_flags(Pyr P, int j, double eps_j2, const double* __rest
     const int64_t np = (int64_t)1 << (D * jc);
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
-    constexpr int NC = 1 << D;
+    constexpr int NC = 1 << D, NS = D == 2 ? 9 : 27;
     int pc[3];
     morton_decode(p, D, jc, pc);
+    uint32_t idx[NS];
+    stencil_index<D>(jc, pc, idx);
+    double acc[NC];
+    for (int i = 0; i < P.m; ++i) {
+        const double* uc = lvl(P, i, jc);
+        double v[NS];
+        for (int q = 0; q < NS; ++q) v[q] = uc[idx[q]];
+        const double* uf = lvl(P, i, j) + p * NC;
+        for (int c = 0; c < NC; ++c) {
+            int cb[3];
+            for (int a = 0; a < D; ++a) cb[a] = (c >> (D - 1 - a)) & 1;
+            const double pred = predict<D>(v, cb);
+            const double dd = uf[c] - pred;
+            const double q = dd / scale[i];
+            acc[c] = (i == 0) ? q * q : acc[c] + q * q;
+        }
+    }
     bool sig = false;
     const double invm = 1.0 / P.m;
     for (int c = 0; c < NC; ++c) {
-        int cb[3];
-        for (int a = 0; a < D; ++a) cb[a] = (c >> (D - 1 - a)) & 1;
-        double acc = 0.0;
-        for (int i = 0; i < P.m; ++i) {
-            const double pred = predict<D>(lvl(P, i, jc), jc, pc, cb);
-            const double dd = lvl(P, i, j)[p * NC + c] - pred;
-            const double q = dd / scale[i];
-            acc = (i == 0) ? q * q : acc + q * q;
-        }
-        const bool sc = acc * invm >= eps_j2;
+        const bool sc = acc[c] * invm >= eps_j2;
         sig = sig || sc;
         if (refine && sc && j < P.J) P.R[P.off[j] + p * NC + c] = 1;
     }
@@ -336,16 +368,36 @@ __global__ void k_tree_up(Pyr P, int j) {
     }
 }
 
-/* nodes outside the tree are predicted from the (complete) coarser level */
+/* nodes outside the tree are predicted from the (complete) coarser level:
+ * one thread per level-(j-1) parent, its stencil gathered once per species
+ * for those of its 2^D children that are outside the tree */
 template <int D>
 __global__ void k_fill_down(Pyr P, int j) {
-    const int64_t nj = (int64_t)1 << (D * j);
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nj || P.T[P.off[j] + k]) return;
-    int pc[3], cb[3];
-    morton_decode(k >> D, D, j - 1, pc);
-    for (int a = 0; a < D; ++a) cb[a] = (int)((k >> (D - 1 - a)) & 1);
-    for (int i = 0; i < P.m; ++i) lvl(P, i, j)[k] = predict<D>(lvl(P, i, j - 1), j - 1, pc, cb);
+    const int jc = j - 1;
+    const int64_t np = (int64_t)1 << (D * jc);
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    constexpr int NC = 1 << D, NS = D == 2 ? 9 : 27;
+    const unsigned char* t = P.T + P.off[j] + p * NC;
+    bool any = false;
+    for (int c = 0; c < NC; ++c) any = any || !t[c];
+    if (!any) return;
+    int pc[3];
+    morton_decode(p, D, jc, pc);
+    uint32_t idx[NS];
+    stencil_index<D>(jc, pc, idx);
+    for (int i = 0; i < P.m; ++i) {
+        const double* uc = lvl(P, i, jc);
+        double v[NS];
+        for (int q = 0; q < NS; ++q) v[q] = uc[idx[q]];
+        double* uf = lvl(P, i, j) + p * NC;
+        for (int c = 0; c < NC; ++c) {
+            if (t[c]) continue;
+            int cb[3];
+            for (int a = 0; a < D; ++a) cb[a] = (c >> (D - 1 - a)) & 1;
+            uf[c] = predict<D>(v, cb);
+        }
+    }
 }
 
 /* ---------------------------------------------------------------- host */
@@ -487,9 +539,9 @@ static int tree_levels(Pyr& P, const uint64_t* keys, const double* values, int64
         else hipLaunchKernelGGL(k_tree_up<3>, dim3(blocks_for(np, B)), dim3(B), 0, s, P, j);
     }
     for (int j = 1; j <= J; ++j) {
-        const int64_t nj = (int64_t)1 << (d * j);
-        if (d == 2) hipLaunchKernelGGL(k_fill_down<2>, dim3(blocks_for(nj, B)), dim3(B), 0, s, P, j);
-        else hipLaunchKernelGGL(k_fill_down<3>, dim3(blocks_for(nj, B)), dim3(B), 0, s, P, j);
+        const int64_t np = (int64_t)1 << (d * (j - 1));
+        if (d == 2) hipLaunchKernelGGL(k_fill_down<2>, dim3(blocks_for(np, B)), dim3(B), 0, s, P, j);
+        else hipLaunchKernelGGL(k_fill_down<3>, dim3(blocks_for(np, B)), dim3(B), 0, s, P, j);
     }
     MRA_TRY(hipGetLastError());
     return 0;
