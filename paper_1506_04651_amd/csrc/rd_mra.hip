@@ -266,11 +266,20 @@ __device__ __forceinline__ int leaf_of(const Pyr& P, int64_t f, int d, bool& fir
 
 constexpr int kLeafBlock = 256;
 
-__global__ void k_leaf_count(Pyr P, int d, unsigned* __restrict__ block_count) {
+constexpr int kMaxLevels = 16; /* J <= 15: the level takes 4 bits of a key */
+
+/* leaves per block, and per block and level (level_block[l * gridDim.x + b]) */
+__global__ void k_leaf_count(Pyr P, int d, unsigned* __restrict__ block_count,
+                             unsigned* __restrict__ level_block) {
     const int64_t n = P.off[P.J + 1] - P.off[P.J];
     const int64_t f = (int64_t)blockIdx.x * kLeafBlock + threadIdx.x;
+    __shared__ unsigned lc[kMaxLevels];
+    if (threadIdx.x < kMaxLevels) lc[threadIdx.x] = 0u;
+    __syncthreads();
     bool first = false;
-    if (f < n) (void)leaf_of(P, f, d, first);
+    int j = -1;
+    if (f < n) j = leaf_of(P, f, d, first);
+    if (first) atomicAdd(&lc[j], 1u);
     const unsigned cnt = (unsigned)__popcll(__ballot(first));
     __shared__ unsigned wsum[kLeafBlock / 64];
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = cnt;
@@ -280,6 +289,23 @@ __global__ void k_leaf_count(Pyr P, int d, unsigned* __restrict__ block_count) {
         for (int w = 0; w < kLeafBlock / 64; ++w) s += wsum[w];
         block_count[blockIdx.x] = s;
     }
+    if (threadIdx.x < kMaxLevels) level_block[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = lc[threadIdx.x];
+}
+
+/* leaves per level: block l sums level l over the nb blocks of k_leaf_count */
+__global__ void k_level_sum(const unsigned* __restrict__ level_block, int64_t nb,
+                            unsigned long long* __restrict__ level_tot) {
+    const unsigned* in = level_block + (int64_t)blockIdx.x * nb;
+    unsigned long long s = 0;
+    for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) s += in[b];
+    __shared__ unsigned long long part[256];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) level_tot[blockIdx.x] = part[0];
 }
 
 /* exclusive scan of nb block counts in one block of 1024 threads; the total
@@ -457,8 +483,10 @@ static int setup_pyr(const rd_mra_params* p, int32_t m, hipStream_t s, Pyr& P, d
     const size_t bU = al(sizeof(double) * (size_t)m * P.total);
     const size_t bR = al((size_t)P.total);
     const size_t bS = al(sizeof(double) * m);
-    const size_t bC = al(sizeof(unsigned) * (size_t)*nblocks);
-    const size_t bO = al(sizeof(unsigned long long) * ((size_t)*nblocks + 1));
+    /* block counts, then per level and block (k_leaf_count) */
+    const size_t bC = al(sizeof(unsigned) * (size_t)*nblocks * (1 + kMaxLevels));
+    /* block offsets and the total, then the leaves per level */
+    const size_t bO = al(sizeof(unsigned long long) * ((size_t)*nblocks + 1 + kMaxLevels));
     int err = 0;
     char* w = (char*)mra_workspace(s, bU + 2 * bR + bS + bC + bO, &err);
     if (!w) return err ? err : RD_ENOMEM;
@@ -500,7 +528,7 @@ static int64_t flags_and_leaves(Pyr& P, const rd_mra_params* p, hipStream_t s, c
         if (d == 2) hipLaunchKernelGGL(k_grade<2>, dim3(blocks_for(nj, B)), dim3(B), 0, s, P, j);
         else hipLaunchKernelGGL(k_grade<3>, dim3(blocks_for(nj, B)), dim3(B), 0, s, P, j);
     }
-    hipLaunchKernelGGL(k_leaf_count, dim3((unsigned)nb), dim3(kLeafBlock), 0, s, P, d, bcount);
+    hipLaunchKernelGGL(k_leaf_count, dim3((unsigned)nb), dim3(kLeafBlock), 0, s, P, d, bcount, bcount + nb);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, (const unsigned*)bcount, boff, nb);
     MRA_TRY(hipGetLastError());
     unsigned long long total = 0;
@@ -513,11 +541,14 @@ static int64_t flags_and_leaves(Pyr& P, const rd_mra_params* p, hipStream_t s, c
                            (const unsigned long long*)boff, keys, values, nl);
         MRA_TRY(hipGetLastError());
         if (level_counts) {
-            std::vector<uint64_t> hk((size_t)nl);
-            MRA_TRY(hipMemcpyAsync(hk.data(), keys, sizeof(uint64_t) * nl, hipMemcpyDeviceToHost, s));
+            unsigned long long* ltot = boff + nb + 1;
+            hipLaunchKernelGGL(k_level_sum, dim3((unsigned)(J + 1)), dim3(256), 0, s,
+                               (const unsigned*)(bcount + nb), nb, ltot);
+            MRA_TRY(hipGetLastError());
+            unsigned long long hl[kMaxLevels];
+            MRA_TRY(hipMemcpyAsync(hl, ltot, sizeof(unsigned long long) * (J + 1), hipMemcpyDeviceToHost, s));
             MRA_TRY(hipStreamSynchronize(s));
-            for (int j = 0; j <= J; ++j) level_counts[j] = 0;
-            for (uint64_t k : hk) level_counts[(k >> 12) & 15u]++;
+            for (int j = 0; j <= J; ++j) level_counts[j] = (int64_t)hl[j];
         }
         MRA_TRY(hipStreamSynchronize(s));
     }
