@@ -320,17 +320,15 @@ __global__ void k_scan_blocks(const unsigned* __restrict__ in, unsigned long lon
     for (int64_t b = b0; b < b1; ++b) s += in[b];
     part[t] = s;
     __syncthreads();
-    if (t == 0) {
-        unsigned long long run = 0;
-        for (int i = 0; i < 1024; ++i) {
-            const unsigned long long v = part[i];
-            part[i] = run;
-            run += v;
-        }
-        out[nb] = run;
+    /* inclusive scan of the 1024 partial sums in LDS (log2 1024 steps) */
+    for (int h = 1; h < 1024; h <<= 1) {
+        const unsigned long long v = t >= h ? part[t - h] : 0ull;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
     }
-    __syncthreads();
-    unsigned long long run = part[t];
+    if (t == 1023) out[nb] = part[1023];
+    unsigned long long run = part[t] - s;
     for (int64_t b = b0; b < b1; ++b) {
         out[b] = run;
         run += in[b];
