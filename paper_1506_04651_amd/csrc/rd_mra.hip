@@ -169,6 +169,59 @@ __global__ void k_from_morton(double* __restrict__ fine, Pyr P) {
     for (int i = 0; i < P.m; ++i) fine[(int64_t)i * n + r] = lvl(P, i, P.J)[k];
 }
 
+/* Finest level <-> row-major field through LDS bricks: an aligned brick of
+ * side 2^S (2^(D S) = 4096 cells) is one contiguous range of Morton indices,
+ * brick b holding [b 4096, (b + 1) 4096) with b the Morton index of the
+ * brick's coordinates.  The row-major side moves as row segments of 2^S
+ * doubles, the Morton side as contiguous runs; a plain copy either way. */
+constexpr int kBrickCells = 4096;
+template <int D> struct Brick { static constexpr int S = D == 2 ? 6 : 4; };
+
+template <int D, bool TO_MORTON>
+__global__ void __launch_bounds__(256) k_morton_brick(const double* __restrict__ fine_in,
+                                                      double* __restrict__ fine_out, Pyr P) {
+    constexpr int S = Brick<D>::S;
+    __shared__ double tile[kBrickCells];
+    const int64_t b = blockIdx.x;
+    const int64_t n = P.off[P.J + 1] - P.off[P.J];
+    const int N = 1 << P.J;
+    int bc[3];
+    morton_decode(b, D, P.J - S, bc);
+    for (int i = 0; i < P.m; ++i) {
+        const double* fi = TO_MORTON ? fine_in + (int64_t)i * n : nullptr;
+        double* fo = TO_MORTON ? nullptr : fine_out + (int64_t)i * n;
+        double* u = lvl(P, i, P.J) + b * kBrickCells;
+        if (TO_MORTON) {
+            for (int q = threadIdx.x; q < kBrickCells; q += 256) {
+                const int lx = q & ((1 << S) - 1), ly = (q >> S) & ((1 << S) - 1), lz = q >> (2 * S);
+                const int64_t gx = ((int64_t)bc[0] << S) + lx, gy = ((int64_t)bc[1] << S) + ly;
+                const int64_t gz = D == 3 ? ((int64_t)bc[2] << S) + lz : 0;
+                tile[q] = fi[gx + N * (gy + N * gz)];
+            }
+            __syncthreads();
+            for (int k = threadIdx.x; k < kBrickCells; k += 256) {
+                int l[3];
+                morton_decode(k, D, S, l);
+                u[k] = tile[l[0] + (l[1] << S) + (D == 3 ? (l[2] << (2 * S)) : 0)];
+            }
+        } else {
+            for (int k = threadIdx.x; k < kBrickCells; k += 256) {
+                int l[3];
+                morton_decode(k, D, S, l);
+                tile[l[0] + (l[1] << S) + (D == 3 ? (l[2] << (2 * S)) : 0)] = u[k];
+            }
+            __syncthreads();
+            for (int q = threadIdx.x; q < kBrickCells; q += 256) {
+                const int lx = q & ((1 << S) - 1), ly = (q >> S) & ((1 << S) - 1), lz = q >> (2 * S);
+                const int64_t gx = ((int64_t)bc[0] << S) + lx, gy = ((int64_t)bc[1] << S) + ly;
+                const int64_t gz = D == 3 ? ((int64_t)bc[2] << S) + lz : 0;
+                fo[gx + N * (gy + N * gz)] = tile[q];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 /* level j -> j-1: node = average of its 2^D children (summed in child order) */
 template <int D>
 __global__ void k_project(Pyr P, int j) {
@@ -608,7 +661,12 @@ int64_t rd_mra_leaves(const double* fine, int32_t m, const rd_mra_params* p, uin
     const int d = P.d, J = P.J;
     const int64_t nfine = (int64_t)1 << (d * J);
     const int B = 256;
-    if (d == 2) hipLaunchKernelGGL(k_to_morton<2>, dim3(blocks_for(nfine, B)), dim3(B), 0, s, fine, P);
+    const int64_t nbrick = nfine / kBrickCells;
+    if (d == 2 && J >= Brick<2>::S)
+        hipLaunchKernelGGL((k_morton_brick<2, true>), dim3((unsigned)nbrick), dim3(256), 0, s, fine, nullptr, P);
+    else if (d == 3 && J >= Brick<3>::S)
+        hipLaunchKernelGGL((k_morton_brick<3, true>), dim3((unsigned)nbrick), dim3(256), 0, s, fine, nullptr, P);
+    else if (d == 2) hipLaunchKernelGGL(k_to_morton<2>, dim3(blocks_for(nfine, B)), dim3(B), 0, s, fine, P);
     else hipLaunchKernelGGL(k_to_morton<3>, dim3(blocks_for(nfine, B)), dim3(B), 0, s, fine, P);
     for (int j = J; j >= 1; --j) {
         const int64_t np = (int64_t)1 << (d * (j - 1));
@@ -635,7 +693,12 @@ int64_t rd_mra_reconstruct(const uint64_t* keys, const double* values, int64_t n
     const int d = P.d, J = P.J;
     const int64_t nfine = (int64_t)1 << (d * J);
     const int B = 256;
-    if (d == 2) hipLaunchKernelGGL(k_from_morton<2>, dim3(blocks_for(nfine, B)), dim3(B), 0, s, fine, P);
+    const int64_t nbrick = nfine / kBrickCells;
+    if (d == 2 && J >= Brick<2>::S)
+        hipLaunchKernelGGL((k_morton_brick<2, false>), dim3((unsigned)nbrick), dim3(256), 0, s, nullptr, fine, P);
+    else if (d == 3 && J >= Brick<3>::S)
+        hipLaunchKernelGGL((k_morton_brick<3, false>), dim3((unsigned)nbrick), dim3(256), 0, s, nullptr, fine, P);
+    else if (d == 2) hipLaunchKernelGGL(k_from_morton<2>, dim3(blocks_for(nfine, B)), dim3(B), 0, s, fine, P);
     else hipLaunchKernelGGL(k_from_morton<3>, dim3(blocks_for(nfine, B)), dim3(B), 0, s, fine, P);
     MRA_TRY(hipGetLastError());
     MRA_TRY(hipStreamSynchronize(s));
