@@ -345,6 +345,45 @@ __global__ void k_leaf_count(Pyr P, int d, unsigned* __restrict__ block_count,
     if (threadIdx.x < kMaxLevels) level_block[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = lc[threadIdx.x];
 }
 
+/* Exclusive scan of the nb block counts in three passes: chunk sums (one
+ * block per 1024 counts), a one-block scan of the chunk sums, and the scan
+ * within each chunk plus its offset.  A chunk sum is at most 1024 x 256. */
+constexpr int kScanChunk = 1024;
+
+__global__ void __launch_bounds__(kScanChunk) k_chunk_sums(const unsigned* __restrict__ in, int64_t nb,
+                                                           unsigned* __restrict__ chunk_sum) {
+    const int64_t b = (int64_t)blockIdx.x * kScanChunk + threadIdx.x;
+    const unsigned v = b < nb ? in[b] : 0u;
+    __shared__ unsigned part[kScanChunk];
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = kScanChunk / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) chunk_sum[blockIdx.x] = part[0];
+}
+
+__global__ void __launch_bounds__(kScanChunk) k_chunk_apply(const unsigned* __restrict__ in, int64_t nb,
+                                                            const unsigned long long* __restrict__ chunk_off,
+                                                            int64_t nchunks,
+                                                            unsigned long long* __restrict__ out) {
+    const int t = threadIdx.x;
+    const int64_t b = (int64_t)blockIdx.x * kScanChunk + t;
+    const unsigned v = b < nb ? in[b] : 0u;
+    __shared__ unsigned long long part[kScanChunk];
+    part[t] = v;
+    __syncthreads();
+    for (int h = 1; h < kScanChunk; h <<= 1) {
+        const unsigned long long x = t >= h ? part[t - h] : 0ull;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    if (b < nb) out[b] = chunk_off[blockIdx.x] + part[t] - v;
+    if (blockIdx.x == 0 && t == 0) out[nb] = chunk_off[nchunks];
+}
+
 /* leaves per level: block l sums level l over the nb blocks of k_leaf_count */
 __global__ void k_level_sum(const unsigned* __restrict__ level_block, int64_t nb,
                             unsigned long long* __restrict__ level_tot) {
@@ -534,10 +573,11 @@ static int setup_pyr(const rd_mra_params* p, int32_t m, hipStream_t s, Pyr& P, d
     const size_t bU = al(sizeof(double) * (size_t)m * P.total);
     const size_t bR = al((size_t)P.total);
     const size_t bS = al(sizeof(double) * m);
-    /* block counts, then per level and block (k_leaf_count) */
-    const size_t bC = al(sizeof(unsigned) * (size_t)*nblocks * (1 + kMaxLevels));
-    /* block offsets and the total, then the leaves per level */
-    const size_t bO = al(sizeof(unsigned long long) * ((size_t)*nblocks + 1 + kMaxLevels));
+    const size_t nch = ((size_t)*nblocks + kScanChunk - 1) / kScanChunk;
+    /* block counts, then per level and block (k_leaf_count), then the chunk sums of the scan */
+    const size_t bC = al(sizeof(unsigned) * ((size_t)*nblocks * (1 + kMaxLevels) + nch));
+    /* block offsets and the total, the leaves per level, then the chunk offsets and their total */
+    const size_t bO = al(sizeof(unsigned long long) * ((size_t)*nblocks + 1 + kMaxLevels + nch + 1));
     int err = 0;
     char* w = (char*)mra_workspace(s, bU + 2 * bR + bS + bC + bO, &err);
     if (!w) return err ? err : RD_ENOMEM;
@@ -580,7 +620,16 @@ static int64_t flags_and_leaves(Pyr& P, const rd_mra_params* p, hipStream_t s, c
         else hipLaunchKernelGGL(k_grade<3>, dim3(blocks_for(nj, B)), dim3(B), 0, s, P, j);
     }
     hipLaunchKernelGGL(k_leaf_count, dim3((unsigned)nb), dim3(kLeafBlock), 0, s, P, d, bcount, bcount + nb);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, (const unsigned*)bcount, boff, nb);
+    {
+        const int64_t nch = (nb + kScanChunk - 1) / kScanChunk;
+        unsigned* csum = bcount + nb * (1 + kMaxLevels);
+        unsigned long long* coff = boff + nb + 1 + kMaxLevels;
+        hipLaunchKernelGGL(k_chunk_sums, dim3((unsigned)nch), dim3(kScanChunk), 0, s,
+                           (const unsigned*)bcount, nb, csum);
+        hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, (const unsigned*)csum, coff, nch);
+        hipLaunchKernelGGL(k_chunk_apply, dim3((unsigned)nch), dim3(kScanChunk), 0, s,
+                           (const unsigned*)bcount, nb, (const unsigned long long*)coff, nch, boff);
+    }
     MRA_TRY(hipGetLastError());
     unsigned long long total = 0;
     MRA_TRY(hipMemcpyAsync(&total, boff + nb, sizeof(total), hipMemcpyDeviceToHost, s));
