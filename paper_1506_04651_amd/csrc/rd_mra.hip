@@ -384,16 +384,17 @@ __global__ void __launch_bounds__(kScanChunk) k_chunk_apply(const unsigned* __re
     if (blockIdx.x == 0 && t == 0) out[nb] = chunk_off[nchunks];
 }
 
-/* leaves per level: block l sums level l over the nb blocks of k_leaf_count */
-__global__ void k_level_sum(const unsigned* __restrict__ level_block, int64_t nb,
-                            unsigned long long* __restrict__ level_tot) {
+/* leaves per level: block l (1024 threads) sums level l over the nb blocks of
+ * k_leaf_count */
+__global__ void __launch_bounds__(1024) k_level_sum(const unsigned* __restrict__ level_block, int64_t nb,
+                                                    unsigned long long* __restrict__ level_tot) {
     const unsigned* in = level_block + (int64_t)blockIdx.x * nb;
     unsigned long long s = 0;
     for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) s += in[b];
-    __shared__ unsigned long long part[256];
+    __shared__ unsigned long long part[1024];
     part[threadIdx.x] = s;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
+    for (int h = 512; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
         __syncthreads();
     }
@@ -642,7 +643,7 @@ static int64_t flags_and_leaves(Pyr& P, const rd_mra_params* p, hipStream_t s, c
         MRA_TRY(hipGetLastError());
         if (level_counts) {
             unsigned long long* ltot = boff + nb + 1;
-            hipLaunchKernelGGL(k_level_sum, dim3((unsigned)(J + 1)), dim3(256), 0, s,
+            hipLaunchKernelGGL(k_level_sum, dim3((unsigned)(J + 1)), dim3(1024), 0, s,
                                (const unsigned*)(bcount + nb), nb, ltot);
             MRA_TRY(hipGetLastError());
             unsigned long long hl[kMaxLevels];
