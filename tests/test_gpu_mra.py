@@ -35,7 +35,9 @@ def front_field_rowmajor(d, J, m=2, width=0.02, seed=0):
 
 
 @pytest.mark.parametrize("d,J,eps,m", [(2, 8, 1e-3, 2), (2, 8, 3e-2, 2), (2, 6, 0.0, 3),
-                                       (3, 5, 1e-3, 2), (2, 7, 1e-3, 1)])
+                                       (3, 5, 1e-3, 2), (2, 7, 1e-3, 1),
+                                       # below one 4096-cell brick: the per-cell Morton copies
+                                       (2, 5, 1e-3, 2), (3, 3, 0.0, 2)])
 def test_leaf_set_parity(rd, d, J, eps, m):
     f = front_field_rowmajor(d, J, m=m, seed=J)
     scale = np.linspace(1.0, 2.0, m)
